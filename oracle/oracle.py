@@ -1,0 +1,275 @@
+"""ctypes wrapper of the FP64 CPU oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the CPU
+baseline of the benchmark, never by the product path.  The oracle and the HIP
+path share no code; the only common module is the seeded input generator
+``orchard_inputs``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = [os.path.join(HERE, f) for f in ("oracle.cpp", "oracle_math.hpp", "tape.hpp", "adjoint.cpp")]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (host code only)."""
+    srcs = [os.path.join(HERE, "oracle.cpp")]
+    if os.path.exists(os.path.join(HERE, "adjoint.cpp")):
+        srcs.append(os.path.join(HERE, "adjoint.cpp"))
+    if force or not os.path.exists(LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", LIB + ".tmp", *srcs, "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class Globals(C.Structure):
+    _fields_ = [("dt", C.c_double), ("gravity", C.c_double * 3), ("tether_k", C.c_double),
+                ("tether_zeta", C.c_double), ("damping_zeta", C.c_double), ("damping_cd", C.c_double),
+                ("tension_factor", C.c_double), ("v_cap", C.c_double), ("react_max_factor", C.c_double),
+                ("event_band", C.c_double), ("n_break", C.c_int32), ("n_pull", C.c_int32),
+                ("n_tension", C.c_int32), ("pad", C.c_int32), ("rng_seed", C.c_uint64),
+                ("wrench_fraction", C.c_double), ("wrench_sigma", C.c_double)]
+
+
+_P = C.c_void_p
+
+
+class Desc(C.Structure):
+    _fields_ = [("n_env", C.c_int32)] + [(n, _P) for n in (
+        "seg_offset", "seg_parent", "seg_rest_quat", "seg_length", "seg_radius", "seg_density",
+        "seg_youngs", "seg_mor", "apple_offset", "apple_seg", "apple_hang", "apple_mass",
+        "apple_radius", "apple_detach")]
+
+
+class IO(C.Structure):
+    _fields_ = [(n, _P) for n in ("q", "qd", "ax", "av", "aq", "aw", "broken", "cnt", "det", "cntp",
+                                  "cntt", "det_path", "break_step", "det_step", "status", "kp", "kd",
+                                  "wrench")] + [("wrench_stride", C.c_int64), ("aforce", _P),
+                                                ("aforce_stride", C.c_int64)] + \
+        [(n, _P) for n in ("band_jmin", "band_amin", "band_jfirst", "band_afirst")]
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or any(os.path.exists(s) and os.path.getmtime(s) > os.path.getmtime(LIB) for s in SRC):
+            build()
+        L = C.CDLL(LIB)
+        L.oracle_create.restype = C.c_void_p
+        L.oracle_create.argtypes = [C.POINTER(Desc), C.POINTER(Globals)]
+        L.oracle_destroy.argtypes = [C.c_void_p]
+        L.oracle_derived.argtypes = [C.c_void_p] + [_P] * 7
+        L.oracle_fk.argtypes = [C.c_void_p, C.c_int, _P, _P, _P]
+        L.oracle_mass_matrix.argtypes = [C.c_void_p, C.c_int, _P, _P]
+        L.oracle_inverse_dynamics.argtypes = [C.c_void_p, C.c_int, _P, _P, _P, _P, C.c_int, _P]
+        L.oracle_ltdl_solve.argtypes = [C.c_void_p, C.c_int, _P, _P, _P, _P]
+        L.oracle_rest_state.argtypes = [C.c_void_p, C.POINTER(IO)]
+        L.oracle_rollout.argtypes = [C.c_void_p, C.POINTER(IO), C.c_int, _P, C.c_int64, C.c_int, C.c_int]
+        L.oracle_rng_u24.restype = C.c_uint32
+        L.oracle_rng_u24.argtypes = [C.c_uint64] * 5
+        L.oracle_splitmix64.restype = C.c_uint64
+        L.oracle_splitmix64.argtypes = [C.c_uint64]
+        _lib = L
+    return _lib
+
+
+@dataclass
+class State:
+    """Batch state in descriptor order (float64)."""
+    q: np.ndarray
+    qd: np.ndarray
+    ax: np.ndarray
+    av: np.ndarray
+    aq: np.ndarray
+    aw: np.ndarray
+    broken: np.ndarray
+    cnt: np.ndarray
+    det: np.ndarray
+    cntp: np.ndarray
+    cntt: np.ndarray
+    det_path: np.ndarray
+    break_step: np.ndarray
+    det_step: np.ndarray
+    status: np.ndarray
+    step: int = 0
+
+    def copy(self) -> "State":
+        return State(*[getattr(self, f).copy() for f in self.__dataclass_fields__ if f != "step"], step=self.step)
+
+
+class Band:
+    """Band-rule log: min |ratio - 1| and first in-band step per joint / apple."""
+
+    def __init__(self, n_seg: int, n_apple: int):
+        self.jmin = np.full(n_seg, np.inf)
+        self.amin = np.full(n_apple, np.inf)
+        self.jfirst = np.full(n_seg, -1, np.int32)
+        self.afirst = np.full(n_apple, -1, np.int32)
+
+
+def make_globals(consts: dict) -> Globals:
+    g = Globals()
+    g.dt = consts["dt"]
+    for i in range(3):
+        g.gravity[i] = consts["gravity"][i]
+    for k in ("tether_k", "tether_zeta", "damping_zeta", "damping_cd", "tension_factor", "v_cap",
+              "react_max_factor", "event_band", "wrench_fraction", "wrench_sigma"):
+        setattr(g, k, float(consts[k]))
+    for k in ("n_break", "n_pull", "n_tension"):
+        setattr(g, k, int(consts[k]))
+    g.rng_seed = int(consts["rng_seed"])
+    return g
+
+
+class Oracle:
+    def __init__(self, batch, consts: dict):
+        self.batch = batch
+        self.consts = dict(consts)
+        self._keep = {}
+        d = Desc()
+        d.n_env = batch.n_env
+        for name in ("seg_offset", "seg_parent", "apple_offset", "apple_seg"):
+            a = np.ascontiguousarray(getattr(batch, name), dtype=np.int32)
+            self._keep[name] = a
+            setattr(d, name, _ptr(a))
+        for name in ("seg_rest_quat", "seg_length", "seg_radius", "seg_density", "seg_youngs", "seg_mor",
+                     "apple_hang", "apple_mass", "apple_radius", "apple_detach"):
+            a = np.ascontiguousarray(getattr(batch, name), dtype=np.float64)
+            self._keep[name] = a
+            setattr(d, name, _ptr(a))
+        self.g = make_globals(consts)
+        h = lib().oracle_create(C.byref(d), C.byref(self.g))
+        if not h:
+            raise ValueError("oracle_create rejected the tree description")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.oracle_destroy(self.h)
+            self.h = None
+
+    # ---- derived parameters -------------------------------------------------------------
+    def derived(self) -> dict:
+        S, A = self.batch.n_seg, self.batch.n_apple
+        out = {k: np.zeros(S) for k in ("mass", "It", "Ia", "kp", "kd", "mmax")}
+        out["apple_cs"] = np.zeros(A)
+        lib().oracle_derived(self.h, *[_ptr(out[k]) for k in ("mass", "It", "Ia", "kp", "kd", "mmax", "apple_cs")])
+        return out
+
+    def _S(self, env):
+        return int(self.batch.seg_offset[env + 1] - self.batch.seg_offset[env])
+
+    # ---- single-tree kernels (tests) ------------------------------------------------------
+    def fk(self, env: int, q):
+        S = self._S(env)
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(2 * S)
+        R = np.zeros((S, 3, 3))
+        p = np.zeros((S, 3))
+        lib().oracle_fk(self.h, env, _ptr(q), _ptr(R), _ptr(p))
+        return R, p
+
+    def mass_matrix(self, env: int, q):
+        S = self._S(env)
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(2 * S)
+        H = np.zeros((2 * S, 2 * S))
+        lib().oracle_mass_matrix(self.h, env, _ptr(q), _ptr(H))
+        return H
+
+    def inverse_dynamics(self, env, q, qd, qdd, wrench=None, gravity=True):
+        S = self._S(env)
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+        q, qd, qdd = f(q), f(qd), f(qdd)
+        w = None if wrench is None else f(wrench)
+        tau = np.zeros(2 * S)
+        lib().oracle_inverse_dynamics(self.h, env, _ptr(q), _ptr(qd), _ptr(qdd), _ptr(w), int(gravity), _ptr(tau))
+        return tau
+
+    def ltdl_solve(self, env, q, diag, b):
+        S = self._S(env)
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64).reshape(2 * S)
+        q, diag, b = f(q), f(diag), f(b)
+        x = np.zeros(2 * S)
+        lib().oracle_ltdl_solve(self.h, env, _ptr(q), _ptr(diag), _ptr(b), _ptr(x))
+        return x
+
+    # ---- state and rollout ----------------------------------------------------------------
+    def empty_state(self) -> State:
+        S, A, B = self.batch.n_seg, self.batch.n_apple, self.batch.n_env
+        return State(q=np.zeros((S, 2)), qd=np.zeros((S, 2)), ax=np.zeros((A, 3)), av=np.zeros((A, 3)),
+                     aq=np.zeros((A, 4)), aw=np.zeros((A, 3)), broken=np.zeros(S, np.uint8),
+                     cnt=np.zeros(S, np.uint8), det=np.zeros(A, np.uint8), cntp=np.zeros(A, np.uint8),
+                     cntt=np.zeros(A, np.uint8), det_path=np.zeros(A, np.uint8),
+                     break_step=np.full(S, -1, np.int32), det_step=np.full(A, -1, np.int32),
+                     status=np.zeros(B, np.uint32))
+
+    def _io(self, st: State, kp=None, kd=None, wrench=None, wrench_stride=0, aforce=None, aforce_stride=0,
+            band: Band | None = None):
+        io = IO()
+        for f in ("q", "qd", "ax", "av", "aq", "aw", "broken", "cnt", "det", "cntp", "cntt", "det_path",
+                  "break_step", "det_step", "status"):
+            setattr(io, f, _ptr(getattr(st, f)))
+        io.kp = _ptr(kp)
+        io.kd = _ptr(kd)
+        io.wrench = _ptr(wrench)
+        io.wrench_stride = int(wrench_stride)
+        io.aforce = _ptr(aforce)
+        io.aforce_stride = int(aforce_stride)
+        if band is not None:
+            io.band_jmin, io.band_amin = _ptr(band.jmin), _ptr(band.amin)
+            io.band_jfirst, io.band_afirst = _ptr(band.jfirst), _ptr(band.afirst)
+        return io
+
+    def rest_state(self) -> State:
+        st = self.empty_state()
+        io = self._io(st)
+        lib().oracle_rest_state(self.h, C.byref(io))
+        return st
+
+    def rollout(self, st: State, n_steps: int, kp=None, kd=None, envs=None, wrench=None, wrench_stride=None,
+                aforce=None, aforce_stride=None, band: Band | None = None, threads: int | None = None) -> State:
+        """Advance ``st`` in place by n_steps (envs: subset of env indices).
+
+        wrench: [S_tot, 6] constant or [n_steps, S_tot, 6]; aforce: [A_tot, 3] constant or
+        [n_steps, A_tot, 3] (descriptor order, world frame)."""
+        d = self.derived() if (kp is None or kd is None) else None
+        kp = np.ascontiguousarray(d["kp"] if kp is None else kp, dtype=np.float64)
+        kd = np.ascontiguousarray(d["kd"] if kd is None else kd, dtype=np.float64)
+        if wrench is not None:
+            wrench = np.ascontiguousarray(wrench, dtype=np.float64)
+            if wrench_stride is None:
+                wrench_stride = 0 if wrench.ndim == 2 else wrench.shape[1] * 6
+        if aforce is not None:
+            aforce = np.ascontiguousarray(aforce, dtype=np.float64)
+            if aforce_stride is None:
+                aforce_stride = 0 if aforce.ndim == 2 else aforce.shape[1] * 3
+        io = self._io(st, kp, kd, wrench, wrench_stride or 0, aforce, aforce_stride or 0, band)
+        envs = np.arange(self.batch.n_env, dtype=np.int32) if envs is None else np.asarray(envs, np.int32)
+        if threads is None:
+            threads = min(len(envs), os.cpu_count() or 1, 16)
+        lib().oracle_rollout(self.h, C.byref(io), int(len(envs)), _ptr(envs), int(st.step), int(n_steps), int(threads))
+        st.step += n_steps
+        return st
+
+
+def rng_u24(seed, env, step, seg, k) -> int:
+    return int(lib().oracle_rng_u24(seed, env, step, seg, k))
+
+
+def splitmix64(x: int) -> int:
+    return int(lib().oracle_splitmix64(x))

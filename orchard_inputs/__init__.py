@@ -1,0 +1,5 @@
+"""Seeded synthetic inputs shared by the FP64 oracle and the HIP path.
+
+Holds no arithmetic of the dynamics step (see ``treegen``)."""
+from .treegen import TreeDesc, gen_tree, chain_tree, random_small_tree, ternary_lsystem_count, depth_stats
+from .presets import STEP_CONSTANTS, step_constants, WORKLOADS, Batch, assemble, make_batch, make_trees, n_trees, pull_forces, grad_apple_forces, grad_targets
