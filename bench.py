@@ -1,0 +1,150 @@
+"""Benchmark: batched forward-dynamics step of 8192 uneven apple trees on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one pass of the whole hot path (events, kinematics, forces, apples, bias,
+factorisation, solve, integration) over all 8192 trees.  The workload is the uneven
+batch: 8192 seeded trees with round(exp(U(ln 50, ln 1500))) segments and U{10..120}
+apples, random body forces (5 % of bodies per step, N(0, 5 N) per component) drawn
+inside the step.  Inputs live in HBM before the timed region starts.
+
+Prints ONE JSON line with the metric, the roofline of the step kernel (algorithmic
+bytes per launch over its measured average duration, HIP events on the launch
+stream) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# kernel mapping used by the benchmark (and by the full-size parity test)
+BENCH_TUNING = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0)
+# the plain per-step kernel: one 256-thread workgroup per tree, one launch per step
+PLAIN_TUNING = dict(threads=256, pack_fill=0.0, steps_per_launch=1, persistent=0)
+
+HBM_PEAK_GBS = 8000.0
+SEG_BYTES, APPLE_BYTES = 84, 146   # algorithmic bytes per segment-step / apple-step
+WORKLOAD = "uneven8192"
+
+
+def algorithmic_bytes(batch) -> int:
+    """Bytes a streaming step must move per batch step: FP32 SoA joint state read and
+    written, event bytes, static segment data; apple state, flags and static data."""
+    return SEG_BYTES * batch.n_seg + APPLE_BYTES * batch.n_apple
+
+
+def time_gpu(model, n_steps, warmup, reps=1):
+    import torch
+    st = model.rest_state()
+    kp, kd = model.default_params()
+    model.step(st, kp, kd, warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        model.step(st, kp, kd, n_steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1)
+        best = (ms, wall) if best is None or ms < best[0] else best
+    status = model.status(st)
+    return best[0], best[1], int((status != 0).sum()), st
+
+
+def cpu_baseline(batch, consts, n_envs=48, n_steps=40):
+    """FP64 oracle on a stratified sample of the same workload."""
+    from oracle.oracle import Oracle
+    from orchard_inputs import assemble
+    sizes = np.diff(batch.seg_offset)
+    order = np.argsort(sizes, kind="stable")
+    pick = sorted(int(order[i]) for i in np.unique(np.linspace(0, len(order) - 1, n_envs).round().astype(int)))
+    sub = assemble([batch.tree(e) for e in pick])
+    o = Oracle(sub, consts)
+    st = o.rest_state()
+    threads = min(16, os.cpu_count() or 1, len(pick))
+    t0 = time.perf_counter()
+    o.rollout(st, n_steps, threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=len(pick) * n_steps / dt, unit="env-steps/s", cores=threads, kind="oracle",
+                sample=f"{len(pick)} size-stratified trees of the workload ({int(sizes[pick].sum())} segments) x "
+                       f"{n_steps} steps, FP64, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (trees are independent, "
+              "a multi-GPU run would shard the envs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    from orchard_inputs import make_batch, step_constants
+    t_gen = time.perf_counter()
+    batch = make_batch(WORKLOAD)
+    consts = step_constants(WORKLOAD)
+    t_gen = time.perf_counter() - t_gen
+    print(f"# generated {batch.n_env} trees, {batch.n_seg} segments, {batch.n_apple} apples in {t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+
+    import torch
+    from paper_2607_06337_amd import Model
+    torch.cuda.init()
+    model = Model(batch, consts, BENCH_TUNING)
+    ms, wall, n_bad, _ = time_gpu(model, args.steps, args.warmup)
+    print(f"# optimized: {args.steps} steps in {ms:.1f} ms ({wall:.2f} s wall), packs={model.n_pack}", file=sys.stderr,
+          flush=True)
+    plain = None
+    if not args.no_plain:
+        pm = Model(batch, consts, PLAIN_TUNING)
+        pms, _, _, _ = time_gpu(pm, max(1, args.steps // 4), args.warmup)
+        plain = dict(value=batch.n_env * max(1, args.steps // 4) / (pms / 1e3), ms_per_step=pms / max(1, args.steps // 4),
+                     tuning=PLAIN_TUNING)
+        del pm
+        print(f"# plain per-step kernel: {plain['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    ms_step = ms / args.steps
+    value = batch.n_env * args.steps / (ms / 1e3)
+    spl = BENCH_TUNING["steps_per_launch"]
+    per_launch_bytes = algorithmic_bytes(batch) * spl
+    launch_ms = ms_step * spl
+    achieved = per_launch_bytes / (launch_ms / 1e3) / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel="k_step_packs", bytes_per_launch=per_launch_bytes)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(batch, consts)
+        print(f"# cpu baseline: {cpu['value']:.1f} env-steps/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
+    out = dict(metric="tree-env steps/sec (FP32, 8192 uneven trees) + adjoint/forward cost ratio",
+               value=round(value, 1), unit="env-steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=round(ms_step, 5), higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32", data="synthetic",
+               config=dict(workload=f"{WORKLOAD}: 8192 seeded L-system trees, log-uniform 50-1500 segments, "
+                                    f"10-120 apples, in-step random body forces 5% N(0,5N), dt 1 ms",
+                           n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=BENCH_TUNING),
+               adjoint_forward_ratio=None, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
+               roofline=roof, cpu_baseline=cpu)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/* orchard.h -- C ABI of liborchard.so: a batched forward-dynamics step of many
+ * independent, differently shaped articulated apple trees on one MI355X (gfx950).
+ *
+ * The physical model follows OrchardBench (arXiv 2607.06337):
+ *   - every internode is a rigid capsule link joined to its parent's tip by a
+ *     compliant two-DoF bending joint whose rest rotation is q_rel
+ *     (Sec. "Physical Model", joint-frame equation; Sec. "Compliant branch
+ *     dynamics": two bending DoF, twist and translation locked);
+ *   - joint stiffness Kp = (pi/4) E r^4 / l (Eq. beam), torque -Kp theta - Kd omega,
+ *     integrated implicitly;
+ *   - rupture when Kp |theta| > sigma_r pi r^3 / 4 (Eq. break) for N consecutive
+ *     steps; the broken joint loses spring and damper in place and becomes a free
+ *     hinge (Sec. "Branch breaking");
+ *   - apples are free bodies on a tether f = -k_s (x - x_hang) - c_s v whose elastic
+ *     part minus the static weight loads the spur, clamped; they detach by a
+ *     sustained pull or stem tension (Sec. "Fruit");
+ *   - applied forces pass an impulse cap and are disabled on snapped sub-trees
+ *     (Sec. "Numerical Stability").
+ *
+ * Conventions.
+ *   - All device pointers are raw HIP device pointers (e.g. torch data_ptr()).
+ *   - Segment and apple arrays on the device are in the model's INTERNAL order
+ *     (trees grouped into packs, level-major inside a pack).  orchard_model_maps()
+ *     gives, for every internal slot, the descriptor's global index.
+ *   - Units SI; world frame z up; quaternions (w, x, y, z).
+ *   - Functions return orchard_status_t; no C++ exception crosses the ABI.  A
+ *     message for the last failure on the calling thread: orchard_last_error().
+ *   - Stream-ordered calls are asynchronous and allocate nothing after create.
+ *     A model is used by one stream at a time (not thread-safe).
+ */
+#ifndef ORCHARD_H
+#define ORCHARD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orchard_model_s* orchard_model_t;
+typedef void* orchard_stream_t; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  ORCHARD_OK = 0,
+  ORCHARD_ERR_INVALID_ARG = 1,      /* bad pointer, size or parameter            */
+  ORCHARD_ERR_INVALID_TOPOLOGY = 2, /* parent >= child, non-positive size, ...   */
+  ORCHARD_ERR_OUT_OF_MEMORY = 3,
+  ORCHARD_ERR_HIP = 4,              /* a HIP runtime call failed                  */
+  ORCHARD_ERR_NONFINITE = 5,        /* an env produced a non-finite state         */
+  ORCHARD_ERR_CAPACITY = 6          /* caller's event buffer was too small        */
+} orchard_status_t;
+
+/* Tree batch description.  HOST memory, read during orchard_model_create; the
+ * caller keeps ownership.  Arrays are concatenated over envs (CSR offsets). */
+typedef struct {
+  int32_t n_env;
+  const int32_t* seg_offset;    /* [n_env+1]                                         */
+  const int32_t* seg_parent;    /* [n_seg] env-local parent, -1 = world, parent < i  */
+  const double* seg_rest_quat;  /* [n_seg][4] q_rel = conj(Q_parent) Q_child, unit   */
+  const double* seg_length;     /* [n_seg] l > 0                                     */
+  const double* seg_radius;     /* [n_seg] r > 0                                     */
+  const double* seg_density;    /* [n_seg] rho > 0                                   */
+  const double* seg_youngs;     /* [n_seg] E > 0                                     */
+  const double* seg_mor;        /* [n_seg] modulus of rupture sigma_r > 0            */
+  const int32_t* apple_offset;  /* [n_env+1]                                         */
+  const int32_t* apple_seg;     /* [n_apple] env-local segment the apple hangs from  */
+  const double* apple_hang;     /* [n_apple][3] hang point in that segment's frame   */
+  const double* apple_mass;     /* [n_apple] > 0                                     */
+  const double* apple_radius;   /* [n_apple] (solid sphere inertia 2/5 m R^2)        */
+  const double* apple_detach;   /* [n_apple] detach force threshold f_det > 0        */
+  /* step constants */
+  double dt;                    /* time step h                                        */
+  double gravity[3];
+  double tether_k;              /* k_s                                                */
+  double tether_zeta;           /* c_s = 2 zeta sqrt(k_s m)                           */
+  double damping_zeta;          /* Kd = 2 zeta sqrt(Kp J), J = mean rest mass-matrix  */
+  double damping_cd;            /*   diagonal of the joint; if > 0: Kd = c_d Kp       */
+  double tension_factor;        /* tension threshold = factor * f_det                 */
+  double v_cap;                 /* impulse cap: |F| <= m_body v_cap / h               */
+  double react_max_factor;      /* spur reaction clamp = factor * f_det               */
+  int32_t n_break, n_pull, n_tension; /* consecutive steps before an event           */
+  int32_t pad0;
+  uint64_t rng_seed;            /* in-step random body forces (see orchard_step)      */
+  double wrench_fraction;       /* fraction of bodies pushed per step (0 = off)       */
+  double wrench_sigma;          /* N(0, sigma) per force component                    */
+} orchard_model_desc_t;
+
+/* Kernel mapping choices (nullable in create: defaults).  threads: workgroup size
+ * for the pack kernel (64, 128, 256 or 512).  pack_fill: a pack collects trees of
+ * similar depth until it holds about pack_fill * threads * depth nodes (0 = one
+ * tree per pack). */
+typedef struct {
+  int32_t threads;
+  float pack_fill;
+  int32_t steps_per_launch;     /* steps fused in one launch by orchard_step (>= 1)   */
+  int32_t persistent;           /* 1: persistent grid pulling packs from a queue      */
+} orchard_tuning_t;
+
+typedef struct {
+  int64_t n_env, n_seg, n_apple;
+  int32_t n_pack, max_depth;
+  int64_t scratch_bytes;        /* device memory the model owns                       */
+} orchard_layout_t;
+
+/* Caller-owned device state (internal order). */
+typedef struct {
+  float* q;            /* [n_seg][2]   bending angles (theta_x, theta_y)               */
+  float* qd;           /* [n_seg][2]   their rates                                      */
+  float* apple;        /* [13][n_apple] planes: x(3) v(3) quat(4, w first) omega(3);   */
+                       /*   x is the displacement from the apple's rest hang point      */
+                       /*   (orchard_model_apple_rest), v the absolute velocity         */
+  uint8_t* seg_evt;    /* [2][n_seg]   broken flag, consecutive-exceed counter          */
+  uint8_t* apple_evt;  /* [4][n_apple] detached flag, pull counter, tension counter,   */
+                       /*              detach path (1 pull, 2 tension)                  */
+  int32_t* evt_step;   /* [n_seg + n_apple] step of break / detach, -1 = none          */
+  uint32_t* env_status;/* [n_env] bit 0: non-finite state produced; env frozen         */
+  int64_t* step;       /* device scalar: index of the next step (event stamps, RNG)    */
+} orchard_state_t;
+
+typedef struct {
+  const float* kp;     /* [n_seg] joint stiffness (both DoF), device                    */
+  const float* kd;     /* [n_seg] joint damping                                         */
+} orchard_params_t;
+
+typedef struct {
+  const float* body_wrench;  /* [n_seg][6] force(3), torque(3) about the COM, world; or NULL */
+  int64_t body_wrench_stride;/* floats between consecutive steps' arrays; 0 = constant      */
+  const float* apple_force;  /* [n_apple][3] world force on the apple; or NULL              */
+  int64_t apple_force_stride;/* floats between steps; 0 = constant                         */
+} orchard_inputs_t;
+
+typedef struct {
+  int32_t env;   /* descriptor env index                                  */
+  int32_t kind;  /* 1 break, 2 detach by pull, 3 detach by stem tension   */
+  int32_t id;    /* env-local descriptor segment / apple index            */
+  int32_t step;
+} orchard_event_t;
+
+/* Build a model: validates the description (synchronously), derives masses,
+ * inertias, Kp (Eq. beam), M_max (Eq. break) and Kd on the host in FP64, groups
+ * trees into packs, and copies everything to the current HIP device.
+ * Errors: INVALID_ARG, INVALID_TOPOLOGY (parent >= child, sizes <= 0, quaternion
+ * not unit within 1e-6, apple_seg out of range), OUT_OF_MEMORY, HIP. */
+orchard_status_t orchard_model_create(const orchard_model_desc_t* desc, const orchard_tuning_t* tuning,
+                                      orchard_model_t* out);
+void orchard_model_destroy(orchard_model_t model);
+orchard_status_t orchard_model_layout(orchard_model_t model, orchard_layout_t* out);
+
+/* Host arrays: seg_map[n_seg] = descriptor global segment index of each internal
+ * slot; apple_map[n_apple] likewise.  Either may be NULL. */
+orchard_status_t orchard_model_maps(orchard_model_t model, int32_t* seg_map, int32_t* apple_map);
+
+/* Rest hang points of the apples, host double [n_apple][3], internal order.  The
+ * apple position state is the displacement from this point (a representation that
+ * keeps the stiff tether's stretch free of absolute-position round-off in FP32). */
+orchard_status_t orchard_model_apple_rest(orchard_model_t model, double* host_out);
+
+/* Derived Kp, Kd (device arrays [n_seg], internal order) -- the defaults of the
+ * differentiable parameters. */
+orchard_status_t orchard_default_params(orchard_model_t model, float* kp, float* kd, orchard_stream_t stream);
+
+/* Rest state: q = qd = 0 (the generated skeleton pose), apples hanging
+ * m |g| / k_s below their hang point at rest, counters and flags zero, event steps
+ * -1, status 0, step counter 0. */
+orchard_status_t orchard_state_rest(orchard_model_t model, const orchard_state_t* state, orchard_stream_t stream);
+
+/* Advance every env by n_steps (stream-ordered, asynchronous, no allocation).
+ * Per step: event tests on the current state (rupture, detachment), snapped mask,
+ * applied forces (inputs plus, if wrench_fraction > 0, the counter-based random
+ * forces), apple reactions, bias forces, factorisation of the implicit mass
+ * matrix, solve, integration.  If ckpt is non-NULL, the full state is written to
+ * ckpt every ckpt_every steps (ckpt[k] = state before step k*ckpt_every of this
+ * call), orchard_ckpt_words() 32-bit words per checkpoint; ckpt needs room for
+ * ceil(n_steps / ckpt_every) records. */
+orchard_status_t orchard_step(orchard_model_t model, const orchard_state_t* state, const orchard_params_t* params,
+                              const orchard_inputs_t* inputs, int32_t n_steps, float* ckpt, int32_t ckpt_every,
+                              orchard_stream_t stream);
+
+/* Size in 32-bit words of one checkpoint record written by orchard_step. */
+int64_t orchard_ckpt_words(orchard_model_t model);
+
+/* Restore a state from one checkpoint record (stream-ordered). */
+orchard_status_t orchard_ckpt_load(orchard_model_t model, const orchard_state_t* state, const float* record,
+                                   orchard_stream_t stream);
+
+/* Events so far (synchronises the stream).  Writes up to capacity events to
+ * host_out in (env, step, kind, id) order and their total count to *n_out;
+ * returns ORCHARD_ERR_CAPACITY if there were more. */
+orchard_status_t orchard_events(orchard_model_t model, const orchard_state_t* state, orchard_event_t* host_out,
+                                int32_t capacity, int32_t* n_out, orchard_stream_t stream);
+
+/* Per-env status words (synchronises).  Returns ORCHARD_ERR_NONFINITE if any env
+ * is flagged. */
+orchard_status_t orchard_status(orchard_model_t model, const orchard_state_t* state, uint32_t* host_env_status,
+                                orchard_stream_t stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* orchard_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ORCHARD_H */

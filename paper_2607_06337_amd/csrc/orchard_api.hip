@@ -1,0 +1,641 @@
+// Host side of liborchard: model creation (validation, FP64 derived parameters,
+// packing trees into level-synchronous packs, device layout), launches, events.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/orchard.h"
+#include "orchard_dev.h"
+
+namespace orchard {
+
+template <int NT> __global__ void k_step_packs(DevModel, DevState, DevInputs, int, int);
+template <int NT> __global__ void k_step_persistent(DevModel, DevState, DevInputs, int, int, int32_t*);
+__global__ void k_advance(int64_t*, int32_t*, int);
+__global__ void k_state_rest(DevModel, DevState, const float*);
+__global__ void k_ckpt_save(DevModel, DevState, uint32_t*);
+__global__ void k_ckpt_load(DevModel, DevState, const uint32_t*);
+
+static thread_local std::string g_err;
+
+static orchard_status_t fail(orchard_status_t s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess) return fail(ORCHARD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+}  // namespace orchard
+
+using namespace orchard;
+
+struct orchard_model_s {
+  DevModel dm{};
+  orchard_tuning_t tun{};
+  int64_t n_env = 0, n_seg = 0, n_apple = 0;
+  int32_t n_pack = 0, max_depth = 0;
+  std::vector<int32_t> seg_map, apple_map;            // internal -> descriptor global
+  std::vector<int32_t> env_seg_off, env_apple_off;    // descriptor offsets
+  std::vector<int32_t> node_env_h, apple_env_h;
+  std::vector<double> apple_hang_rest;                // [n_apple][3] rest hang points
+  void* arena = nullptr;
+  float* scr = nullptr;
+  float* kp0 = nullptr;
+  float* kd0 = nullptr;
+  float* apple_rest = nullptr;
+  int64_t bytes = 0;
+  int n_cu = 256;
+  int persist_blocks = 0;
+};
+
+namespace {
+
+struct D3 { double x, y, z; };
+inline D3 d3(double a, double b, double c) { return D3{a, b, c}; }
+inline D3 add(D3 a, D3 b) { return d3(a.x + b.x, a.y + b.y, a.z + b.z); }
+inline D3 sub(D3 a, D3 b) { return d3(a.x - b.x, a.y - b.y, a.z - b.z); }
+inline D3 scl(double s, D3 a) { return d3(s * a.x, s * a.y, s * a.z); }
+inline double ddot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+struct DM3 { double m[9]; };
+inline DM3 mm(const DM3& a, const DM3& b) {
+  DM3 r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) r.m[3 * i + j] = a.m[3 * i] * b.m[j] + a.m[3 * i + 1] * b.m[3 + j] + a.m[3 * i + 2] * b.m[6 + j];
+  return r;
+}
+inline D3 mv(const DM3& a, D3 v) {
+  return d3(a.m[0] * v.x + a.m[1] * v.y + a.m[2] * v.z, a.m[3] * v.x + a.m[4] * v.y + a.m[5] * v.z,
+            a.m[6] * v.x + a.m[7] * v.y + a.m[8] * v.z);
+}
+inline DM3 quatm(const double* q) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  return DM3{{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y), 2 * (x * y + w * z),
+              1 - 2 * (x * x + z * z), 2 * (y * z - w * x), 2 * (x * z - w * y), 2 * (y * z + w * x),
+              1 - 2 * (x * x + y * y)}};
+}
+
+struct Arena {
+  size_t off = 0;
+  struct Item { size_t off; const void* src; size_t bytes; };
+  std::vector<Item> items;
+  size_t put(const void* src, size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    items.push_back({off, src, bytes});
+    size_t o = off;
+    off += bytes;
+    return o;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* orchard_last_error(void) { return g_err.c_str(); }
+
+orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orchard_tuning_t* tuning,
+                                      orchard_model_t* out) {
+  g_err.clear();
+  if (!d || !out) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (d->n_env <= 0 || !d->seg_offset || !d->seg_parent || !d->seg_rest_quat || !d->seg_length || !d->seg_radius ||
+      !d->seg_density || !d->seg_youngs || !d->seg_mor || !d->apple_offset)
+    return fail(ORCHARD_ERR_INVALID_ARG, "missing descriptor array");
+  if (!(d->dt > 0) || !(d->tether_k > 0) || d->n_break < 1 || d->n_pull < 1 || d->n_tension < 1 ||
+      !(d->tension_factor > 0) || !(d->v_cap > 0) || !(d->react_max_factor > 0) || d->wrench_fraction < 0 ||
+      d->wrench_fraction > 1)
+    return fail(ORCHARD_ERR_INVALID_ARG, "step constant out of range");
+  orchard_tuning_t tun{128, 1.0f, 1, 0};
+  if (tuning) tun = *tuning;
+  if (tun.threads != 64 && tun.threads != 128 && tun.threads != 256 && tun.threads != 512)
+    return fail(ORCHARD_ERR_INVALID_ARG, "tuning.threads must be 64, 128, 256 or 512");
+  if (tun.steps_per_launch < 1) tun.steps_per_launch = 1;
+
+  const int B = d->n_env;
+  if (d->seg_offset[0] != 0 || d->apple_offset[0] != 0) return fail(ORCHARD_ERR_INVALID_ARG, "offsets must start at 0");
+  for (int e = 0; e < B; ++e)
+    if (d->seg_offset[e + 1] <= d->seg_offset[e] || d->apple_offset[e + 1] < d->apple_offset[e])
+      return fail(ORCHARD_ERR_INVALID_TOPOLOGY, "env " + std::to_string(e) + ": empty tree or decreasing offsets");
+  const int64_t NS = d->seg_offset[B], NA = d->apple_offset[B];
+  if (NS > (1LL << 30) || NA > (1LL << 30)) return fail(ORCHARD_ERR_INVALID_ARG, "batch too large");
+  if (NA > 0 && (!d->apple_seg || !d->apple_hang || !d->apple_mass || !d->apple_radius || !d->apple_detach))
+    return fail(ORCHARD_ERR_INVALID_ARG, "missing apple array");
+
+  // ---- validation and FP64 derived parameters ----
+  std::vector<double> mass(NS), Jt(NS), Iax(NS), kp(NS), mmax(NS), kd(NS);
+  std::vector<DM3> Rw(NS);
+  std::vector<D3> pw(NS);
+  std::vector<int32_t> depth(NS);
+  for (int e = 0; e < B; ++e) {
+    const int s0 = d->seg_offset[e], s1 = d->seg_offset[e + 1];
+    for (int g = s0; g < s1; ++g) {
+      const int i = g - s0, p = d->seg_parent[g];
+      if (p >= i || p < -1)
+        return fail(ORCHARD_ERR_INVALID_TOPOLOGY, "env " + std::to_string(e) + " segment " + std::to_string(i) + ": parent must be -1 or < index");
+      const double l = d->seg_length[g], r = d->seg_radius[g], rho = d->seg_density[g];
+      if (!(l > 0) || !(r > 0) || !(rho > 0) || !(d->seg_youngs[g] > 0) || !(d->seg_mor[g] > 0) || !std::isfinite(l) || !std::isfinite(r))
+        return fail(ORCHARD_ERR_INVALID_TOPOLOGY, "env " + std::to_string(e) + " segment " + std::to_string(i) + ": non-positive size or material");
+      const double* q = d->seg_rest_quat + 4 * (int64_t)g;
+      const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      if (!(std::fabs(nq - 1.0) <= 1e-6)) return fail(ORCHARD_ERR_INVALID_TOPOLOGY, "rest quaternion not unit");
+      // capsule: cylinder + two hemispheres
+      const double mc = rho * M_PI * r * r * l, mh = rho * 4.0 / 3.0 * M_PI * r * r * r;
+      mass[g] = mc + mh;
+      Iax[g] = mc * r * r / 2.0 + mh * 2.0 * r * r / 5.0;
+      const double It = mc * (l * l / 12.0 + r * r / 4.0) + mh * (2.0 * r * r / 5.0 + l * l / 4.0 + 3.0 * l * r / 8.0);
+      Jt[g] = It + mass[g] * l * l / 4.0;  // transverse inertia about the joint point
+      kp[g] = M_PI / 4.0 * d->seg_youngs[g] * r * r * r * r / l;  // Eq. beam
+      mmax[g] = d->seg_mor[g] * M_PI * r * r * r / 4.0;           // Eq. break
+      // rest pose
+      double qn[4] = {q[0] / nq, q[1] / nq, q[2] / nq, q[3] / nq};
+      const DM3 Q = quatm(qn);
+      if (p < 0) {
+        Rw[g] = Q; pw[g] = d3(0, 0, 0); depth[g] = 0;
+      } else {
+        const int gp = s0 + p;
+        Rw[g] = mm(Rw[gp], Q);
+        pw[g] = add(pw[gp], scl(d->seg_length[gp], d3(Rw[gp].m[2], Rw[gp].m[5], Rw[gp].m[8])));
+        depth[g] = depth[gp] + 1;
+      }
+    }
+    // composite rotational inertia of every sub-tree about its joint point at rest:
+    // accumulate mass, first moment and inertia about the world origin leaf -> root
+    const int S = s1 - s0;
+    std::vector<double> Msum(S, 0.0);
+    std::vector<D3> Csum(S, d3(0, 0, 0));
+    std::vector<std::array<double, 6>> JO(S);
+    for (int i = S - 1; i >= 0; --i) {
+      const int g = s0 + i;
+      const D3 z = d3(Rw[g].m[2], Rw[g].m[5], Rw[g].m[8]);
+      const D3 c = add(pw[g], scl(0.5 * d->seg_length[g], z));
+      const double It = Jt[g] - mass[g] * d->seg_length[g] * d->seg_length[g] / 4.0, dI = Iax[g] - It;
+      const double m = mass[g], cc = ddot(c, c);
+      std::array<double, 6>& J = JO[i];
+      J[0] += It + dI * z.x * z.x + m * (cc - c.x * c.x);
+      J[1] += It + dI * z.y * z.y + m * (cc - c.y * c.y);
+      J[2] += It + dI * z.z * z.z + m * (cc - c.z * c.z);
+      J[3] += dI * z.x * z.y - m * c.x * c.y;
+      J[4] += dI * z.x * z.z - m * c.x * c.z;
+      J[5] += dI * z.y * z.z - m * c.y * c.z;
+      Msum[i] += m;
+      Csum[i] = add(Csum[i], scl(m, c));
+      const int p = d->seg_parent[g];
+      if (p >= 0) {
+        for (int k = 0; k < 6; ++k) JO[p][k] += J[k];
+        Msum[p] += Msum[i];
+        Csum[p] = add(Csum[p], Csum[i]);
+      }
+    }
+    for (int i = 0; i < S; ++i) {
+      const int g = s0 + i, p = d->seg_parent[g];
+      const double M = Msum[i];
+      const D3 C = scl(1.0 / M, Csum[i]), P = pw[g], Cp = sub(C, P);
+      // J_P = J_O - M(|C|^2 1 - C C^T) + M(|C-P|^2 1 - (C-P)(C-P)^T)
+      const double cc = ddot(C, C), pp = ddot(Cp, Cp);
+      double J[6];
+      J[0] = JO[i][0] - M * (cc - C.x * C.x) + M * (pp - Cp.x * Cp.x);
+      J[1] = JO[i][1] - M * (cc - C.y * C.y) + M * (pp - Cp.y * Cp.y);
+      J[2] = JO[i][2] - M * (cc - C.z * C.z) + M * (pp - Cp.z * Cp.z);
+      J[3] = JO[i][3] + M * C.x * C.y - M * Cp.x * Cp.y;
+      J[4] = JO[i][4] + M * C.x * C.z - M * Cp.x * Cp.z;
+      J[5] = JO[i][5] + M * C.y * C.z - M * Cp.y * Cp.z;
+      const DM3 Rpar = p < 0 ? DM3{{1, 0, 0, 0, 1, 0, 0, 0, 1}} : Rw[s0 + p];
+      const double* q = d->seg_rest_quat + 4 * (int64_t)g;
+      const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      double qn[4] = {q[0] / nq, q[1] / nq, q[2] / nq, q[3] / nq};
+      const DM3 Jf = mm(Rpar, quatm(qn));
+      const D3 a0 = d3(Jf.m[0], Jf.m[3], Jf.m[6]), a1 = d3(Rw[g].m[1], Rw[g].m[4], Rw[g].m[7]);
+      auto quad = [&](D3 a) {
+        return J[0] * a.x * a.x + J[1] * a.y * a.y + J[2] * a.z * a.z +
+               2.0 * (J[3] * a.x * a.y + J[4] * a.x * a.z + J[5] * a.y * a.z);
+      };
+      const double Jj = 0.5 * (quad(a0) + quad(a1));
+      kd[g] = d->damping_cd > 0 ? d->damping_cd * kp[g] : 2.0 * d->damping_zeta * std::sqrt(kp[g] * Jj);
+    }
+  }
+  std::vector<float> arest(3 * NA);
+  std::vector<float4> ahang_h(NA), apar_h(NA);
+  std::vector<int32_t> aseg_g(NA);
+  for (int e = 0; e < B; ++e) {
+    const int s0 = d->seg_offset[e], S = d->seg_offset[e + 1] - s0;
+    for (int a = d->apple_offset[e]; a < d->apple_offset[e + 1]; ++a) {
+      const int b = d->apple_seg[a];
+      if (b < 0 || b >= S) return fail(ORCHARD_ERR_INVALID_TOPOLOGY, "apple_seg out of range");
+      if (!(d->apple_mass[a] > 0) || !(d->apple_detach[a] > 0)) return fail(ORCHARD_ERR_INVALID_ARG, "apple mass / detach force must be > 0");
+      aseg_g[a] = s0 + b;
+    }
+  }
+
+  // ---- per-tree breadth-first order and level widths ----
+  std::vector<std::vector<int32_t>> bfs(B);     // descriptor global indices in BFS order
+  std::vector<std::vector<int32_t>> lvlw(B);    // nodes per level
+  int32_t maxd = 0;
+  for (int e = 0; e < B; ++e) {
+    const int s0 = d->seg_offset[e], S = d->seg_offset[e + 1] - s0;
+    std::vector<int32_t> cnt(S + 1, 0);
+    for (int i = 0; i < S; ++i) if (d->seg_parent[s0 + i] >= 0) cnt[d->seg_parent[s0 + i] + 1]++;
+    for (int i = 0; i < S; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> kids(cnt[S]), fill(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < S; ++i) { const int p = d->seg_parent[s0 + i]; if (p >= 0) kids[fill[p]++] = i; }
+    std::vector<int32_t>& order = bfs[e];
+    order.reserve(S);
+    for (int i = 0; i < S; ++i) if (d->seg_parent[s0 + i] < 0) order.push_back(i);
+    for (size_t k = 0; k < order.size(); ++k) {
+      const int i = order[k];
+      for (int c = cnt[i]; c < cnt[i + 1]; ++c) order.push_back(kids[c]);
+    }
+    int dmax = 0;
+    for (int i = 0; i < S; ++i) dmax = std::max(dmax, depth[s0 + i]);
+    lvlw[e].assign(dmax + 1, 0);
+    for (int i = 0; i < S; ++i) lvlw[e][depth[s0 + i]]++;
+    for (int& i : order) i += s0;
+    maxd = std::max(maxd, dmax + 1);
+  }
+
+  // ---- packs: trees of similar depth share one workgroup ----
+  const int NT = tun.threads;
+  std::vector<int32_t> tord(B);
+  std::iota(tord.begin(), tord.end(), 0);
+  std::stable_sort(tord.begin(), tord.end(), [&](int a, int b) {
+    if (lvlw[a].size() != lvlw[b].size()) return lvlw[a].size() > lvlw[b].size();
+    return d->seg_offset[a + 1] - d->seg_offset[a] > d->seg_offset[b + 1] - d->seg_offset[b];
+  });
+  std::vector<std::vector<int32_t>> packs;
+  {
+    std::vector<int32_t> cur;
+    int64_t cur_nodes = 0;
+    size_t cur_depth = 0;
+    for (int t : tord) {
+      const int64_t St = d->seg_offset[t + 1] - d->seg_offset[t];
+      const size_t dt = lvlw[t].size();
+      if (!cur.empty() && (tun.pack_fill <= 0.f || cur_nodes + St > (int64_t)(tun.pack_fill * NT * cur_depth) ||
+                           dt * 10 < cur_depth * 7)) {
+        packs.push_back(cur);
+        cur.clear();
+        cur_nodes = 0;
+      }
+      if (cur.empty()) cur_depth = dt;
+      cur.push_back(t);
+      cur_nodes += St;
+    }
+    if (!cur.empty()) packs.push_back(cur);
+  }
+  // longest-processing-time order: estimated cost = sum over levels of ceil(width / NT)
+  std::vector<int64_t> pcost(packs.size());
+  for (size_t p = 0; p < packs.size(); ++p) {
+    size_t L = 0;
+    for (int t : packs[p]) L = std::max(L, lvlw[t].size());
+    int64_t c = 0;
+    for (size_t l = 0; l < L; ++l) {
+      int64_t w = 0;
+      for (int t : packs[p]) if (l < lvlw[t].size()) w += lvlw[t][l];
+      c += (w + NT - 1) / NT;
+    }
+    pcost[p] = c;
+  }
+  std::vector<int32_t> pord(packs.size());
+  std::iota(pord.begin(), pord.end(), 0);
+  std::stable_sort(pord.begin(), pord.end(), [&](int a, int b) { return pcost[a] > pcost[b]; });
+
+  // ---- internal order ----
+  std::vector<int32_t> seg_map;  seg_map.reserve(NS);
+  std::vector<int32_t> pack_node, pack_lvl, lvl_off;
+  std::vector<int32_t> int_of(NS, -1);
+  for (int pi : pord) {
+    const auto& P = packs[pi];
+    pack_node.push_back((int32_t)seg_map.size());
+    pack_lvl.push_back((int32_t)lvl_off.size());
+    size_t L = 0;
+    for (int t : P) L = std::max(L, lvlw[t].size());
+    std::vector<size_t> pos(P.size(), 0);
+    for (size_t l = 0; l < L; ++l) {
+      lvl_off.push_back((int32_t)seg_map.size());
+      for (size_t k = 0; k < P.size(); ++k) {
+        const int t = P[k];
+        const auto& ord = bfs[t];
+        while (pos[k] < ord.size() && depth[ord[pos[k]]] == (int)l) {
+          int_of[ord[pos[k]]] = (int32_t)seg_map.size();
+          seg_map.push_back(ord[pos[k]]);
+          pos[k]++;
+        }
+      }
+    }
+    lvl_off.push_back((int32_t)seg_map.size());
+  }
+  pack_node.push_back((int32_t)seg_map.size());
+  pack_lvl.push_back((int32_t)lvl_off.size());
+
+  std::vector<int32_t> par_i(NS), child_i(NS), nchild_i(NS, 0), env_i(NS), orig_i(NS);
+  std::vector<float4> rq(NS), geo(NS);
+  std::vector<float> mmax_f(NS), kp_f(NS), kd_f(NS);
+  std::vector<int32_t> env_of_g(NS);
+  for (int e = 0; e < B; ++e)
+    for (int g = d->seg_offset[e]; g < d->seg_offset[e + 1]; ++g) env_of_g[g] = e;
+  for (int64_t i = 0; i < NS; ++i) {
+    const int g = seg_map[i], e = env_of_g[g], s0 = d->seg_offset[e], p = d->seg_parent[g];
+    par_i[i] = p < 0 ? -1 : int_of[s0 + p];
+    child_i[i] = (int32_t)NS;  // no children marker, replaced below
+    env_i[i] = e;
+    orig_i[i] = g - s0;
+    const double* q = d->seg_rest_quat + 4 * (int64_t)g;
+    const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    rq[i] = make_float4((float)(q[0] / nq), (float)(q[1] / nq), (float)(q[2] / nq), (float)(q[3] / nq));
+    geo[i] = make_float4((float)d->seg_length[g], (float)mass[g], (float)Jt[g], (float)Iax[g]);
+    mmax_f[i] = (float)mmax[g];
+    kp_f[i] = (float)kp[g];
+    kd_f[i] = (float)kd[g];
+  }
+  for (int64_t i = NS - 1; i >= 0; --i) {
+    const int p = par_i[i];
+    if (p >= 0) { child_i[p] = (int32_t)i; nchild_i[p]++; }
+  }
+  for (int64_t i = 0; i < NS; ++i) if (nchild_i[i] == 0) child_i[i] = 0;
+  // apples sorted by internal node
+  std::vector<int32_t> aord(NA);
+  std::iota(aord.begin(), aord.end(), 0);
+  std::stable_sort(aord.begin(), aord.end(), [&](int a, int b) { return int_of[aseg_g[a]] < int_of[aseg_g[b]]; });
+  std::vector<int32_t> apple_beg(NS + 1, 0), apple_env(NA);
+  std::vector<double> ahang_rest(3 * NA);
+  for (int64_t k = 0; k < NA; ++k) {
+    const int a = aord[k], g = aseg_g[a], e = env_of_g[g];
+    apple_beg[int_of[g] + 1]++;
+    const double ma = d->apple_mass[a];
+    ahang_h[k] = make_float4((float)d->apple_hang[3 * a], (float)d->apple_hang[3 * a + 1], (float)d->apple_hang[3 * a + 2], (float)ma);
+    apar_h[k] = make_float4((float)d->apple_detach[a], (float)(2.0 * d->tether_zeta * std::sqrt(d->tether_k * ma)),
+                            (float)(d->react_max_factor * d->apple_detach[a]), 0.f);
+    const D3 hl = d3(d->apple_hang[3 * a], d->apple_hang[3 * a + 1], d->apple_hang[3 * a + 2]);
+    // apple positions are stored relative to their rest hang point; at rest the apple
+    // hangs m |g| / k_s below it
+    const D3 xh0 = add(pw[g], mv(Rw[g], hl));
+    ahang_rest[3 * k] = xh0.x; ahang_rest[3 * k + 1] = xh0.y; ahang_rest[3 * k + 2] = xh0.z;
+    arest[k] = (float)(ma / d->tether_k * d->gravity[0]);
+    arest[NA + k] = (float)(ma / d->tether_k * d->gravity[1]);
+    arest[2 * NA + k] = (float)(ma / d->tether_k * d->gravity[2]);
+    apple_env[k] = e;
+  }
+  for (int64_t i = 0; i < NS; ++i) apple_beg[i + 1] += apple_beg[i];
+
+  // ---- device layout ----
+  orchard_model_s* M = new orchard_model_s();
+  M->tun = tun;
+  M->n_env = B; M->n_seg = NS; M->n_apple = NA;
+  M->n_pack = (int32_t)packs.size();
+  M->max_depth = maxd;
+  M->seg_map = seg_map;
+  M->apple_map = aord;
+  M->env_seg_off.assign(d->seg_offset, d->seg_offset + B + 1);
+  M->env_apple_off.assign(d->apple_offset, d->apple_offset + B + 1);
+  M->node_env_h = env_i;
+  M->apple_env_h = apple_env;
+  M->apple_hang_rest = ahang_rest;
+  const int32_t zero = 0;
+  Arena ar;
+  size_t o_pn = ar.put(pack_node.data(), pack_node.size() * 4), o_pl = ar.put(pack_lvl.data(), pack_lvl.size() * 4),
+         o_lo = ar.put(lvl_off.data(), lvl_off.size() * 4), o_par = ar.put(par_i.data(), NS * 4),
+         o_ch = ar.put(child_i.data(), NS * 4), o_nc = ar.put(nchild_i.data(), NS * 4), o_env = ar.put(env_i.data(), NS * 4),
+         o_or = ar.put(orig_i.data(), NS * 4), o_ab = ar.put(apple_beg.data(), (NS + 1) * 4),
+         o_rq = ar.put(rq.data(), NS * 16), o_geo = ar.put(geo.data(), NS * 16), o_mm = ar.put(mmax_f.data(), NS * 4),
+         o_ah = ar.put(ahang_h.data(), NA * 16), o_ap = ar.put(apar_h.data(), NA * 16),
+         o_kp = ar.put(kp_f.data(), NS * 4), o_kd = ar.put(kd_f.data(), NS * 4), o_ar = ar.put(arest.data(), 3 * NA * 4),
+         o_q = ar.put(&zero, 4 * 16);
+  hipError_t he = hipMalloc(&M->arena, ar.off + 256);
+  if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
+  std::vector<char> zeros(64, 0);
+  for (auto& it : ar.items) {
+    const void* src = it.src == &zero ? zeros.data() : it.src;
+    if (it.bytes) {
+      he = hipMemcpy((char*)M->arena + it.off, src, it.bytes, hipMemcpyHostToDevice);
+      if (he != hipSuccess) { (void)hipFree(M->arena); delete M; return fail(ORCHARD_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(he)); }
+    }
+  }
+  const size_t scr_bytes = (size_t)N_FIELDS * (size_t)std::max<int64_t>(NS, 1) * 4;
+  he = hipMalloc(&M->scr, scr_bytes);
+  if (he != hipSuccess) { (void)hipFree(M->arena); delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc scratch: ") + hipGetErrorString(he)); }
+  M->bytes = (int64_t)(ar.off + scr_bytes);
+  char* base = (char*)M->arena;
+  DevModel& dm = M->dm;
+  dm.n_env = B; dm.n_seg = (int32_t)NS; dm.n_apple = (int32_t)NA; dm.n_pack = M->n_pack;
+  dm.pack_node = (const int32_t*)(base + o_pn); dm.pack_lvl = (const int32_t*)(base + o_pl);
+  dm.lvl_off = (const int32_t*)(base + o_lo); dm.par = (const int32_t*)(base + o_par);
+  dm.child = (const int32_t*)(base + o_ch); dm.nchild = (const int32_t*)(base + o_nc);
+  dm.env = (const int32_t*)(base + o_env); dm.orig = (const int32_t*)(base + o_or);
+  dm.apple_beg = (const int32_t*)(base + o_ab); dm.rq = (const float4*)(base + o_rq);
+  dm.geo = (const float4*)(base + o_geo); dm.mmax = (const float*)(base + o_mm);
+  dm.ahang = (const float4*)(base + o_ah); dm.apar = (const float4*)(base + o_ap);
+  M->kp0 = (float*)(base + o_kp); M->kd0 = (float*)(base + o_kd); M->apple_rest = (float*)(base + o_ar);
+  dm.queue = (int32_t*)(base + o_q);
+  dm.h = (float)d->dt;
+  dm.gx = (float)d->gravity[0]; dm.gy = (float)d->gravity[1]; dm.gz = (float)d->gravity[2];
+  dm.ks = (float)d->tether_k; dm.alpha = (float)d->tension_factor; dm.vcap = (float)d->v_cap;
+  dm.n_break = d->n_break; dm.n_pull = d->n_pull; dm.n_tension = d->n_tension;
+  dm.use_rng = d->wrench_fraction > 0 ? 1 : 0;
+  dm.seed = d->rng_seed;
+  dm.rng_thr = (uint32_t)std::floor(d->wrench_fraction * 16777216.0);
+  dm.wsig = (float)d->wrench_sigma;
+  dm.scr = M->scr;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&M->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  int per_cu = 1;
+  switch (tun.threads) {
+    case 64: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<64>, 64, 0); break;
+    case 128: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<128>, 128, 0); break;
+    case 256: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<256>, 256, 0); break;
+    default: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<512>, 512, 0); break;
+  }
+  M->persist_blocks = std::max(1, std::min<int>(M->n_pack, std::max(1, per_cu) * std::max(1, M->n_cu)));
+  *out = M;
+  return ORCHARD_OK;
+}
+
+void orchard_model_destroy(orchard_model_t m) {
+  if (!m) return;
+  if (m->arena) (void)hipFree(m->arena);
+  if (m->scr) (void)hipFree(m->scr);
+  delete m;
+}
+
+orchard_status_t orchard_model_layout(orchard_model_t m, orchard_layout_t* out) {
+  if (!m || !out) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  out->n_env = m->n_env; out->n_seg = m->n_seg; out->n_apple = m->n_apple;
+  out->n_pack = m->n_pack; out->max_depth = m->max_depth; out->scratch_bytes = m->bytes;
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_model_maps(orchard_model_t m, int32_t* seg_map, int32_t* apple_map) {
+  if (!m) return fail(ORCHARD_ERR_INVALID_ARG, "null model");
+  if (seg_map) std::copy(m->seg_map.begin(), m->seg_map.end(), seg_map);
+  if (apple_map) std::copy(m->apple_map.begin(), m->apple_map.end(), apple_map);
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_model_apple_rest(orchard_model_t m, double* host_out) {
+  if (!m || (!host_out && m->n_apple)) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  std::copy(m->apple_hang_rest.begin(), m->apple_hang_rest.end(), host_out);
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_default_params(orchard_model_t m, float* kp, float* kd, orchard_stream_t stream) {
+  if (!m) return fail(ORCHARD_ERR_INVALID_ARG, "null model");
+  if (kp) HIPCHK(hipMemcpyAsync(kp, m->kp0, m->n_seg * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  if (kd) HIPCHK(hipMemcpyAsync(kd, m->kd0, m->n_seg * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return ORCHARD_OK;
+}
+
+static orchard_status_t dev_state(orchard_model_t m, const orchard_state_t* s, DevState* ds) {
+  if (!s || !s->q || !s->qd || !s->seg_evt || !s->evt_step || !s->env_status || !s->step)
+    return fail(ORCHARD_ERR_INVALID_ARG, "state pointer missing");
+  if (m->n_apple > 0 && (!s->apple || !s->apple_evt)) return fail(ORCHARD_ERR_INVALID_ARG, "apple state pointer missing");
+  ds->q = (float2*)s->q; ds->qd = (float2*)s->qd; ds->apple = s->apple; ds->seg_evt = s->seg_evt;
+  ds->apple_evt = s->apple_evt; ds->evt_step = s->evt_step; ds->status = s->env_status; ds->step = s->step;
+  return ORCHARD_OK;
+}
+
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)); }
+
+orchard_status_t orchard_state_rest(orchard_model_t m, const orchard_state_t* s, orchard_stream_t stream) {
+  if (!m) return fail(ORCHARD_ERR_INVALID_ARG, "null model");
+  DevState ds;
+  orchard_status_t st = dev_state(m, s, &ds);
+  if (st) return st;
+  const int64_t n = std::max<int64_t>(m->n_seg + m->n_apple, m->n_env);
+  hipLaunchKernelGGL(k_state_rest, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, m->dm, ds, m->apple_rest);
+  HIPCHK(hipGetLastError());
+  return ORCHARD_OK;
+}
+
+int64_t orchard_ckpt_words(orchard_model_t m) {
+  return 4LL * m->n_seg + 13LL * m->n_apple + m->n_seg + m->n_apple + m->n_seg + m->n_apple + m->n_env + 2;
+}
+
+static orchard_status_t launch_steps(orchard_model_t m, const DevState& ds, const DevInputs& di, int k, int s_call,
+                                     hipStream_t stream) {
+  const int NT = m->tun.threads;
+  if (m->tun.persistent) {
+    const dim3 g(m->persist_blocks);
+    switch (NT) {
+      case 64: hipLaunchKernelGGL(k_step_persistent<64>, g, dim3(64), 0, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
+      case 128: hipLaunchKernelGGL(k_step_persistent<128>, g, dim3(128), 0, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
+      case 256: hipLaunchKernelGGL(k_step_persistent<256>, g, dim3(256), 0, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
+      default: hipLaunchKernelGGL(k_step_persistent<512>, g, dim3(512), 0, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
+    }
+  } else {
+    const dim3 g(m->n_pack);
+    switch (NT) {
+      case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), 0, stream, m->dm, ds, di, k, s_call); break;
+      case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), 0, stream, m->dm, ds, di, k, s_call); break;
+      case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), 0, stream, m->dm, ds, di, k, s_call); break;
+      default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), 0, stream, m->dm, ds, di, k, s_call); break;
+    }
+  }
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, stream, ds.step, m->tun.persistent ? m->dm.queue : nullptr, k);
+  HIPCHK(hipGetLastError());
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_step(orchard_model_t m, const orchard_state_t* s, const orchard_params_t* params,
+                              const orchard_inputs_t* inputs, int32_t n_steps, float* ckpt, int32_t ckpt_every,
+                              orchard_stream_t stream) {
+  if (!m || !params || !params->kp || !params->kd) return fail(ORCHARD_ERR_INVALID_ARG, "null model or params");
+  if (n_steps < 0) return fail(ORCHARD_ERR_INVALID_ARG, "n_steps < 0");
+  if (ckpt && ckpt_every < 1) return fail(ORCHARD_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+  DevState ds;
+  orchard_status_t st = dev_state(m, s, &ds);
+  if (st) return st;
+  DevInputs di{params->kp, params->kd, nullptr, 0, nullptr, 0};
+  if (inputs) {
+    di.wrench = inputs->body_wrench; di.wrench_stride = inputs->body_wrench_stride;
+    di.aforce = inputs->apple_force; di.aforce_stride = inputs->apple_force_stride;
+    if (di.wrench_stride < 0 || di.aforce_stride < 0) return fail(ORCHARD_ERR_INVALID_ARG, "negative input stride");
+  }
+  hipStream_t hs = (hipStream_t)stream;
+  const int spl = m->tun.steps_per_launch;
+  const int64_t words = orchard_ckpt_words(m);
+  int s0 = 0;
+  while (s0 < n_steps) {
+    int k = std::min(spl, n_steps - s0);
+    if (ckpt) {
+      if (s0 % ckpt_every == 0) {
+        hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, ds,
+                           (uint32_t*)ckpt + (int64_t)(s0 / ckpt_every) * words);
+        HIPCHK(hipGetLastError());
+      }
+      k = std::min(k, ckpt_every - s0 % ckpt_every);
+    }
+    st = launch_steps(m, ds, di, k, s0, hs);
+    if (st) return st;
+    s0 += k;
+  }
+  return ORCHARD_OK;
+}
+
+// load a checkpoint record written by orchard_step into the state
+orchard_status_t orchard_ckpt_load(orchard_model_t m, const orchard_state_t* s, const float* rec, orchard_stream_t stream) {
+  if (!m || !rec) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  DevState ds;
+  orchard_status_t st = dev_state(m, s, &ds);
+  if (st) return st;
+  hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(orchard_ckpt_words(m))), dim3(256), 0, (hipStream_t)stream, m->dm, ds,
+                     (const uint32_t*)rec);
+  HIPCHK(hipGetLastError());
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_events(orchard_model_t m, const orchard_state_t* s, orchard_event_t* host_out,
+                                int32_t capacity, int32_t* n_out, orchard_stream_t stream) {
+  if (!m || !s || !n_out || (capacity > 0 && !host_out)) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  const int64_t NS = m->n_seg, NA = m->n_apple;
+  std::vector<int32_t> steps(NS + NA);
+  std::vector<uint8_t> path(NA);
+  hipStream_t hs = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(steps.data(), s->evt_step, (NS + NA) * 4, hipMemcpyDeviceToHost, hs));
+  if (NA) HIPCHK(hipMemcpyAsync(path.data(), s->apple_evt + 3 * NA, NA, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  std::vector<orchard_event_t> ev;
+  for (int64_t i = 0; i < NS; ++i)
+    if (steps[i] >= 0) {
+      const int g = m->seg_map[i], e = m->node_env_h[i];
+      ev.push_back({e, 1, g - m->env_seg_off[e], steps[i]});
+    }
+  for (int64_t a = 0; a < NA; ++a)
+    if (steps[NS + a] >= 0) {
+      const int g = m->apple_map[a], e = m->apple_env_h[a];
+      ev.push_back({e, path[a] == 2 ? 3 : 2, g - m->env_apple_off[e], steps[NS + a]});
+    }
+  std::sort(ev.begin(), ev.end(), [](const orchard_event_t& a, const orchard_event_t& b) {
+    if (a.env != b.env) return a.env < b.env;
+    if (a.step != b.step) return a.step < b.step;
+    if (a.kind != b.kind) return a.kind < b.kind;
+    return a.id < b.id;
+  });
+  *n_out = (int32_t)ev.size();
+  const int32_t nw = std::min<int32_t>(capacity, (int32_t)ev.size());
+  if (nw > 0) std::copy(ev.begin(), ev.begin() + nw, host_out);
+  if ((int64_t)ev.size() > capacity) return fail(ORCHARD_ERR_CAPACITY, "event buffer too small");
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_status(orchard_model_t m, const orchard_state_t* s, uint32_t* host_env_status,
+                                orchard_stream_t stream) {
+  if (!m || !s || !host_env_status) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  hipStream_t hs = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(host_env_status, s->env_status, m->n_env * 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  for (int64_t e = 0; e < m->n_env; ++e)
+    if (host_env_status[e]) return fail(ORCHARD_ERR_NONFINITE, "env " + std::to_string(e) + " produced a non-finite state");
+  return ORCHARD_OK;
+}
+
+}  // extern "C"

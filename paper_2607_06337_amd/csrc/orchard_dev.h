@@ -1,0 +1,135 @@
+// Device-side model description and small vector helpers for the orchard kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace orchard {
+
+// ---- scratch fields: one float per node per field, field f at scr + f * n_seg -----------
+// down-pass publication of a node, read by its children (world axes, at the node's tip)
+enum : int {
+  F_R = 0,          // 9: body rotation, row major
+  F_DR = 9,         // 9: body rotation minus its rest value, row major
+  F_DPT = 18,       // 3: tip point minus its rest value (= children's joint point)
+  F_W = 21,         // 3: angular velocity
+  F_VT = 24,        // 3: linear velocity of the tip point
+  F_AVA = 27,       // 3: velocity-product (+ base) acceleration at the tip, angular
+  F_AVL = 30,       // 3:   linear
+  F_SNAP = 33,      // 1: snapped flag
+  // node-private data kept from the down pass for the up pass
+  F_A0 = 34,        // 3: joint axis x (world)
+  F_A1 = 37,        // 3: joint axis y (world)
+  F_C = 40,         // 6: velocity-product acceleration c (ang, lin)
+  F_P = 46,         // 6: bias force p (ang, lin) incl. applied forces
+  F_MO = 52,        // 1: own mass (+ virtual apple masses)
+  F_HO = 53,        // 3: own first moment about the joint point
+  F_JO = 56,        // 6: own rotational inertia about the joint (xx yy zz xy xz yz)
+  F_TAU = 62,       // 2: spring/damper torque
+  F_DG = 64,        // 1: implicit diagonal h kd + h^2 kp
+  F_LZ = 65,        // 3: l * z (joint point -> tip)
+  F_SKIP = 68,      // 1: env frozen at the start of this step
+  // up-pass publication (articulated inertia and bias at the node's joint point)
+  F_IA = 69,        // 6: A (rotational block, sym)
+  F_IB = 75,        // 9: B (coupling block, row major)
+  F_IM = 84,        // 6: M (linear block, sym)
+  F_PA = 90,        // 6: bias (ang, lin)
+  // node-private factor data for the second down pass
+  F_U = 96,         // 12: U = I^A S (col 0: ang 3 lin 3, col 1: ang 3 lin 3)
+  F_DI = 108,       // 3: D^-1 (00 01 11)
+  F_UU = 111,       // 2: u = tau - S^T p^A
+  N_FIELDS = 113,
+  // second down pass publication overwrites the first six fields
+  F_AT = 0          // 6: acceleration at the tip (ang, lin)
+};
+
+struct DevModel {
+  int32_t n_env, n_seg, n_apple, n_pack;
+  // packs: nodes [pack_node[p], pack_node[p+1]); levels lvl_off[pack_lvl[p] .. pack_lvl[p+1]-1]
+  // (the last entry of a pack is its end)
+  const int32_t* pack_node;
+  const int32_t* pack_lvl;
+  const int32_t* lvl_off;
+  // per node (internal order)
+  const int32_t* par;        // parent node, -1 = world
+  const int32_t* child;      // first child node
+  const int32_t* nchild;     // number of children (contiguous)
+  const int32_t* env;        // descriptor env index
+  const int32_t* orig;       // env-local descriptor segment index (counter generator key)
+  const int32_t* apple_beg;  // [n_seg+1] apples of node i: apple_beg[i] .. apple_beg[i+1]-1
+  const float4* rq;          // rest quaternion (w, x, y, z)
+  const float4* geo;         // (l, m, Jt about the joint, Ia)
+  const float* mmax;         // rupture moment
+  // per apple (internal order)
+  const float4* ahang;       // (hang x, y, z in the segment frame, mass)
+  const float4* apar;        // (f_det, c_s, F_max, unused)
+  // constants
+  float h, gx, gy, gz, ks, alpha, vcap, pad;
+  int32_t n_break, n_pull, n_tension, use_rng;
+  uint64_t seed;
+  uint32_t rng_thr;
+  float wsig;
+  float* scr;                // [N_FIELDS][n_seg]
+  int32_t* queue;            // persistent-kernel pack counter(s)
+};
+
+struct DevState {
+  float2* q;
+  float2* qd;
+  float* apple;       // [13][n_apple]
+  uint8_t* seg_evt;   // [2][n_seg]
+  uint8_t* apple_evt; // [4][n_apple]
+  int32_t* evt_step;  // [n_seg + n_apple]
+  uint32_t* status;   // [n_env]
+  int64_t* step;
+};
+
+struct DevInputs {
+  const float* kp;
+  const float* kd;
+  const float* wrench;
+  int64_t wrench_stride;
+  const float* aforce;
+  int64_t aforce_stride;
+};
+
+// ---- small vector helpers ---------------------------------------------------------------
+struct V3 { float x, y, z; };
+__device__ __forceinline__ V3 v3(float a, float b, float c) { return V3{a, b, c}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return V3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return V3{s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return V3{fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x)};
+}
+__device__ __forceinline__ V3 fma3(float s, V3 a, V3 b) { return V3{fmaf(s, a.x, b.x), fmaf(s, a.y, b.y), fmaf(s, a.z, b.z)}; }
+
+// symmetric 3x3 stored (xx yy zz xy xz yz)
+struct Sym3 { float xx, yy, zz, xy, xz, yz; };
+__device__ __forceinline__ V3 mul(const Sym3& A, V3 v) {
+  return V3{fmaf(A.xx, v.x, fmaf(A.xy, v.y, A.xz * v.z)), fmaf(A.xy, v.x, fmaf(A.yy, v.y, A.yz * v.z)),
+            fmaf(A.xz, v.x, fmaf(A.yz, v.y, A.zz * v.z))};
+}
+// general 3x3 row major
+struct Mat3 { float m[9]; };
+__device__ __forceinline__ V3 mul(const Mat3& A, V3 v) {
+  return V3{fmaf(A.m[0], v.x, fmaf(A.m[1], v.y, A.m[2] * v.z)), fmaf(A.m[3], v.x, fmaf(A.m[4], v.y, A.m[5] * v.z)),
+            fmaf(A.m[6], v.x, fmaf(A.m[7], v.y, A.m[8] * v.z))};
+}
+__device__ __forceinline__ V3 mulT(const Mat3& A, V3 v) {
+  return V3{fmaf(A.m[0], v.x, fmaf(A.m[3], v.y, A.m[6] * v.z)), fmaf(A.m[1], v.x, fmaf(A.m[4], v.y, A.m[7] * v.z)),
+            fmaf(A.m[2], v.x, fmaf(A.m[5], v.y, A.m[8] * v.z))};
+}
+
+// ---- SplitMix64 (Steele, Lea & Flood 2014): output mix of x + golden gamma ------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint32_t counter_u24(uint64_t seed, uint64_t env, uint64_t step, uint64_t seg, uint64_t k) {
+  return (uint32_t)(splitmix64(seed ^ splitmix64(env ^ splitmix64(step ^ splitmix64(8ull * seg + k)))) >> 40);
+}
+
+}  // namespace orchard

@@ -1,0 +1,152 @@
+"""Helpers shared by the GPU parity tests: run the HIP path and the FP64 oracle on the
+same seeded inputs and compare them element by element.
+
+Tolerances (joint state): per env and per class, the largest deviation over all
+compared steps and DoF divided by max(largest oracle magnitude in that env, floor),
+floors 1e-3 rad (angles) and 1e-2 rad/s (rates); bar 1e-4.  Events: every (env,
+joint) and (env, apple) whose oracle ratio |mu - 1| (or |pi - 1|, |tau - 1|) stayed
+at least EPS away from 1 over the compared steps must have the identical event (kind
+and step) or none on both sides; ids that came within EPS ("in band") are excluded,
+and if such an id's event differs, the env's state comparison stops at the first
+in-band step.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle.oracle import Band, Oracle
+
+TOL = 1e-4
+FLOOR_Q, FLOOR_QD = 1e-3, 1e-2
+EPS = 1e-3
+
+
+def gpu_events_desc(model, state):
+    """GPU events as {(env, kind, id): step} with descriptor-local ids."""
+    return {(e, k, i): s for (e, k, i, s) in model.events(state)}
+
+
+def oracle_events(batch, st, envs):
+    ev = {}
+    for e in envs:
+        s0, s1 = batch.seg_offset[e], batch.seg_offset[e + 1]
+        a0, a1 = batch.apple_offset[e], batch.apple_offset[e + 1]
+        for i in np.flatnonzero(st.break_step[s0:s1] >= 0):
+            ev[(int(e), 1, int(i))] = int(st.break_step[s0 + i])
+        for a in np.flatnonzero(st.det_step[a0:a1] >= 0):
+            ev[(int(e), 1 + int(st.det_path[a0 + a]), int(a))] = int(st.det_step[a0 + a])
+    return ev
+
+
+class Recorder:
+    """Collects GPU and oracle joint states at the compared steps."""
+
+    def __init__(self, batch, envs):
+        self.batch = batch
+        self.envs = list(envs)
+        self.steps = []
+        self.gq, self.gqd, self.oq, self.oqd = [], [], [], []
+
+    def add(self, step, gq_desc, gqd_desc, ost):
+        self.steps.append(step)
+        self.gq.append(gq_desc.copy())
+        self.gqd.append(gqd_desc.copy())
+        self.oq.append(ost.q.copy())
+        self.oqd.append(ost.qd.copy())
+
+    def errors(self, cut=None):
+        """Per env: (rel q, rel qd, n compared steps)."""
+        out = {}
+        steps = np.array(self.steps)
+        for e in self.envs:
+            s0, s1 = self.batch.seg_offset[e], self.batch.seg_offset[e + 1]
+            use = np.ones(len(steps), bool) if cut is None or cut.get(e) is None else steps <= cut[e]
+            if not use.any():
+                out[e] = (0.0, 0.0, 0)
+                continue
+            gq = np.stack([x[s0:s1] for x in self.gq])[use]
+            oq = np.stack([x[s0:s1] for x in self.oq])[use]
+            gqd = np.stack([x[s0:s1] for x in self.gqd])[use]
+            oqd = np.stack([x[s0:s1] for x in self.oqd])[use]
+            rq = np.max(np.abs(gq - oq)) / max(np.max(np.abs(oq)), FLOOR_Q)
+            rqd = np.max(np.abs(gqd - oqd)) / max(np.max(np.abs(oqd)), FLOOR_QD)
+            out[e] = (float(rq), float(rqd), int(use.sum()))
+        return out
+
+
+def compare_events(batch, gpu_ev, ora_ev, band: Band, envs):
+    """Returns (mismatches outside the band, per-env cut step for in-band differences,
+    number of in-band ids)."""
+    bad, cut, n_band = [], {}, 0
+    for e in envs:
+        s0, s1 = batch.seg_offset[e], batch.seg_offset[e + 1]
+        a0, a1 = batch.apple_offset[e], batch.apple_offset[e + 1]
+        ids = [(1, i, band.jmin[s0 + i], band.jfirst[s0 + i]) for i in range(s1 - s0)]
+        ids += [(None, a, band.amin[a0 + a], band.afirst[a0 + a]) for a in range(a1 - a0)]
+        for kind, i, m, first in ids:
+            keys = [(e, 1, i)] if kind == 1 else [(e, 2, i), (e, 3, i)]
+            g = {k: gpu_ev.get(k) for k in keys if k in gpu_ev}
+            o = {k: ora_ev.get(k) for k in keys if k in ora_ev}
+            if m < EPS:
+                n_band += 1
+                if g != o:
+                    cut[e] = min(cut.get(e, 1 << 30), int(first))
+                continue
+            if g != o:
+                bad.append((e, keys, g, o))
+    return bad, cut, n_band
+
+
+def run_parity(batch, consts, n_steps, every, *, envs=None, tuning=None, aforce_desc=None, aforce_from=0,
+               wrench_desc=None, threads=None):
+    """Run the whole batch on the GPU and the listed envs on the oracle.
+
+    aforce_desc: constant apple force [A_tot, 3] (descriptor order) applied from step
+    aforce_from on.  Returns (errors per env, event mismatches, in-band count, model,
+    gpu state, oracle state)."""
+    import torch
+
+    from paper_2607_06337_amd import Model
+
+    envs = list(range(batch.n_env)) if envs is None else list(envs)
+    m = Model(batch, consts, tuning)
+    st = m.rest_state()
+    kp, kd = m.default_params()
+    o = Oracle(batch, consts)
+    d = o.derived()
+    ost = o.rest_state()
+    band = Band(batch.n_seg, batch.n_apple)
+    af_int = None
+    if aforce_desc is not None:
+        af_int = torch.tensor(m.apple_from_desc(np.asarray(aforce_desc, np.float32), axis=0), device="cuda").contiguous()
+    w_int = None
+    if wrench_desc is not None:
+        w_int = torch.tensor(m.seg_from_desc(np.asarray(wrench_desc, np.float32)), device="cuda").contiguous()
+    rec = Recorder(batch, envs)
+    marks = sorted(set(list(range(every, n_steps + 1, every)) + ([aforce_from] if 0 < aforce_from < n_steps else [])))
+    done = 0
+    for mk in marks:
+        k = mk - done
+        use_f = aforce_desc is not None and done >= aforce_from
+        m.step(st, kp, kd, k, aforce=af_int if use_f else None, wrench=w_int)
+        o.rollout(ost, k, kp=d["kp"], kd=d["kd"], envs=envs, aforce=aforce_desc if use_f else None,
+                  wrench=wrench_desc, band=band, threads=threads)
+        done = mk
+        torch.cuda.synchronize()
+        gq = m.seg_to_desc(st.q.cpu().numpy().astype(np.float64))
+        gqd = m.seg_to_desc(st.qd.cpu().numpy().astype(np.float64))
+        rec.add(done, gq, gqd, ost)
+    gev = gpu_events_desc(m, st)
+    gev = {k: v for k, v in gev.items() if k[0] in set(envs)}
+    oev = oracle_events(batch, ost, envs)
+    bad, cut, n_band = compare_events(batch, gev, oev, band, envs)
+    errs = rec.errors(cut)
+    return errs, bad, n_band, m, st, ost, gev, oev
+
+
+def stratified_envs(batch, n, seed=0):
+    """n env indices spread over the size distribution (sorted by segment count)."""
+    sizes = np.diff(batch.seg_offset)
+    order = np.argsort(sizes, kind="stable")
+    pick = np.unique(np.linspace(0, len(order) - 1, n).round().astype(int))
+    return sorted(int(order[i]) for i in pick)
