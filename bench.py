@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB read + 256 MiB write kernel (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (trees are independent, "
@@ -121,6 +123,12 @@ def main():
         del pm
         print(f"# plain per-step kernel: {plain['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
+    if args.copy_probe:
+        x = torch.ones(64 << 20, device="cuda")
+        for _ in range(3):
+            y = x * 1.0001  # one elementwise kernel: 256 MiB read, 256 MiB written
+        torch.cuda.synchronize()
+        del x, y
     ms_step = ms / args.steps
     value = batch.n_env * args.steps / (ms / 1e3)
     spl = BENCH_TUNING["steps_per_launch"]

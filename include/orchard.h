@@ -107,8 +107,10 @@ typedef struct {
   float* q;            /* [n_seg][2]   bending angles (theta_x, theta_y)               */
   float* qd;           /* [n_seg][2]   their rates                                      */
   float* apple;        /* [13][n_apple] planes: x(3) v(3) quat(4, w first) omega(3);   */
-                       /*   x is the displacement from the apple's rest hang point      */
-                       /*   (orchard_model_apple_rest), v the absolute velocity         */
+                       /*   v is the absolute velocity.  x: while attached, the stretch */
+                       /*   x_abs - x_hang plus h v (the stretch advanced by the apple  */
+                       /*   but not yet by the hang point); once detached, x_abs minus  */
+                       /*   the rest hang point (orchard_model_apple_rest)              */
   uint8_t* seg_evt;    /* [2][n_seg]   broken flag, consecutive-exceed counter          */
   uint8_t* apple_evt;  /* [4][n_apple] detached flag, pull counter, tension counter,   */
                        /*              detach path (1 pull, 2 tension)                  */
@@ -150,9 +152,10 @@ orchard_status_t orchard_model_layout(orchard_model_t model, orchard_layout_t* o
  * slot; apple_map[n_apple] likewise.  Either may be NULL. */
 orchard_status_t orchard_model_maps(orchard_model_t model, int32_t* seg_map, int32_t* apple_map);
 
-/* Rest hang points of the apples, host double [n_apple][3], internal order.  The
- * apple position state is the displacement from this point (a representation that
- * keeps the stiff tether's stretch free of absolute-position round-off in FP32). */
+/* Rest hang points of the apples, host double [n_apple][3], internal order (the
+ * origin of a detached apple's position state).  Attached apples keep their stretch
+ * relative to the current hang point as state, so the stiff tether never sees
+ * absolute-position round-off in FP32. */
 orchard_status_t orchard_model_apple_rest(orchard_model_t model, double* host_out);
 
 /* Derived Kp, Kd (device arrays [n_seg], internal order) -- the defaults of the

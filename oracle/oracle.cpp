@@ -21,7 +21,8 @@
 // The step itself is the plain definition: the joint accelerations qdd are the
 // unique solution of the dense linear system
 //     Mt(q) qdd = -Kp (q + h qd) - Kd qd - c(q, qd, f_ext)
-//     Mt = H(q) + diag(h Kd + h^2 Kp) + h^2 k_s sum_a J_a^T J_a  (unclamped apples)
+//     Mt = H(q) + diag(h Kd + h^2 Kp) + h^2 k_s sum_a s_a J_a^T J_a  (attached apples,
+//          s_a the reaction clamp scale)
 // with H the joint-space mass matrix assembled by the composite-rigid-body
 // method and c the bias of recursive Newton-Euler (textbook forms, world-frame
 // spatial vectors), factored by the tree-sparse L^T D L method.  Then
@@ -312,13 +313,20 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
   // --- event tests on the state at the start of the step (Eq. break; Sec. "Fruit") ---
   for (int i = 0; i < S; ++i) broken[i] = ev ? ev->broken[i] : 0;
   for (int a = 0; a < A; ++a) det[a] = ev ? ev->det[a] : 0;
-  std::vector<V3<T>> xh(A), vh(A);
+  const std::vector<uint8_t> det0(det);  // detached before this step
+  // Apple position state: while attached, sigma = (x - x_hang) + h v after the
+  // previous step's update, so the stretch at this step is s = sigma - h v_hang, with
+  // v_hang the hang point's velocity now (the hang point moved by h v_hang during the
+  // previous step); once detached, the absolute position.
+  std::vector<V3<T>> xh(A), vh(A), sa(A);
   for (int a = 0; a < A; ++a) {
     const int b = t.aseg[a];
     V3<T> hb = K.R[b] * V3<T>(T(t.ahang[a].x), T(t.ahang[a].y), T(t.ahang[a].z));
     xh[a] = K.p[b] + hb;
     const SV<T>& vb = vel[2 * b + 1];
     vh[a] = vb.l + cross(vb.a, xh[a]);
+    V3<T> sig(ax[3 * a], ax[3 * a + 1], ax[3 * a + 2]);
+    sa[a] = det0[a] ? sig - xh[a] : sig - h * vh[a];
   }
   if (replay) {
     broken = replay->broken;
@@ -342,7 +350,7 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
       double F2 = 0.0, d2 = 0.0;
       for (int c = 0; c < 3; ++c) {
         double f = aforce ? val(aforce[3 * a + c]) : 0.0;
-        double d = val(ax[3 * a + c]) - val(xh[a][c]);
+        double d = val(sa[a][c]);
         F2 += f * f; d2 += d * d;
       }
       double pi = std::sqrt(F2) / t.afdet[a];
@@ -389,16 +397,23 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
     V3<T> Tv = V3<T>(T(Tq[0]), T(Tq[1]), T(Tq[2]));
     fext[i] = fext[i] + SV<T>{Tv + cross(K.I[i].c, Fv), Fv};
   }
-  // --- apple reactions on the spur (Sec. "Fruit", linearly implicit in the hang point) ---
+  // --- apple reactions on the spur (Sec. "Fruit"): the elastic tether force minus the
+  // static weight, with the hang point taken at the end of the step to first order
+  // (linearly implicit: explicit part below, h^2 k_s J^T J in the matrix).  The clamp
+  // scales the whole reaction, explicit part and implicit term alike, by
+  // s = min(1, F_max / |f|), so the force stays continuous across the threshold ---
   std::vector<V3<T>> fh(A);
+  std::vector<T> rs(A, T(0));
   for (int a = 0; a < A; ++a) {
     if (det[a]) continue;
-    V3<T> x(ax[3 * a], ax[3 * a + 1], ax[3 * a + 2]);
     V3<T> gw(T(g.gravity[0]), T(g.gravity[1]), T(g.gravity[2]));
-    V3<T> f = ks * (x - xh[a] - h * vh[a]) - t.am[a] * gw;
+    V3<T> f = ks * (sa[a] - h * vh[a]) - t.am[a] * gw;
     T nf = norm(f);
     bool cl = replay ? replay->clamped[a] : (val(nf) > t.afmax[a]);
-    if (cl) { f = (T(t.afmax[a]) / nf) * f; clamped[a] = 1; }
+    T sc = cl ? T(t.afmax[a]) / nf : T(1);
+    if (cl) clamped[a] = 1;
+    rs[a] = sc;
+    f = sc * f;
     fh[a] = f;
     fext[t.aseg[a]] = fext[t.aseg[a]] + SV<T>{cross(xh[a], f), f};
   }
@@ -417,9 +432,9 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
       rhs[k] = -kpe * (q[k] + h * qd[k]) - kde * qd[k] - c[k];
     }
   }
-  for (int a = 0; a < A; ++a) {  // virtual point mass h^2 k_s at the hang point
-    if (det[a] || clamped[a]) continue;
-    const double mv = h * h * ks;
+  for (int a = 0; a < A; ++a) {  // virtual point mass s h^2 k_s at the hang point
+    if (det[a]) continue;
+    const T mv = (h * h * ks) * rs[a];
     std::vector<int> anc;
     for (int j = 2 * t.aseg[a] + 1; j >= 0; j = t.dpar[j]) anc.push_back(j);
     std::vector<V3<T>> col(anc.size());
@@ -439,13 +454,16 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
   }
   // --- apples (explicit, symplectic Euler) ---
   for (int a = 0; a < A; ++a) {
-    V3<T> x(ax[3 * a], ax[3 * a + 1], ax[3 * a + 2]), v(av[3 * a], av[3 * a + 1], av[3 * a + 2]);
+    V3<T> v(av[3 * a], av[3 * a + 1], av[3 * a + 2]);
     V3<T> gw(T(g.gravity[0]), T(g.gravity[1]), T(g.gravity[2]));
     V3<T> f = t.am[a] * gw;
     if (aforce) f += V3<T>(aforce[3 * a], aforce[3 * a + 1], aforce[3 * a + 2]);
-    if (!det[a]) f += -ks * (x - xh[a]) - t.acs[a] * v;
+    if (!det[a]) f += -ks * sa[a] - t.acs[a] * v;
     V3<T> vn = v + (h / t.am[a]) * f;
-    V3<T> xn = x + h * vn;
+    // attached: sigma+ = s + h v+;  detached: absolute x+ = x + h v+ (x = x_hang + s if it
+    // detached at this step)
+    V3<T> base = det[a] ? (det0[a] ? V3<T>(ax[3 * a], ax[3 * a + 1], ax[3 * a + 2]) : xh[a] + sa[a]) : sa[a];
+    V3<T> xn = base + h * vn;
     for (int cc = 0; cc < 3; ++cc) { avo[3 * a + cc] = vn[cc]; axo[3 * a + cc] = xn[cc]; awo[3 * a + cc] = aw[3 * a + cc]; }
     // quat+ = normalize(exp(h w / 2) * quat)
     V3<T> hw = (0.5 * h) * V3<T>(aw[3 * a], aw[3 * a + 1], aw[3 * a + 2]);
@@ -604,6 +622,7 @@ void oracle_ltdl_solve(void* m, int env, const double* q, const double* dg, cons
 }
 
 // rest state: q = qd = 0, apples hanging m g / k_s below the hang point, at rest
+// (apple position state = stretch from the hang point while attached)
 void oracle_rest_state(void* m, const OracleIO* io) {
   Model* M = static_cast<Model*>(m);
   const Globals& g = M->g;
@@ -614,9 +633,8 @@ void oracle_rest_state(void* m, const OracleIO* io) {
     for (int k = 0; k < 2 * t.S; ++k) { io->q[2 * t.seg0 + k] = 0.0; io->qd[2 * t.seg0 + k] = 0.0; }
     for (int a = 0; a < t.A; ++a) {
       const int b = t.aseg[a], ga = t.app0 + a;
-      V3<double> xh = K.p[b] + K.R[b] * t.ahang[a];
       for (int c = 0; c < 3; ++c) {
-        io->ax[3 * ga + c] = xh[c] + t.am[a] * g.gravity[c] / g.tether_k;
+        io->ax[3 * ga + c] = t.am[a] * g.gravity[c] / g.tether_k;  // stretch at rest
         io->av[3 * ga + c] = 0.0;
         io->aw[3 * ga + c] = 0.0;
       }

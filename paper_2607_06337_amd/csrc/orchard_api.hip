@@ -375,8 +375,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     apar_h[k] = make_float4((float)d->apple_detach[a], (float)(2.0 * d->tether_zeta * std::sqrt(d->tether_k * ma)),
                             (float)(d->react_max_factor * d->apple_detach[a]), 0.f);
     const D3 hl = d3(d->apple_hang[3 * a], d->apple_hang[3 * a + 1], d->apple_hang[3 * a + 2]);
-    // apple positions are stored relative to their rest hang point; at rest the apple
-    // hangs m |g| / k_s below it
+    // attached apples store their stretch from the hang point (plus h v); at rest the
+    // apple hangs m |g| / k_s below it
     const D3 xh0 = add(pw[g], mv(Rw[g], hl));
     ahang_rest[3 * k] = xh0.x; ahang_rest[3 * k + 1] = xh0.y; ahang_rest[3 * k + 2] = xh0.z;
     arest[k] = (float)(ma / d->tether_k * d->gravity[0]);

@@ -171,11 +171,17 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
     const float4 ap = M.apar[a];
     const float ma = hm.w, fdet = ap.x, cs = ap.y, fmax = ap.z;
     const V3 d = fma3(hm.x, c0, fma3(hm.y, c1, hm.z * c2));
-    const V3 xh = dpt + fma3(hm.x, d0, fma3(hm.y, d1, hm.z * d2));  // hang point - its rest value
     const V3 vh = v + cross(wi, d);
     float* P = S.apple;
-    V3 x = v3(P[a], P[NA + a], P[2 * NA + a]);
+    // position state: while attached sigma = (x - x_hang) + h v from the previous
+    // update, so the stretch now is s = sigma - h v_hang; once detached, x minus the
+    // rest hang point.  The stretch never passes through absolute positions.
+    const V3 sig = v3(P[a], P[NA + a], P[2 * NA + a]);
     V3 va = v3(P[3 * NA + a], P[4 * NA + a], P[5 * NA + a]);
+    const uint8_t det0 = S.apple_evt[a];
+    V3 sa;
+    if (det0) sa = sig - (dpt + fma3(hm.x, d0, fma3(hm.y, d1, hm.z * d2)));
+    else sa = fma3(-h, vh, sig);
     V3 Fa = v3(0, 0, 0);
     if (I.aforce) {
       const float* fp = I.aforce + (int64_t)s_call * I.aforce_stride + 3 * (int64_t)a;
@@ -184,8 +190,7 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
     uint8_t det = S.apple_evt[a];
     if (!det) {
       const float pi = sqrtf(dot(Fa, Fa)) / fdet;
-      const V3 dx = x - xh;
-      const float tau = M.ks * sqrtf(dot(dx, dx)) / (M.alpha * fdet);
+      const float tau = M.ks * sqrtf(dot(sa, sa)) / (M.alpha * fdet);
       int cp = pi > 1.f ? (int)S.apple_evt[NA + a] + 1 : 0;
       int ct = tau > 1.f ? (int)S.apple_evt[2 * NA + a] + 1 : 0;
       cp = cp > 255 ? 255 : cp;
@@ -203,16 +208,17 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
     const V3 gv = v3(M.gx, M.gy, M.gz);
     if (!det) {
       // reaction on the spur: elastic tether force minus static weight, hang point
-      // taken at the end of the step to first order (implicit), clamped
-      V3 fh = M.ks * (x - xh - h * vh) - ma * gv;
+      // taken at the end of the step to first order (linearly implicit); the clamp
+      // scales explicit part and implicit term alike by s = min(1, F_max / |f|)
+      V3 fh = M.ks * fma3(-h, vh, sa) - ma * gv;
       const float nf = sqrtf(dot(fh, fh));
-      const bool clamped = nf > fmax;
-      if (clamped) fh = (fmax / nf) * fh;
+      const float sc = nf > fmax ? fmax / nf : 1.f;
+      fh = sc * fh;
       pang = pang - cross(d, fh);
       plin = plin - fh;
-      if (!clamped) {
-        // virtual point mass h^2 k_s at the hang point (only its q-acceleration part)
-        const float mv = h * h * M.ks;
+      {
+        // virtual point mass s h^2 k_s at the hang point (only its q-acceleration part)
+        const float mv = sc * h * h * M.ks;
         mo += mv;
         ho = fma3(mv, d, ho);
         const float dd = dot(d, d);
@@ -226,9 +232,11 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
     }
     // apple update: explicit symplectic Euler
     V3 fa = fma3(ma, gv, Fa);
-    if (!det) fa = fa - M.ks * (x - xh) - cs * va;
+    if (!det) fa = fa - M.ks * sa - cs * va;
     va = fma3(h / ma, fa, va);
-    x = fma3(h, va, x);
+    // attached: sigma+ = s + h v+;  detached: (x - x_hang,rest)+ = x - x_hang,rest + h v+
+    const V3 base = det ? (det0 ? sig : (dpt + fma3(hm.x, d0, fma3(hm.y, d1, hm.z * d2))) + sa) : sa;
+    const V3 x = fma3(h, va, base);
     P[a] = x.x; P[NA + a] = x.y; P[2 * NA + a] = x.z;
     P[3 * NA + a] = va.x; P[4 * NA + a] = va.y; P[5 * NA + a] = va.z;
     const V3 om = v3(P[10 * NA + a], P[11 * NA + a], P[12 * NA + a]);

@@ -19,8 +19,10 @@ if not torch.cuda.is_available():  # pragma: no cover
 def _report(name, errs, bad, n_band):
     worst_q = max(v[0] for v in errs.values())
     worst_qd = max(v[1] for v in errs.values())
-    print(f"[{name}] envs={len(errs)} worst rel q={worst_q:.3e} qd={worst_qd:.3e} "
-          f"event mismatches={len(bad)} in-band ids={n_band}", flush=True)
+    eq = max(errs, key=lambda e: errs[e][0])
+    eqd = max(errs, key=lambda e: errs[e][1])
+    print(f"[{name}] envs={len(errs)} worst rel q={worst_q:.3e} (env {eq}) qd={worst_qd:.3e} (env {eqd}, "
+          f"{errs[eqd][2]} compared steps) event mismatches={len(bad)} in-band ids={n_band}", flush=True)
     return worst_q, worst_qd
 
 

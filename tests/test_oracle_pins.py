@@ -425,10 +425,8 @@ def test_static_equilibrium_is_fixed_point_and_apples_do_not_load_it():
     # put the fruited tree there with every apple hanging m g / k_s below its hang point
     st = o_fruit.rest_state()
     st.q[:] = q.reshape(S, 2)
-    R, p = o_fruit.fk(0, q)
-    for a in range(t.n_apple):
-        b = t.apple_seg[a]
-        st.ax[a] = p[b] + R[b] @ t.apple_hang[a] + np.array([0, 0, -t.apple_mass[a] * G / 2e3])
+    for a in range(t.n_apple):  # apple state = stretch from the hang point while attached
+        st.ax[a] = np.array([0, 0, -t.apple_mass[a] * G / 2e3])
     x0 = st.ax.copy()
     o_fruit.rollout(st, 5)
     # the step leaves it in place: zero reaction at rest, rest pose unaffected by fruit
