@@ -15,6 +15,8 @@ stream) and the FP64 CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +43,26 @@ def algorithmic_bytes(batch) -> int:
     return SEG_BYTES * batch.n_seg + APPLE_BYTES * batch.n_apple
 
 
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("paper_2607_06337_amd/csrc/orchard_step.hip", "paper_2607_06337_amd/csrc/orchard_dev.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel,
+    or None if there is none for the current kernel source."""
+    cur = kernel_source_hash()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            if line.startswith("machine-readable: "):
+                rec = json.loads(line[len("machine-readable: "):])
+                if rec.get("kernel") == kernel and rec.get("src_hash") == cur:
+                    return rec["hbm_bytes_per_launch"]
+    return None
+
+
 def time_gpu(model, n_steps, warmup, reps=1):
     import torch
     st = model.rest_state()
@@ -65,7 +87,7 @@ def time_gpu(model, n_steps, warmup, reps=1):
     return best[0], best[1], int((status != 0).sum()), st
 
 
-def cpu_baseline(batch, consts, n_envs=48, n_steps=40):
+def cpu_baseline(batch, consts, n_envs=64, n_steps=1500):
     """FP64 oracle on a stratified sample of the same workload."""
     from oracle.oracle import Oracle
     from orchard_inputs import assemble
@@ -135,9 +157,11 @@ def main():
     per_launch_bytes = algorithmic_bytes(batch) * spl
     launch_ms = ms_step * spl
     achieved = per_launch_bytes / (launch_ms / 1e3) / 1e9
+    traffic = profiled_traffic("k_step_packs")
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel="k_step_packs", bytes_per_launch=per_launch_bytes)
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel="k_step_packs", bytes_per_launch=per_launch_bytes,
+                launch_us=round(launch_ms * 1e3, 2))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, consts)
