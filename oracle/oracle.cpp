@@ -692,3 +692,176 @@ int oracle_rollout(void* m, const OracleIO* io, int n_sel, const int32_t* env_li
 }
 
 }  // extern "C"
+
+// ======================================================================================
+// Adjoint (FP64, reverse mode by taping the step itself; discrete switches frozen)
+// ======================================================================================
+#include "tape.hpp"
+
+namespace orc {
+
+// per-step record: switches used plus the detached flags at entry
+struct StepRecord {
+  Switches sw;
+  std::vector<uint8_t> det0, broken0;
+};
+
+struct EnvRun {
+  const Tree& t;
+  const Globals& g;
+  int env;
+  int64_t step0;
+  int n_steps;
+};
+
+// Tip positions p_b + R_b (0, 0, l_b) of the listed segments.
+template <class T>
+void tips(const Tree& t, const T* q, int n_tips, const int32_t* seg, V3<T>* out) {
+  Kin<T> K;
+  fk(t, q, K);
+  for (int k = 0; k < n_tips; ++k) {
+    const int b = seg[k];
+    out[k] = K.p[b] + K.R[b] * V3<T>(T(0), T(0), T(t.len[b]));
+  }
+}
+
+// Forward rollout of one tree in double, recording every state and switch.
+static void forward_record(const EnvRun& r, const double* q0, const double* qd0, const double* ax0, const double* av0,
+                           const double* kp, const double* kd, const double* F, std::vector<std::vector<double>>& states,
+                           std::vector<StepRecord>* rec, const std::vector<StepRecord>* replay) {
+  const Tree& t = r.t;
+  const int S = t.S, A = t.A;
+  std::vector<double> q(q0, q0 + 2 * S), qd(qd0, qd0 + 2 * S), ax(ax0, ax0 + 3 * A), av(av0, av0 + 3 * A);
+  std::vector<double> aq(4 * A, 0.0), aw(3 * A, 0.0);
+  for (int a = 0; a < A; ++a) aq[4 * a] = 1.0;
+  std::vector<uint8_t> broken(S, 0), cnt(S, 0), det(A, 0), cntp(A, 0), cntt(A, 0), path(A, 0);
+  std::vector<int32_t> bstep(S, -1), dstep(A, -1);
+  uint32_t status = 0;
+  std::vector<double> qn(2 * S), qdn(2 * S), axn(3 * A), avn(3 * A), aqn(4 * A), awn(3 * A);
+  states.assign(r.n_steps + 1, {});
+  auto pack = [&](std::vector<double>& s) {
+    s.clear();
+    s.insert(s.end(), q.begin(), q.end()); s.insert(s.end(), qd.begin(), qd.end());
+    s.insert(s.end(), ax.begin(), ax.end()); s.insert(s.end(), av.begin(), av.end());
+  };
+  pack(states[0]);
+  if (rec) rec->assign(r.n_steps, {});
+  for (int s = 0; s < r.n_steps; ++s) {
+    if (rec) { (*rec)[s].det0 = det; (*rec)[s].broken0 = broken; }
+    Switches sw;
+    const Switches* rp = nullptr;
+    if (replay) { det = (*replay)[s].det0; broken = (*replay)[s].broken0; rp = &(*replay)[s].sw; }
+    EventRefs ev{broken.data(), cnt.data(), det.data(), cntp.data(), cntt.data(), path.data(), bstep.data(), dstep.data(), &status};
+    step_tree<double>(t, r.g, r.env, r.step0 + s, q.data(), qd.data(), ax.data(), av.data(), aq.data(), aw.data(), kp, kd,
+                      nullptr, F ? F + (int64_t)s * 3 * A : nullptr, qn.data(), qdn.data(), axn.data(), avn.data(),
+                      aqn.data(), awn.data(), &ev, nullptr, &sw, rp);
+    if (replay) { broken = rp->broken; det = rp->detached; }
+    if (rec) (*rec)[s].sw = sw;
+    q = qn; qd = qdn; ax = axn; av = avn; aq = aqn; aw = awn;
+    pack(states[s + 1]);
+  }
+}
+
+static double loss_of(const Tree& t, const double* q, int n_tips, const int32_t* seg, const double* target) {
+  std::vector<V3<double>> tp(n_tips);
+  tips(t, q, n_tips, seg, tp.data());
+  double L = 0;
+  for (int k = 0; k < n_tips; ++k)
+    for (int c = 0; c < 3; ++c) { const double d = tp[k][c] - target[3 * k + c]; L += d * d; }
+  return L;
+}
+
+}  // namespace orc
+
+extern "C" {
+
+// Opaque record of a forward run's switches (for replay in finite differences).
+void* oracle_record_new(void) { return new std::vector<StepRecord>(); }
+void oracle_record_free(void* r) { delete static_cast<std::vector<StepRecord>*>(r); }
+
+// Loss L = sum_k |tip_k(q_T) - target_k|^2 after n_steps from the given state (flags
+// zero at start).  If rec_in is non-null the switches are replayed from it; if rec_out
+// is non-null they are recorded there.  F: [n_steps][A][3] apple forces or null.
+double oracle_loss(void* m, int env, int64_t step0, int n_steps, const double* q0, const double* qd0,
+                   const double* ax0, const double* av0, const double* kp, const double* kd, const double* F,
+                   int n_tips, const int32_t* tip_seg, const double* target, void* rec_in, void* rec_out,
+                   double* q_final) {
+  Model* M = static_cast<Model*>(m);
+  const Tree& t = M->trees[env];
+  EnvRun r{t, M->g, env, step0, n_steps};
+  std::vector<std::vector<double>> states;
+  forward_record(r, q0, qd0, ax0, av0, kp, kd, F, states, static_cast<std::vector<StepRecord>*>(rec_out),
+                 static_cast<std::vector<StepRecord>*>(rec_in));
+  const std::vector<double>& last = states.back();
+  if (q_final) std::copy(last.begin(), last.begin() + 4 * t.S, q_final);
+  return loss_of(t, last.data(), n_tips, tip_seg, target);
+}
+
+// Gradient of the loss above with the forward's switches frozen.  Outputs (accumulated
+// into zero-initialised arrays): g_kp, g_kd [S], g_F [n_steps][A][3] (nullable),
+// g_state0 [4S + 6A] = (q, qd, apple position state, apple velocity) (nullable).
+double oracle_adjoint(void* m, int env, int64_t step0, int n_steps, const double* q0, const double* qd0,
+                      const double* ax0, const double* av0, const double* kp, const double* kd, const double* F,
+                      int n_tips, const int32_t* tip_seg, const double* target, double* g_kp, double* g_kd,
+                      double* g_F, double* g_state0) {
+  Model* M = static_cast<Model*>(m);
+  const Tree& t = M->trees[env];
+  const int S = t.S, A = t.A, NX = 4 * S + 6 * A;
+  EnvRun r{t, M->g, env, step0, n_steps};
+  std::vector<std::vector<double>> states;
+  std::vector<StepRecord> rec;
+  forward_record(r, q0, qd0, ax0, av0, kp, kd, F, states, &rec, nullptr);
+  Tape tp;
+  tape() = &tp;
+  // loss seed
+  std::vector<double> xbar(NX, 0.0);
+  double L;
+  {
+    std::vector<AD> q(2 * S);
+    for (int k = 0; k < 2 * S; ++k) q[k] = AD::var(states.back()[k]);
+    std::vector<V3<AD>> tips_ad(n_tips);
+    tips(t, q.data(), n_tips, tip_seg, tips_ad.data());
+    AD Ls(0.0);
+    for (int k = 0; k < n_tips; ++k)
+      for (int c = 0; c < 3; ++c) { AD d = tips_ad[k][c] - target[3 * k + c]; Ls = Ls + d * d; }
+    L = Ls.v;
+    tp.adj.assign(tp.nodes.size(), 0.0);
+    if (Ls.i >= 0) tp.adj[Ls.i] = 1.0;
+    tp.reverse();
+    for (int k = 0; k < 2 * S; ++k) xbar[k] = tp.adj[q[k].i];
+    tp.clear();
+  }
+  for (int s = n_steps - 1; s >= 0; --s) {
+    const std::vector<double>& x = states[s];
+    std::vector<AD> q(2 * S), qd(2 * S), ax(3 * A), av(3 * A), aq(4 * A), aw(3 * A, AD(0.0)), kpa(S), kda(S), Fa(F ? 3 * A : 0);
+    for (int k = 0; k < 2 * S; ++k) { q[k] = AD::var(x[k]); qd[k] = AD::var(x[2 * S + k]); }
+    for (int k = 0; k < 3 * A; ++k) { ax[k] = AD::var(x[4 * S + k]); av[k] = AD::var(x[4 * S + 3 * A + k]); }
+    for (int a = 0; a < A; ++a) { aq[4 * a] = AD(1.0); aq[4 * a + 1] = aq[4 * a + 2] = aq[4 * a + 3] = AD(0.0); }
+    for (int i = 0; i < S; ++i) { kpa[i] = AD::var(kp[i]); kda[i] = AD::var(kd[i]); }
+    for (int k = 0; k < (int)Fa.size(); ++k) Fa[k] = AD::var(F[(int64_t)s * 3 * A + k]);
+    std::vector<AD> qn(2 * S), qdn(2 * S), axn(3 * A), avn(3 * A), aqn(4 * A), awn(3 * A);
+    std::vector<uint8_t> broken = rec[s].broken0, cnt(S, 0), det = rec[s].det0, cntp(A, 0), cntt(A, 0), path(A, 0);
+    std::vector<int32_t> bstep(S, -1), dstep(A, -1);
+    uint32_t status = 0;
+    EventRefs ev{broken.data(), cnt.data(), det.data(), cntp.data(), cntt.data(), path.data(), bstep.data(), dstep.data(), &status};
+    step_tree<AD>(t, M->g, env, step0 + s, q.data(), qd.data(), ax.data(), av.data(), aq.data(), aw.data(), kpa.data(),
+                  kda.data(), nullptr, F ? Fa.data() : nullptr, qn.data(), qdn.data(), axn.data(), avn.data(), aqn.data(),
+                  awn.data(), &ev, nullptr, nullptr, &rec[s].sw);
+    tp.adj.assign(tp.nodes.size(), 0.0);
+    auto seed = [&](const AD& o, double g) { if (o.i >= 0) tp.adj[o.i] += g; };
+    for (int k = 0; k < 2 * S; ++k) { seed(qn[k], xbar[k]); seed(qdn[k], xbar[2 * S + k]); }
+    for (int k = 0; k < 3 * A; ++k) { seed(axn[k], xbar[4 * S + k]); seed(avn[k], xbar[4 * S + 3 * A + k]); }
+    tp.reverse();
+    auto get = [&](const AD& v) { return v.i >= 0 ? tp.adj[v.i] : 0.0; };
+    for (int k = 0; k < 2 * S; ++k) { xbar[k] = get(q[k]); xbar[2 * S + k] = get(qd[k]); }
+    for (int k = 0; k < 3 * A; ++k) { xbar[4 * S + k] = get(ax[k]); xbar[4 * S + 3 * A + k] = get(av[k]); }
+    for (int i = 0; i < S; ++i) { g_kp[i] += get(kpa[i]); g_kd[i] += get(kda[i]); }
+    if (F && g_F) for (int k = 0; k < 3 * A; ++k) g_F[(int64_t)s * 3 * A + k] += get(Fa[k]);
+    tp.clear();
+  }
+  tape() = nullptr;
+  if (g_state0) for (int k = 0; k < NX; ++k) g_state0[k] += xbar[k];
+  return L;
+}
+
+}  // extern "C"

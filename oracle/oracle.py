@@ -273,3 +273,80 @@ def rng_u24(seed, env, step, seg, k) -> int:
 
 def splitmix64(x: int) -> int:
     return int(lib().oracle_splitmix64(x))
+
+
+# ---- adjoint (FP64, taped step, switches frozen) ------------------------------------------
+def _setup_adjoint(L):
+    if getattr(L, "_adj_ready", False):
+        return
+    L.oracle_record_new.restype = C.c_void_p
+    L.oracle_record_free.argtypes = [C.c_void_p]
+    L.oracle_loss.restype = C.c_double
+    L.oracle_loss.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int] + [_P] * 7 + [C.c_int, _P, _P, C.c_void_p,
+                                                                                   C.c_void_p, _P]
+    L.oracle_adjoint.restype = C.c_double
+    L.oracle_adjoint.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int] + [_P] * 7 + [C.c_int, _P, _P] + [_P] * 4
+    L._adj_ready = True
+
+
+class Record:
+    """Switch schedule of a forward run (replayed by finite differences)."""
+
+    def __init__(self):
+        L = lib()
+        _setup_adjoint(L)
+        self.h = L.oracle_record_new()
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.oracle_record_free(self.h)
+            self.h = None
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _adj_args(o, env, x0, kp, kd, F, tips, target):
+    b = o.batch
+    S = int(b.seg_offset[env + 1] - b.seg_offset[env])
+    A = int(b.apple_offset[env + 1] - b.apple_offset[env])
+    q0, qd0, ax0, av0 = (_f64(x0[k]) for k in ("q", "qd", "ax", "av"))
+    assert q0.size == 2 * S and ax0.size == 3 * A
+    tips = np.ascontiguousarray(tips, dtype=np.int32)
+    target = _f64(target).reshape(-1, 3)
+    return S, A, q0, qd0, ax0, av0, _f64(kp), _f64(kd), _f64(F), tips, target
+
+
+def env_state0(o, st, env):
+    """Initial-state dict of one env from a batch State (descriptor order)."""
+    b = o.batch
+    s0, s1 = b.seg_offset[env], b.seg_offset[env + 1]
+    a0, a1 = b.apple_offset[env], b.apple_offset[env + 1]
+    return dict(q=st.q[s0:s1], qd=st.qd[s0:s1], ax=st.ax[a0:a1], av=st.av[a0:a1])
+
+
+def loss(o, env, x0, kp, kd, F, n_steps, tips, target, step0=0, record_in=None, record_out=None, return_q=False):
+    L = lib()
+    _setup_adjoint(L)
+    S, A, q0, qd0, ax0, av0, kp, kd, F, tips, target = _adj_args(o, env, x0, kp, kd, F, tips, target)
+    qf = np.zeros(4 * S) if return_q else None
+    v = L.oracle_loss(o.h, env, step0, n_steps, _ptr(q0), _ptr(qd0), _ptr(ax0), _ptr(av0), _ptr(kp), _ptr(kd), _ptr(F),
+                      len(tips), _ptr(tips), _ptr(target), record_in.h if record_in else None,
+                      record_out.h if record_out else None, _ptr(qf))
+    return (v, qf) if return_q else v
+
+
+def adjoint(o, env, x0, kp, kd, F, n_steps, tips, target, step0=0):
+    """Returns (L, dL/dkp, dL/dkd, dL/dF [n_steps, A, 3] or None, dL/dx0 dict)."""
+    L = lib()
+    _setup_adjoint(L)
+    S, A, q0, qd0, ax0, av0, kp, kd, F, tips, target = _adj_args(o, env, x0, kp, kd, F, tips, target)
+    gkp, gkd = np.zeros(S), np.zeros(S)
+    gF = np.zeros((n_steps, A, 3)) if F is not None else None
+    gx = np.zeros(4 * S + 6 * A)
+    v = L.oracle_adjoint(o.h, env, step0, n_steps, _ptr(q0), _ptr(qd0), _ptr(ax0), _ptr(av0), _ptr(kp), _ptr(kd),
+                         _ptr(F), len(tips), _ptr(tips), _ptr(target), _ptr(gkp), _ptr(gkd), _ptr(gF), _ptr(gx))
+    g0 = dict(q=gx[:2 * S].reshape(S, 2), qd=gx[2 * S:4 * S].reshape(S, 2), ax=gx[4 * S:4 * S + 3 * A].reshape(A, 3),
+              av=gx[4 * S + 3 * A:].reshape(A, 3))
+    return v, gkp, gkd, gF, g0
