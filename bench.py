@@ -106,6 +106,40 @@ def cpu_baseline(batch, consts, n_envs=64, n_steps=1500):
                        f"{n_steps} steps, FP64, {dt:.1f} s")
 
 
+def adjoint_ratio(reps: int = 3):
+    """Adjoint/forward cost ratio on the differentiable-rollout workload: 512 trees of 300
+    segments and 40 apples, 200 steps with checkpoints every 20, per-step apple forces;
+    backward = recompute of every checkpoint segment + adjoint kernels."""
+    import torch
+    from orchard_inputs import grad_apple_forces, make_batch, step_constants
+    from paper_2607_06337_amd import Model
+    T, K = 200, 20
+    batch = make_batch("grad512")
+    m = Model(batch, step_constants(), dict(BENCH_TUNING, adjoint_ckpt_max=K))
+    kp, kd = m.default_params()
+    F = torch.tensor(m.apple_from_desc(grad_apple_forces(batch, T).astype(np.float32), axis=1), device="cuda").contiguous()
+    ck = torch.empty(-(-T // K) * m.ckpt_words, device="cuda")
+    fw, bw = [], []
+    for _ in range(reps + 1):
+        st = m.rest_state()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        adj = dict(q=torch.randn(m.n_seg, 2, device="cuda"), qd=torch.zeros(m.n_seg, 2, device="cuda"),
+                   ax=torch.zeros(3, m.n_apple, device="cuda"), av=torch.zeros(3, m.n_apple, device="cuda"))
+        gkp, gkd, gF = torch.zeros_like(kp), torch.zeros_like(kd), torch.zeros_like(F)
+        torch.cuda.synchronize()
+        e0.record()
+        m.step(st, kp, kd, T, aforce=F, ckpt=ck, ckpt_every=K)
+        e1.record()
+        m.step_backward(ck, K, T, kp, kd, adj, gkp, gkd, gF, aforce=F)
+        e2.record()
+        torch.cuda.synchronize()
+        fw.append(e0.elapsed_time(e1))
+        bw.append(e1.elapsed_time(e2))
+    fw, bw = np.median(fw[1:]), np.median(bw[1:])
+    return dict(ratio=round(bw / fw, 3), forward_ms=round(fw, 2), backward_ms=round(bw, 2),
+                workload="grad512: 512 trees x 300 segments x 40 apples, 200 steps, checkpoints every 20")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +147,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB read + 256 MiB write kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -162,6 +197,10 @@ def main():
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel="k_step_packs", bytes_per_launch=per_launch_bytes,
                 launch_us=round(launch_ms * 1e3, 2))
+    adj = None
+    if not args.no_adjoint:
+        adj = adjoint_ratio()
+        print(f"# adjoint/forward: {adj}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, consts)
@@ -173,7 +212,7 @@ def main():
                config=dict(workload=f"{WORKLOAD}: 8192 seeded L-system trees, log-uniform 50-1500 segments, "
                                     f"10-120 apples, in-step random body forces 5% N(0,5N), dt 1 ms",
                            n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=BENCH_TUNING),
-               adjoint_forward_ratio=None, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
+               adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
                roofline=roof, cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 

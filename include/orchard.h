@@ -94,6 +94,8 @@ typedef struct {
   float pack_fill;
   int32_t steps_per_launch;     /* steps fused in one launch by orchard_step (>= 1)   */
   int32_t persistent;           /* 1: persistent grid pulling packs from a queue      */
+  int32_t adjoint_ckpt_max;     /* > 0: allocate recompute buffers for                */
+                                /*   orchard_step_backward with ckpt_every up to this */
 } orchard_tuning_t;
 
 typedef struct {
@@ -178,6 +180,43 @@ orchard_status_t orchard_state_rest(orchard_model_t model, const orchard_state_t
 orchard_status_t orchard_step(orchard_model_t model, const orchard_state_t* state, const orchard_params_t* params,
                               const orchard_inputs_t* inputs, int32_t n_steps, float* ckpt, int32_t ckpt_every,
                               orchard_stream_t stream);
+
+/* Adjoint state (caller-owned device arrays, internal order): dL/dq, dL/dqd
+ * [n_seg][2] and dL/d(apple position state), dL/d(apple velocity) [3][n_apple]. */
+typedef struct {
+  float* q;
+  float* qd;
+  float* apple_x;
+  float* apple_v;
+} orchard_adjoint_t;
+
+/* Reverse-mode gradient of a rollout (growth direction "differentiation"):
+ * given the checkpoints a forward orchard_step call wrote (ckpt, ckpt_every <=
+ * tuning.adjoint_ckpt_max) and, in adj, dL/dS_T of the state after its n_steps
+ * steps, recompute each checkpoint segment and walk the steps backwards: per step
+ * lambda = Mt^-1 (h dL/dqd+) with the step's own factorisation (Mt is symmetric),
+ * then the reverse of the inverse dynamics, kinematics, apple tether and reaction
+ * and of the implicit-Euler update, with every discrete switch of the forward
+ * (breaks, detachments, clamp branch, impulse cap, snapped mask) frozen.
+ * On return adj holds dL/dS_0 (in place).  Accumulates (+=) into grad_kp, grad_kd
+ * [n_seg] and, if non-NULL, grad_apple_force [n_steps][n_apple][3].  Params and
+ * inputs must be those of the forward call.  The quaternion and angular velocity of
+ * the apples are not differentiated, nor is a detached apple's position w.r.t. the
+ * tree pose at the detach step.  Stream-ordered; no allocation. */
+orchard_status_t orchard_step_backward(orchard_model_t model, const float* ckpt, int32_t ckpt_every, int32_t n_steps,
+                                       const orchard_params_t* params, const orchard_inputs_t* inputs,
+                                       const orchard_adjoint_t* adj, float* grad_kp, float* grad_kd,
+                                       float* grad_apple_force, orchard_stream_t stream);
+
+/* Tip positions p_b + R_b (0, 0, l_b) (world frame, tree base at the origin) of the
+ * segments node[k] (internal indices, device int32 [n_tips]) at joint angles q
+ * (device [n_seg][2]) into out (device float [n_tips][3]).  Stream-ordered. */
+orchard_status_t orchard_tips(orchard_model_t model, const float* q, int32_t n_tips, const int32_t* node, float* out,
+                              orchard_stream_t stream);
+
+/* Accumulates (+=) into grad_q ([n_seg][2]) the gradient of sum_k grad_out[k] . tip_k(q). */
+orchard_status_t orchard_tips_backward(orchard_model_t model, const float* q, int32_t n_tips, const int32_t* node,
+                                       const float* grad_out, float* grad_q, orchard_stream_t stream);
 
 /* Size in 32-bit words of one checkpoint record written by orchard_step. */
 int64_t orchard_ckpt_words(orchard_model_t model);

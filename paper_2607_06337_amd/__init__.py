@@ -6,5 +6,7 @@ The native library (liborchard.so, HIP for gfx950) is loaded lazily by
 from .orchard import (EVENT_BREAK, EVENT_DETACH_PULL, EVENT_DETACH_TENSION, EXPORTS, Model, OrchardError, State,
                       load_library)
 
-__all__ = ["Model", "State", "load_library", "OrchardError", "EXPORTS", "EVENT_BREAK", "EVENT_DETACH_PULL",
+from .autograd import rollout, tips
+
+__all__ = ["rollout", "tips", "Model", "State", "load_library", "OrchardError", "EXPORTS", "EVENT_BREAK", "EVENT_DETACH_PULL",
            "EVENT_DETACH_TENSION"]

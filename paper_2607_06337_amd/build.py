@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liborchard.so")
-SOURCES = ["orchard_api.hip", "orchard_step.hip"]
+SOURCES = ["orchard_api.hip", "orchard_step.hip", "orchard_adjoint.hip"]
 # packed FP32 instructions are kept out of every kernel (-packed-fp32-ops)
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

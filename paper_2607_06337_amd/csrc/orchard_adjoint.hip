@@ -1,0 +1,434 @@
+// Adjoint of one step (switches frozen) and tip positions.
+//
+// The step solves r(qdd; q, qd, s, kp, kd) = Mt(q) qdd + c(q, qd, s) + Kp(q + h qd) + Kd qd = 0.
+// Given the adjoint of the state after the step, with qdd_bar = h (qd_bar' + h q_bar'):
+//   lambda = Mt^-1 qdd_bar  (same factorisation as the forward: Mt is symmetric),
+//   theta_bar -= (dr/dtheta)^T lambda  for theta in {q, qd, apple stretch, kp, kd},
+// and lambda^T r is evaluated as sum_i nu_i . f_i^B + spring terms, where nu (the
+// acceleration field of the lambda solve) is the virtual velocity of every body.  The
+// reverse pass walks leaf -> root accumulating the adjoints of the down-pass quantities
+// of the forward step; rotation adjoints travel as 3-vectors (for R = [dphi] R
+// perturbations), so every DoF's derivative is its axis dotted with that vector.
+#include "orchard_dev.h"
+
+namespace orchard {
+
+__device__ __forceinline__ float aldf(const DevModel& M, int f, int i) { return M.scr[(size_t)f * M.n_seg + i]; }
+__device__ __forceinline__ void asto(const DevModel& M, int f, int i, float v) { M.scr[(size_t)f * M.n_seg + i] = v; }
+__device__ __forceinline__ V3 ald3(const DevModel& M, int f, int i) { return v3(aldf(M, f, i), aldf(M, f + 1, i), aldf(M, f + 2, i)); }
+__device__ __forceinline__ void asto3(const DevModel& M, int f, int i, V3 v) { asto(M, f, i, v.x); asto(M, f + 1, i, v.y); asto(M, f + 2, i, v.z); }
+
+struct DevAdj {
+  float2* q;        // [n_seg] adjoint of q (in: after the step, out: before)
+  float2* qd;       // [n_seg]
+  float* ax;        // [3][n_apple] adjoint of the apple position state
+  float* av;        // [3][n_apple] adjoint of the apple velocity
+  float* gkp;       // [n_seg] accumulated
+  float* gkd;       // [n_seg] accumulated
+  float* gF;        // [n_steps][n_apple][3] or null (this step's slice is gF + s_call * 3 * n_apple)
+};
+
+// record words: q (2S) qd (2S) apple (13A) seg_evt (S) apple_evt (A) ...
+struct RecView {
+  const float* w;
+  int NS, NA;
+  __device__ float2 q(int i) const { return make_float2(w[2 * i], w[2 * i + 1]); }
+  __device__ float2 qd(int i) const { return make_float2(w[2 * NS + 2 * i], w[2 * NS + 2 * i + 1]); }
+  __device__ float apple(int plane, int a) const { return w[4 * NS + plane * NA + a]; }
+  __device__ uint32_t apple_evt(int a) const { return __float_as_uint(w[4 * NS + 13 * NA + NS + a]); }
+};
+
+// ---- lambda solve, up pass: forward substitution with the stored factor ------------------
+__device__ void node_lam_up(const DevModel& M, const DevAdj& X, int i) {
+  if (aldf(M, F_SKIP, i) != 0.f) return;
+  V3 pn = v3(0, 0, 0), pf = v3(0, 0, 0);
+  const int cb = M.child[i], ce = cb + M.nchild[i];
+  for (int c = cb; c < ce; ++c) { pn = pn + ald3(M, F_LPA, c); pf = pf + ald3(M, F_LPA + 3, c); }
+  const V3 lz = ald3(M, F_LZ, i);
+  pn = pn + cross(lz, pf);
+  const float h = M.h;
+  const float2 qb = X.q[i], qdb = X.qd[i];
+  const float b0 = h * fmaf(h, qb.x, qdb.x), b1 = h * fmaf(h, qb.y, qdb.y);  // qdd_bar
+  const V3 a0 = ald3(M, F_A0, i), a1 = ald3(M, F_A1, i);
+  const float u0 = b0 - dot(a0, pn), u1 = b1 - dot(a1, pn);
+  const V3 U0a = ald3(M, F_U, i), U0l = ald3(M, F_U + 3, i), U1a = ald3(M, F_U + 6, i), U1l = ald3(M, F_U + 9, i);
+  const float Di00 = aldf(M, F_DI, i), Di01 = aldf(M, F_DI + 1, i), Di11 = aldf(M, F_DI + 2, i);
+  const float w0 = fmaf(Di00, u0, Di01 * u1), w1 = fmaf(Di01, u0, Di11 * u1);
+  pn = fma3(w0, U0a, fma3(w1, U1a, pn));
+  pf = fma3(w0, U0l, fma3(w1, U1l, pf));
+  asto(M, F_LU, i, u0); asto(M, F_LU + 1, i, u1);
+  asto3(M, F_LPA, i, pn); asto3(M, F_LPA + 3, i, pf);
+}
+
+// ---- lambda solve, down pass: back substitution; the field is the virtual velocity nu --
+__device__ void node_lam_down(const DevModel& M, int i) {
+  if (aldf(M, F_SKIP, i) != 0.f) return;
+  const int par = M.par[i];
+  V3 aa = v3(0, 0, 0), al = v3(0, 0, 0);
+  if (par >= 0) { aa = ald3(M, F_LA, par); al = ald3(M, F_LA + 3, par); }
+  const V3 U0a = ald3(M, F_U, i), U0l = ald3(M, F_U + 3, i), U1a = ald3(M, F_U + 6, i), U1l = ald3(M, F_U + 9, i);
+  const float t0 = aldf(M, F_LU, i) - (dot(U0a, aa) + dot(U0l, al));
+  const float t1 = aldf(M, F_LU + 1, i) - (dot(U1a, aa) + dot(U1l, al));
+  const float Di00 = aldf(M, F_DI, i), Di01 = aldf(M, F_DI + 1, i), Di11 = aldf(M, F_DI + 2, i);
+  const float l0 = fmaf(Di00, t0, Di01 * t1), l1 = fmaf(Di01, t0, Di11 * t1);
+  aa = fma3(l0, ald3(M, F_A0, i), fma3(l1, ald3(M, F_A1, i), aa));
+  asto3(M, F_NU, i, aa); asto3(M, F_NU + 3, i, al);
+  asto(M, F_LAM, i, l0); asto(M, F_LAM + 1, i, l1);
+  const V3 lz = ald3(M, F_LZ, i);
+  asto3(M, F_LA, i, aa); asto3(M, F_LA + 3, i, al + cross(aa, lz));
+}
+
+// ---- reverse pass (leaf -> root) ---------------------------------------------------------
+__device__ void node_reverse(const DevModel& M, const DevState& W, const RecView& R0, const DevInputs& I,
+                             const DevAdj& X, int i, int64_t n, int s_call) {
+  if (aldf(M, F_SKIP, i) != 0.f) return;  // frozen env: the step is the identity
+  const float h = M.h;
+  const int par = M.par[i];
+  // forward quantities of this node
+  V3 c0, c1, c2;
+  c0 = v3(aldf(M, F_SR + 0, i), aldf(M, F_SR + 3, i), aldf(M, F_SR + 6, i));
+  c1 = v3(aldf(M, F_SR + 1, i), aldf(M, F_SR + 4, i), aldf(M, F_SR + 7, i));
+  c2 = v3(aldf(M, F_SR + 2, i), aldf(M, F_SR + 5, i), aldf(M, F_SR + 8, i));
+  const V3 a0 = ald3(M, F_A0, i), a1 = c1, z = c2;
+  const V3 lz = ald3(M, F_LZ, i);
+  const V3 om = ald3(M, F_W, i);
+  const V3 v = par >= 0 ? ald3(M, F_VT, par) : v3(0, 0, 0);
+  const V3 Aa = ald3(M, F_SA, i), Al = ald3(M, F_SA + 3, i);
+  const V3 Pa = ald3(M, F_SAVP, i), Pl = ald3(M, F_SAVP + 3, i);
+  const float qdd0 = aldf(M, F_SQDD, i), qdd1 = aldf(M, F_SQDD + 1, i);
+  const float l0 = aldf(M, F_LAM, i), l1 = aldf(M, F_LAM + 1, i);
+  const V3 na = ald3(M, F_NU, i), nl = ald3(M, F_NU + 3, i);
+  // transmitted force f = I^A A + p^A (before the pivot update)
+  Sym3 IA{aldf(M, F_SIA + 0, i), aldf(M, F_SIA + 1, i), aldf(M, F_SIA + 2, i), aldf(M, F_SIA + 3, i),
+          aldf(M, F_SIA + 4, i), aldf(M, F_SIA + 5, i)};
+  Mat3 IB;
+  for (int k = 0; k < 9; ++k) IB.m[k] = aldf(M, F_SIA + 6 + k, i);
+  Sym3 IM{aldf(M, F_SIA + 15, i), aldf(M, F_SIA + 16, i), aldf(M, F_SIA + 17, i), aldf(M, F_SIA + 18, i),
+          aldf(M, F_SIA + 19, i), aldf(M, F_SIA + 20, i)};
+  const V3 fn = mul(IA, Aa) + mul(IB, Al) + ald3(M, F_SPA, i);
+  const V3 ff = mulT(IB, Aa) + mul(IM, Al) + ald3(M, F_SPA + 3, i);
+  const float2 q = R0.q(i), qd = R0.qd(i);
+  const V3 u = fma3(qd.x, a0, qd.y * a1);
+  const float4 g4 = M.geo[i];
+  const float l = g4.x, m = g4.y, Jt = g4.z, Iax = g4.w, dJ = Iax - Jt;
+  const V3 ho = (0.5f * m * l) * z;
+  const Sym3 Jo{fmaf(dJ, z.x * z.x, Jt), fmaf(dJ, z.y * z.y, Jt), fmaf(dJ, z.z * z.z, Jt), dJ * z.x * z.y, dJ * z.x * z.z,
+                dJ * z.y * z.z};
+  const uint8_t brk = W.seg_evt[i];
+  const float kp = I.kp[i], kd = I.kd[i];
+  const float kpe = brk ? 0.f : kp, kde = brk ? 0.f : kd;
+
+  // accumulators
+  V3 Aba = v3(0, 0, 0), Abl = v3(0, 0, 0), Pba = v3(0, 0, 0), Pbl = v3(0, 0, 0);
+  V3 omb = v3(0, 0, 0), vb = v3(0, 0, 0), zb = v3(0, 0, 0), a0b = v3(0, 0, 0), a1b = v3(0, 0, 0), lzb = v3(0, 0, 0);
+  V3 tau = v3(0, 0, 0);  // rotation adjoint of this body (R -> [dphi] R)
+  float qdb0 = 0.f, qdb1 = 0.f;
+  // ---- gather the children ----
+  V3 vtb = v3(0, 0, 0), Atba = v3(0, 0, 0), Atbl = v3(0, 0, 0), Avtba = v3(0, 0, 0), Avtbl = v3(0, 0, 0), Fch = v3(0, 0, 0);
+  const int cb = M.child[i], ce = cb + M.nchild[i];
+  for (int c = cb; c < ce; ++c) {
+    tau = tau + ald3(M, F_RB + 0, c);
+    omb = omb + ald3(M, F_RB + 3, c);
+    vtb = vtb + ald3(M, F_RB + 6, c);
+    Atba = Atba + ald3(M, F_RB + 9, c);
+    Atbl = Atbl + ald3(M, F_RB + 12, c);
+    Avtba = Avtba + ald3(M, F_RB + 15, c);
+    Avtbl = Avtbl + ald3(M, F_RB + 18, c);
+    Fch = Fch + ald3(M, F_RB + 21, c);
+  }
+  // tip publications: At = (A_ang, A_lin + A_ang x lz), same for Avp; vt = v + om x lz
+  Aba = Aba + Atba + cross(lz, Atbl);
+  Abl = Abl + Atbl;
+  lzb = lzb + cross(Atbl, Aa);
+  Pba = Pba + Avtba + cross(lz, Avtbl);
+  Pbl = Pbl + Avtbl;
+  lzb = lzb + cross(Avtbl, Pa);
+  vb = vb + vtb;
+  omb = omb + cross(lz, vtb);
+  lzb = lzb + cross(vtb, om);
+  // children's transmitted force moved from the tip: n += lz x F_children
+  lzb = lzb + cross(Fch, na);
+  // joint torques tau_k = a_k . n
+  a0b = fma3(l0, fn, a0b);
+  a1b = fma3(l1, fn, a1b);
+
+  // ---- body force, seed nu: rigid body part I A + V x* I V ----
+  Aba = Aba + mul(Jo, na) + cross(ho, nl);
+  Abl = Abl + m * nl + cross(na, ho);
+  V3 hb = cross(Al, na) - cross(Aa, nl);
+  zb = zb + dJ * (dot(na, z) * Aa + dot(Aa, z) * na);
+  {
+    const V3 K = mul(Jo, om) + cross(ho, v);
+    const V3 L = m * v - cross(ho, om);
+    const V3 Kb = cross(na, om);
+    const V3 Lb = cross(na, v) + cross(nl, om);
+    omb = omb + cross(K, na) + cross(L, nl);
+    vb = vb + cross(L, na);
+    omb = omb + mul(Jo, Kb);
+    hb = hb + cross(v, Kb);
+    vb = vb + cross(Kb, ho);
+    zb = zb + dJ * (dot(Kb, z) * om + dot(om, z) * Kb);
+    vb = vb + m * Lb;
+    hb = hb - cross(om, Lb);
+    omb = omb - cross(Lb, ho);
+  }
+  // applied force: moment arm (l/2) z
+  {
+    V3 F, T;
+    const bool snp = aldf(M, F_SNAP, i) != 0.f;
+    if (applied_force(M, I, i, M.env[i], n, s_call, m, snp, F, T)) zb = zb - (0.5f * l) * cross(F, na);
+  }
+  zb = fma3(0.5f * m * l, hb, zb);
+
+  // ---- apples on this segment ----
+  const int NA = M.n_apple;
+  const V3 gv = v3(M.gx, M.gy, M.gz);
+  const V3 dAa = Aa - Pa, dAl = Al - Pl;
+  float* gF = X.gF ? X.gF + (int64_t)s_call * 3 * NA : nullptr;
+  for (int a = M.apple_beg[i]; a < M.apple_beg[i + 1]; ++a) {
+    const float4 hm = M.ahang[a];
+    const float4 ap = M.apar[a];
+    const float ma = hm.w, cs = ap.y, fmax = ap.z;
+    const V3 hl = v3(hm.x, hm.y, hm.z);
+    const V3 d = fma3(hl.x, c0, fma3(hl.y, c1, hl.z * c2));
+    const V3 vh = v + cross(om, d);
+    const V3 sig = v3(R0.apple(0, a), R0.apple(1, a), R0.apple(2, a));
+    const uint8_t det0 = (uint8_t)(R0.apple_evt(a) & 255u);
+    const uint8_t det = W.apple_evt[a];
+    const V3 xb = v3(X.ax[a], X.ax[NA + a], X.ax[2 * NA + a]);
+    const V3 vbn = v3(X.av[a], X.av[NA + a], X.av[2 * NA + a]);
+    const V3 vtot = fma3(h, xb, vbn);
+    // Two flows meet here: the apple's own update (direct adjoint) and its reaction on
+    // the spur, which enters the step residual r (adjoint -(dr/dx)^T lambda).  The
+    // tree-side accumulators hold d(lambda^T r)/dx, so direct terms enter them negated.
+    V3 sigb, vab, Fb, db = v3(0, 0, 0), vhb = v3(0, 0, 0);
+    if (!det) {
+      const V3 s = fma3(-h, vh, sig);
+      const V3 fab = (h / ma) * vtot;
+      const V3 sd = xb - M.ks * fab;  // direct adjoint of the stretch
+      vab = vtot - cs * fab;
+      Fb = fab;
+      // residual part: lambda^T r contains (mv w - fhat) . nu_pt, nu_pt = nu_lin + nu_ang x d
+      const V3 nup = nl + cross(na, d);
+      const V3 fe = M.ks * fma3(-h, vh, s) - ma * gv;
+      const float nf = sqrtf(dot(fe, fe));
+      const bool clamped = nf > fmax;
+      const float sc = clamped ? fmax / nf : 1.f;
+      const V3 fhat = sc * fe;
+      const float mv = sc * h * h * M.ks;
+      const V3 w = dAl + cross(dAa, d);
+      db = db + cross(mv * w - fhat, na);
+      const V3 wb = mv * nup;
+      Aba = Aba + cross(d, wb);
+      Abl = Abl + wb;
+      Pba = Pba - cross(d, wb);
+      Pbl = Pbl - wb;
+      db = db + cross(wb, dAa);
+      const float scb = h * h * M.ks * dot(w, nup) - dot(nup, fe);
+      V3 feb = (-sc) * nup;
+      if (clamped) feb = feb - (fmax / (nf * nf * nf) * scb) * fe;
+      const V3 gs = M.ks * feb;                 // d(lambda^T r)/ds
+      sigb = sd - gs;                           // s = sigma - h vh
+      vhb = (-2.f * h * M.ks) * feb + h * sd;   // d(lambda^T r)/dvh minus the direct part
+    } else {
+      // ballistic: x' = x + h v', v' = v + (h/m)(m g + F); the hang point's motion at
+      // the detach step is not propagated into the tree
+      vab = vtot;
+      Fb = (h / ma) * vtot;
+      sigb = xb;
+      if (!det0) vhb = h * xb;
+    }
+    vb = vb + vhb;
+    omb = omb + cross(d, vhb);
+    db = db + cross(vhb, om);
+    tau = tau + cross(d, db);
+    X.ax[a] = sigb.x; X.ax[NA + a] = sigb.y; X.ax[2 * NA + a] = sigb.z;
+    X.av[a] = vab.x; X.av[NA + a] = vab.y; X.av[2 * NA + a] = vab.z;
+    if (gF) { gF[3 * a] += Fb.x; gF[3 * a + 1] += Fb.y; gF[3 * a + 2] += Fb.z; }
+  }
+
+  // ---- c, A, Avp, omega, v recursions ----
+  const V3 cba = Aba + Pba, cbl = Abl + Pbl;
+  a0b = fma3(qdd0, Aba, a0b);
+  a1b = fma3(qdd1, Aba, a1b);
+  omb = omb + cross(u, cba);
+  V3 ub = cross(cba, om);
+  const float pq = qd.x * qd.y;
+  a0b = fma3(pq, cross(a1, cba), a0b);
+  a1b = fma3(pq, cross(cba, a0), a1b);
+  const float ca = dot(cross(a0, a1), cba);
+  qdb0 = fmaf(qd.y, ca, qdb0);
+  qdb1 = fmaf(qd.x, ca, qdb1);
+  vb = vb + cross(u, cbl);
+  ub = ub + cross(cbl, v);
+  ub = ub + omb;  // omega = omega_parent + u
+  a0b = fma3(qd.x, ub, a0b);
+  a1b = fma3(qd.y, ub, a1b);
+  qdb0 += dot(a0, ub);
+  qdb1 += dot(a1, ub);
+  zb = fma3(l, lzb, zb);
+
+  // ---- rotation: a1 = R e_y and z = R e_z are fixed in the body; a0 in the parent ----
+  tau = tau + cross(a1, a1b) + cross(z, zb);
+  float qb0 = dot(a0, tau), qb1 = dot(a1, tau);
+  const V3 tau_par = tau + cross(a0, a0b);
+
+  // ---- springs, dampers, implicit diagonal; parameter gradients ----
+  const float h2 = h * h;
+  if (!brk) {
+    X.gkp[i] -= l0 * (h2 * qdd0 + q.x + h * qd.x) + l1 * (h2 * qdd1 + q.y + h * qd.y);
+    X.gkd[i] -= l0 * (h * qdd0 + qd.x) + l1 * (h * qdd1 + qd.y);
+  }
+  qb0 = fmaf(kpe, l0, qb0);
+  qb1 = fmaf(kpe, l1, qb1);
+  qdb0 = fmaf(h * kpe + kde, l0, qdb0);
+  qdb1 = fmaf(h * kpe + kde, l1, qdb1);
+
+  // ---- state adjoint before the step ----
+  const float2 qbn = X.q[i], qdbn = X.qd[i];
+  const float qdp0 = fmaf(h, qbn.x, qdbn.x), qdp1 = fmaf(h, qbn.y, qdbn.y);
+  X.q[i] = make_float2(qbn.x - qb0, qbn.y - qb1);
+  X.qd[i] = make_float2(qdp0 - qdb0, qdp1 - qdb1);
+
+  // ---- publish for the parent ----
+  asto3(M, F_RB + 0, i, tau_par);
+  asto3(M, F_RB + 3, i, omb);
+  asto3(M, F_RB + 6, i, vb);
+  asto3(M, F_RB + 9, i, Aba);
+  asto3(M, F_RB + 12, i, Abl);
+  asto3(M, F_RB + 15, i, Pba);
+  asto3(M, F_RB + 18, i, Pbl);
+  asto3(M, F_RB + 21, i, ff);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_adjoint_packs(DevModel M, DevState W, const float* rec, DevInputs I, DevAdj X,
+                                                      int s_call) {
+  const int pk = blockIdx.x;
+  const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
+  const int64_t n = *W.step - 1;  // the forward step just taken on W
+  const RecView R0{rec, M.n_seg, M.n_apple};
+  for (int lv = le - 1; lv >= lb; --lv) {
+    const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
+    for (int i = a + (int)threadIdx.x; i < b; i += NT) node_lam_up(M, X, i);
+    __syncthreads();
+  }
+  for (int lv = lb; lv < le; ++lv) {
+    const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
+    for (int i = a + (int)threadIdx.x; i < b; i += NT) node_lam_down(M, i);
+    __syncthreads();
+  }
+  for (int lv = le - 1; lv >= lb; --lv) {
+    const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
+    for (int i = a + (int)threadIdx.x; i < b; i += NT) node_reverse(M, W, R0, I, X, i, n, s_call);
+    __syncthreads();
+  }
+}
+
+// ---- tip positions: p_b + R_b (0, 0, l_b) -----------------------------------------------
+// down pass: absolute rotation (F_SR) and tip point (F_LA) of every node
+__device__ void node_tip_fk(const DevModel& M, const float2* qs, int i) {
+  const int par = M.par[i];
+  Mat3 Rp;
+  V3 pt = v3(0, 0, 0);
+  if (par < 0) { for (int k = 0; k < 9; ++k) Rp.m[k] = (k % 4 == 0) ? 1.f : 0.f; }
+  else { for (int k = 0; k < 9; ++k) Rp.m[k] = aldf(M, F_SR + k, par); pt = ald3(M, F_LA, par); }
+  const float4 r = M.rq[i];
+  const float ww = r.x, xx = r.y, yy = r.z, zz = r.w;
+  const V3 Q0 = v3(1.f - 2.f * (yy * yy + zz * zz), 2.f * (xx * yy + ww * zz), 2.f * (xx * zz - ww * yy));
+  const V3 Q1 = v3(2.f * (xx * yy - ww * zz), 1.f - 2.f * (xx * xx + zz * zz), 2.f * (yy * zz + ww * xx));
+  const V3 Q2 = v3(2.f * (xx * zz + ww * yy), 2.f * (yy * zz - ww * xx), 1.f - 2.f * (xx * xx + yy * yy));
+  const V3 J0 = mul(Rp, Q0), J1 = mul(Rp, Q1), J2 = mul(Rp, Q2);
+  const float2 q = qs[i];
+  float sx, cx, sy, cy;
+  sincosf(q.x, &sx, &cx);
+  sincosf(q.y, &sy, &cy);
+  const V3 c0 = fma3(cy, J0, fma3(sx * sy, J1, (-cx * sy) * J2));
+  const V3 c1 = fma3(cx, J1, sx * J2);
+  const V3 c2 = fma3(sy, J0, fma3(-sx * cy, J1, (cx * cy) * J2));
+  asto(M, F_SR + 0, i, c0.x); asto(M, F_SR + 1, i, c1.x); asto(M, F_SR + 2, i, c2.x);
+  asto(M, F_SR + 3, i, c0.y); asto(M, F_SR + 4, i, c1.y); asto(M, F_SR + 5, i, c2.y);
+  asto(M, F_SR + 6, i, c0.z); asto(M, F_SR + 7, i, c1.z); asto(M, F_SR + 8, i, c2.z);
+  asto3(M, F_NU, i, pt);                         // joint point
+  asto3(M, F_LA, i, fma3(M.geo[i].x, c2, pt));    // tip point
+  asto3(M, F_A0, i, J0);                          // axis x
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_tip_fk(DevModel M, const float2* q) {
+  const int pk = blockIdx.x;
+  const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
+  for (int lv = lb; lv < le; ++lv) {
+    const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
+    for (int i = a + (int)threadIdx.x; i < b; i += NT) node_tip_fk(M, q, i);
+    __syncthreads();
+  }
+}
+
+__global__ void k_tip_gather(DevModel M, int n_tips, const int32_t* node, float* out) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_tips; k += gridDim.x * blockDim.x) {
+    const V3 p = ald3(M, F_LA, node[k]);
+    out[3 * k] = p.x; out[3 * k + 1] = p.y; out[3 * k + 2] = p.z;
+  }
+}
+
+// seeds: force-like adjoints at the tip points, summed per node by one thread in tip
+// order (several tips may share a node; a serial sum keeps the result deterministic)
+__global__ void k_tip_seed(DevModel M, int n_tips, const int32_t* node, const float* g) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int k = 0; k < n_tips; ++k) {
+    const int i = node[k];
+    M.scr[(size_t)(F_LPA + 0) * M.n_seg + i] += g[3 * k];
+    M.scr[(size_t)(F_LPA + 1) * M.n_seg + i] += g[3 * k + 1];
+    M.scr[(size_t)(F_LPA + 2) * M.n_seg + i] += g[3 * k + 2];
+  }
+}
+
+__global__ void k_clear_fields(DevModel M, int f0, int nf) {
+  const int64_t tot = (int64_t)nf * M.n_seg;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x)
+    M.scr[(size_t)f0 * M.n_seg + k] = 0.f;
+}
+
+// up pass: wrench (n, f) of the position adjoints about each joint point; dq_k = a_k . n
+__device__ void node_tip_bwd(const DevModel& M, float2* gq, int i) {
+  V3 n = v3(0, 0, 0), f = ald3(M, F_LPA, i);  // seed at the tip
+  const int cb = M.child[i], ce = cb + M.nchild[i];
+  for (int c = cb; c < ce; ++c) { n = n + ald3(M, F_RB, c); f = f + ald3(M, F_RB + 3, c); }
+  const V3 lz = ald3(M, F_LA, i) - ald3(M, F_NU, i);
+  n = n + cross(lz, f);
+  const V3 a0 = ald3(M, F_A0, i);
+  const V3 a1 = v3(aldf(M, F_SR + 1, i), aldf(M, F_SR + 4, i), aldf(M, F_SR + 7, i));
+  float2 g = gq[i];
+  g.x += dot(a0, n);
+  g.y += dot(a1, n);
+  gq[i] = g;
+  asto3(M, F_RB, i, n);
+  asto3(M, F_RB + 3, i, f);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_tip_bwd(DevModel M, float2* gq) {
+  const int pk = blockIdx.x;
+  const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
+  for (int lv = le - 1; lv >= lb; --lv) {
+    const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
+    for (int i = a + (int)threadIdx.x; i < b; i += NT) node_tip_bwd(M, gq, i);
+    __syncthreads();
+  }
+}
+
+template __global__ void k_adjoint_packs<64>(DevModel, DevState, const float*, DevInputs, DevAdj, int);
+template __global__ void k_adjoint_packs<128>(DevModel, DevState, const float*, DevInputs, DevAdj, int);
+template __global__ void k_adjoint_packs<256>(DevModel, DevState, const float*, DevInputs, DevAdj, int);
+template __global__ void k_adjoint_packs<512>(DevModel, DevState, const float*, DevInputs, DevAdj, int);
+template __global__ void k_tip_fk<64>(DevModel, const float2*);
+template __global__ void k_tip_fk<128>(DevModel, const float2*);
+template __global__ void k_tip_fk<256>(DevModel, const float2*);
+template __global__ void k_tip_fk<512>(DevModel, const float2*);
+template __global__ void k_tip_bwd<64>(DevModel, float2*);
+template __global__ void k_tip_bwd<128>(DevModel, float2*);
+template __global__ void k_tip_bwd<256>(DevModel, float2*);
+template __global__ void k_tip_bwd<512>(DevModel, float2*);
+
+}  // namespace orchard

@@ -22,6 +22,21 @@ __global__ void k_advance(int64_t*, int32_t*, int);
 __global__ void k_state_rest(DevModel, DevState, const float*);
 __global__ void k_ckpt_save(DevModel, DevState, uint32_t*);
 __global__ void k_ckpt_load(DevModel, DevState, const uint32_t*);
+struct DevAdj {
+  float2* q;
+  float2* qd;
+  float* ax;
+  float* av;
+  float* gkp;
+  float* gkd;
+  float* gF;
+};
+template <int NT> __global__ void k_adjoint_packs(DevModel, DevState, const float*, DevInputs, DevAdj, int);
+template <int NT> __global__ void k_tip_fk(DevModel, const float2*);
+template <int NT> __global__ void k_tip_bwd(DevModel, float2*);
+__global__ void k_tip_gather(DevModel, int, const int32_t*, float*);
+__global__ void k_tip_seed(DevModel, int, const int32_t*, const float*);
+__global__ void k_clear_fields(DevModel, int, int);
 
 static thread_local std::string g_err;
 
@@ -57,6 +72,11 @@ struct orchard_model_s {
   int64_t bytes = 0;
   int n_cu = 256;
   int persist_blocks = 0;
+  // adjoint support
+  int32_t adj_kmax = 0;
+  float* recs = nullptr;       // [adj_kmax][ckpt words]
+  void* work = nullptr;        // work state
+  DevState ws{};
 };
 
 namespace {
@@ -103,6 +123,7 @@ struct Arena {
 extern "C" {
 
 const char* orchard_last_error(void) { return g_err.c_str(); }
+int64_t orchard_ckpt_words(orchard_model_t m);
 
 orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orchard_tuning_t* tuning,
                                       orchard_model_t* out) {
@@ -116,8 +137,9 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       !(d->tension_factor > 0) || !(d->v_cap > 0) || !(d->react_max_factor > 0) || d->wrench_fraction < 0 ||
       d->wrench_fraction > 1)
     return fail(ORCHARD_ERR_INVALID_ARG, "step constant out of range");
-  orchard_tuning_t tun{128, 1.0f, 1, 0};
+  orchard_tuning_t tun{128, 1.0f, 1, 0, 0};
   if (tuning) tun = *tuning;
+  if (tun.adjoint_ckpt_max < 0) return fail(ORCHARD_ERR_INVALID_ARG, "tuning.adjoint_ckpt_max < 0");
   if (tun.threads != 64 && tun.threads != 128 && tun.threads != 256 && tun.threads != 512)
     return fail(ORCHARD_ERR_INVALID_ARG, "tuning.threads must be 64, 128, 256 or 512");
   if (tun.steps_per_launch < 1) tun.steps_per_launch = 1;
@@ -419,7 +441,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       if (he != hipSuccess) { (void)hipFree(M->arena); delete M; return fail(ORCHARD_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(he)); }
     }
   }
-  const size_t scr_bytes = (size_t)N_FIELDS * (size_t)std::max<int64_t>(NS, 1) * 4;
+  const size_t scr_bytes = (size_t)N_FIELDS_ADJ * (size_t)std::max<int64_t>(NS, 1) * 4;
   he = hipMalloc(&M->scr, scr_bytes);
   if (he != hipSuccess) { (void)hipFree(M->arena); delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc scratch: ") + hipGetErrorString(he)); }
   M->bytes = (int64_t)(ar.off + scr_bytes);
@@ -455,12 +477,32 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     default: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<512>, 512, 0); break;
   }
   M->persist_blocks = std::max(1, std::min<int>(M->n_pack, std::max(1, per_cu) * std::max(1, M->n_cu)));
+  if (tun.adjoint_ckpt_max > 0) {
+    const int64_t words = orchard_ckpt_words(M);
+    M->adj_kmax = tun.adjoint_ckpt_max;
+    const size_t rb = (size_t)M->adj_kmax * (size_t)words * 4;
+    // work state: q, qd (float2), apple (13A), seg_evt (2S), apple_evt (4A), evt_step (S+A), status (B), step
+    const size_t wb = 16 * (size_t)NS + 52 * (size_t)NA + 256 + 2 * (size_t)NS + 4 * (size_t)NA + 256 +
+                      4 * (size_t)(NS + NA) + 256 + 4 * (size_t)B + 256 + 64;
+    if (hipMalloc(&M->recs, rb) != hipSuccess || hipMalloc(&M->work, wb) != hipSuccess) {
+      orchard_model_destroy(M);
+      return fail(ORCHARD_ERR_OUT_OF_MEMORY, "adjoint buffers");
+    }
+    char* w = (char*)M->work;
+    auto take = [&](size_t b) { char* r = w; w += (b + 255) & ~size_t(255); return r; };
+    M->ws.q = (float2*)take(8 * NS); M->ws.qd = (float2*)take(8 * NS); M->ws.apple = (float*)take(52 * NA);
+    M->ws.seg_evt = (uint8_t*)take(2 * NS); M->ws.apple_evt = (uint8_t*)take(4 * NA);
+    M->ws.evt_step = (int32_t*)take(4 * (NS + NA)); M->ws.status = (uint32_t*)take(4 * B); M->ws.step = (int64_t*)take(8);
+    M->bytes += (int64_t)(rb + wb);
+  }
   *out = M;
   return ORCHARD_OK;
 }
 
 void orchard_model_destroy(orchard_model_t m) {
   if (!m) return;
+  if (m->recs) (void)hipFree(m->recs);
+  if (m->work) (void)hipFree(m->work);
   if (m->arena) (void)hipFree(m->arena);
   if (m->scr) (void)hipFree(m->scr);
   delete m;
@@ -520,9 +562,19 @@ int64_t orchard_ckpt_words(orchard_model_t m) {
 }
 
 static orchard_status_t launch_steps(orchard_model_t m, const DevState& ds, const DevInputs& di, int k, int s_call,
-                                     hipStream_t stream) {
+                                     hipStream_t stream, bool save = false) {
   const int NT = m->tun.threads;
-  if (m->tun.persistent) {
+  if (save) {
+    DevModel dm = m->dm;
+    dm.save_adj = 1;
+    const dim3 g(m->n_pack);
+    switch (NT) {
+      case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), 0, stream, dm, ds, di, k, s_call); break;
+      case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), 0, stream, dm, ds, di, k, s_call); break;
+      case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), 0, stream, dm, ds, di, k, s_call); break;
+      default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), 0, stream, dm, ds, di, k, s_call); break;
+    }
+  } else if (m->tun.persistent) {
     const dim3 g(m->persist_blocks);
     switch (NT) {
       case 64: hipLaunchKernelGGL(k_step_persistent<64>, g, dim3(64), 0, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
@@ -540,7 +592,7 @@ static orchard_status_t launch_steps(orchard_model_t m, const DevState& ds, cons
     }
   }
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, stream, ds.step, m->tun.persistent ? m->dm.queue : nullptr, k);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, stream, ds.step, (m->tun.persistent && !save) ? m->dm.queue : nullptr, k);
   HIPCHK(hipGetLastError());
   return ORCHARD_OK;
 }
@@ -635,6 +687,96 @@ orchard_status_t orchard_status(orchard_model_t m, const orchard_state_t* s, uin
   HIPCHK(hipStreamSynchronize(hs));
   for (int64_t e = 0; e < m->n_env; ++e)
     if (host_env_status[e]) return fail(ORCHARD_ERR_NONFINITE, "env " + std::to_string(e) + " produced a non-finite state");
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_step_backward(orchard_model_t m, const float* ckpt, int32_t ckpt_every, int32_t n_steps,
+                                       const orchard_params_t* params, const orchard_inputs_t* inputs,
+                                       const orchard_adjoint_t* adj, float* grad_kp, float* grad_kd,
+                                       float* grad_apple_force, orchard_stream_t stream) {
+  if (!m || !ckpt || !params || !params->kp || !params->kd || !adj || !adj->q || !adj->qd || !grad_kp || !grad_kd)
+    return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  if (m->n_apple > 0 && (!adj->apple_x || !adj->apple_v)) return fail(ORCHARD_ERR_INVALID_ARG, "apple adjoint missing");
+  if (m->adj_kmax <= 0) return fail(ORCHARD_ERR_INVALID_ARG, "model created without adjoint support (tuning.adjoint_ckpt_max)");
+  if (ckpt_every < 1 || ckpt_every > m->adj_kmax) return fail(ORCHARD_ERR_INVALID_ARG, "ckpt_every out of [1, adjoint_ckpt_max]");
+  if (n_steps < 0) return fail(ORCHARD_ERR_INVALID_ARG, "n_steps < 0");
+  DevInputs di{params->kp, params->kd, nullptr, 0, nullptr, 0};
+  if (inputs) {
+    di.wrench = inputs->body_wrench; di.wrench_stride = inputs->body_wrench_stride;
+    di.aforce = inputs->apple_force; di.aforce_stride = inputs->apple_force_stride;
+  }
+  DevAdj X{(float2*)adj->q, (float2*)adj->qd, adj->apple_x, adj->apple_v, grad_kp, grad_kd, grad_apple_force};
+  hipStream_t hs = (hipStream_t)stream;
+  const int64_t words = orchard_ckpt_words(m);
+  const int NT = m->tun.threads;
+  const int nseg = (n_steps + ckpt_every - 1) / ckpt_every;
+  const DevState& W = m->ws;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int n0 = sg * ckpt_every, nk = std::min(ckpt_every, n_steps - n0);
+    hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (const uint32_t*)ckpt + (int64_t)sg * words);
+    hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (uint32_t*)m->recs);
+    for (int j = 0; j + 1 < nk; ++j) {
+      orchard_status_t st = launch_steps(m, W, di, 1, n0 + j, hs);
+      if (st) return st;
+      hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (uint32_t*)m->recs + (int64_t)(j + 1) * words);
+    }
+    for (int j = nk - 1; j >= 0; --j) {
+      const float* rec = m->recs + (int64_t)j * words;
+      hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (const uint32_t*)rec);
+      orchard_status_t st = launch_steps(m, W, di, 1, n0 + j, hs, true);
+      if (st) return st;
+      const dim3 g(m->n_pack);
+      switch (NT) {
+        case 64: hipLaunchKernelGGL(k_adjoint_packs<64>, g, dim3(64), 0, hs, m->dm, W, rec, di, X, n0 + j); break;
+        case 128: hipLaunchKernelGGL(k_adjoint_packs<128>, g, dim3(128), 0, hs, m->dm, W, rec, di, X, n0 + j); break;
+        case 256: hipLaunchKernelGGL(k_adjoint_packs<256>, g, dim3(256), 0, hs, m->dm, W, rec, di, X, n0 + j); break;
+        default: hipLaunchKernelGGL(k_adjoint_packs<512>, g, dim3(512), 0, hs, m->dm, W, rec, di, X, n0 + j); break;
+      }
+      HIPCHK(hipGetLastError());
+    }
+  }
+  return ORCHARD_OK;
+}
+
+static orchard_status_t tip_fk(orchard_model_t m, const float* q, hipStream_t hs) {
+  const dim3 g(m->n_pack);
+  switch (m->tun.threads) {
+    case 64: hipLaunchKernelGGL(k_tip_fk<64>, g, dim3(64), 0, hs, m->dm, (const float2*)q); break;
+    case 128: hipLaunchKernelGGL(k_tip_fk<128>, g, dim3(128), 0, hs, m->dm, (const float2*)q); break;
+    case 256: hipLaunchKernelGGL(k_tip_fk<256>, g, dim3(256), 0, hs, m->dm, (const float2*)q); break;
+    default: hipLaunchKernelGGL(k_tip_fk<512>, g, dim3(512), 0, hs, m->dm, (const float2*)q); break;
+  }
+  HIPCHK(hipGetLastError());
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_tips(orchard_model_t m, const float* q, int32_t n_tips, const int32_t* node, float* out,
+                              orchard_stream_t stream) {
+  if (!m || !q || (n_tips > 0 && (!node || !out)) || n_tips < 0) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  hipStream_t hs = (hipStream_t)stream;
+  orchard_status_t st = tip_fk(m, q, hs);
+  if (st) return st;
+  if (n_tips) hipLaunchKernelGGL(k_tip_gather, dim3(grid_for(n_tips)), dim3(256), 0, hs, m->dm, n_tips, node, out);
+  HIPCHK(hipGetLastError());
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_tips_backward(orchard_model_t m, const float* q, int32_t n_tips, const int32_t* node,
+                                       const float* grad_out, float* grad_q, orchard_stream_t stream) {
+  if (!m || !q || !grad_q || n_tips < 0 || (n_tips > 0 && (!node || !grad_out))) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  hipStream_t hs = (hipStream_t)stream;
+  orchard_status_t st = tip_fk(m, q, hs);
+  if (st) return st;
+  hipLaunchKernelGGL(k_clear_fields, dim3(grid_for(3 * m->n_seg)), dim3(256), 0, hs, m->dm, (int)F_LPA, 3);
+  if (n_tips) hipLaunchKernelGGL(k_tip_seed, dim3(1), dim3(64), 0, hs, m->dm, n_tips, node, grad_out);
+  const dim3 g(m->n_pack);
+  switch (m->tun.threads) {
+    case 64: hipLaunchKernelGGL(k_tip_bwd<64>, g, dim3(64), 0, hs, m->dm, (float2*)grad_q); break;
+    case 128: hipLaunchKernelGGL(k_tip_bwd<128>, g, dim3(128), 0, hs, m->dm, (float2*)grad_q); break;
+    case 256: hipLaunchKernelGGL(k_tip_bwd<256>, g, dim3(256), 0, hs, m->dm, (float2*)grad_q); break;
+    default: hipLaunchKernelGGL(k_tip_bwd<512>, g, dim3(512), 0, hs, m->dm, (float2*)grad_q); break;
+  }
+  HIPCHK(hipGetLastError());
   return ORCHARD_OK;
 }
 

@@ -39,7 +39,23 @@ enum : int {
   F_UU = 111,       // 2: u = tau - S^T p^A
   N_FIELDS = 113,
   // second down pass publication overwrites the first six fields
-  F_AT = 0          // 6: acceleration at the tip (ang, lin)
+  F_AT = 0,         // 6: acceleration at the tip (ang, lin)
+  // ---- fields of the adjoint (allocated only when the model supports it) ----
+  // saved by the forward step in save mode
+  F_SR = 113,       // 9: body rotation, row major
+  F_SAVP = 122,     // 6: velocity-product (+ base) acceleration at the joint point
+  F_SIA = 128,      // 21: articulated inertia before the pivot update (A 6, B 9, M 6)
+  F_SPA = 149,      // 6: articulated bias before the pivot update
+  F_SA = 155,       // 6: total acceleration at the joint point
+  F_SQDD = 161,     // 2: joint accelerations
+  // adjoint passes
+  F_LU = 163,       // 2: u of the solve M lambda = qdd_bar
+  F_LPA = 165,      // 6: bias of that solve passed to the parent
+  F_LA = 171,       // 6: acceleration of that solve at the tip
+  F_NU = 177,       // 6: virtual velocity nu at the joint point
+  F_LAM = 183,      // 2: lambda
+  F_RB = 185,       // 24: reverse-pass publication: tau_bar 3, omega_bar 3, vt_bar 3, At_bar 6, Avt_bar 6, f_lin 3
+  N_FIELDS_ADJ = 209
 };
 
 struct DevModel {
@@ -68,8 +84,10 @@ struct DevModel {
   uint64_t seed;
   uint32_t rng_thr;
   float wsig;
-  float* scr;                // [N_FIELDS][n_seg]
+  float* scr;                // [N_FIELDS or N_FIELDS_ADJ][n_seg]
   int32_t* queue;            // persistent-kernel pack counter(s)
+  int32_t save_adj;          // forward step also writes the F_S* fields
+  int32_t pad1;
 };
 
 struct DevState {
@@ -130,6 +148,42 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
 }
 __device__ __forceinline__ uint32_t counter_u24(uint64_t seed, uint64_t env, uint64_t step, uint64_t seg, uint64_t k) {
   return (uint32_t)(splitmix64(seed ^ splitmix64(env ^ splitmix64(step ^ splitmix64(8ull * seg + k)))) >> 40);
+}
+
+// Applied force on segment i at step n: the input wrench plus the counter-based random
+// force, disabled on a snapped sub-tree, the force impulse-capped at m v_cap / h.  Returns
+// false if there is none.
+__device__ __forceinline__ bool applied_force(const DevModel& M, const DevInputs& I, int i, int e, int64_t n, int s_call,
+                                              float m, bool snp, V3& F, V3& T) {
+  F = v3(0, 0, 0);
+  T = v3(0, 0, 0);
+  if (snp) return false;
+  bool any = false;
+  if (I.wrench) {
+    const float* wp = I.wrench + (int64_t)s_call * I.wrench_stride + 6 * (int64_t)i;
+    F = v3(wp[0], wp[1], wp[2]);
+    T = v3(wp[3], wp[4], wp[5]);
+    any = true;
+  }
+  if (M.use_rng) {
+    const uint64_t ee = (uint64_t)e, nn = (uint64_t)n, ss = (uint64_t)M.orig[i];
+    if (counter_u24(M.seed, ee, nn, ss, 0) < M.rng_thr) {
+      float uu[4];
+      for (int k = 0; k < 4; ++k) uu[k] = ((float)counter_u24(M.seed, ee, nn, ss, (uint64_t)(k + 1)) + 0.5f) * (1.f / 16777216.f);
+      const float r0 = sqrtf(-2.f * logf(uu[0])), r1 = sqrtf(-2.f * logf(uu[2]));
+      float s1, c1v, s3, c3;
+      sincosf(6.283185307179586f * uu[1], &s1, &c1v);
+      sincosf(6.283185307179586f * uu[3], &s3, &c3);
+      F = F + M.wsig * v3(r0 * c1v, r0 * s1, r1 * c3);
+      any = true;
+    }
+  }
+  if (any) {
+    const float nF = sqrtf(dot(F, F));
+    const float cap = m * M.vcap / M.h;
+    if (nF > cap) F = (cap / nF) * F;
+  }
+  return any;
 }
 
 }  // namespace orchard

@@ -116,6 +116,12 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
   sto3(M, F_AVA, i, Ava);
   sto3(M, F_AVL, i, Avl + cross(Ava, lz));
   sto(M, F_SNAP, i, snp ? 1.f : 0.f);
+  if (M.save_adj) {
+    sto(M, F_SR + 0, i, c0.x); sto(M, F_SR + 1, i, c1.x); sto(M, F_SR + 2, i, c2.x);
+    sto(M, F_SR + 3, i, c0.y); sto(M, F_SR + 4, i, c1.y); sto(M, F_SR + 5, i, c2.y);
+    sto(M, F_SR + 6, i, c0.z); sto(M, F_SR + 7, i, c1.z); sto(M, F_SR + 8, i, c2.z);
+    sto3(M, F_SAVP, i, Ava); sto3(M, F_SAVP + 3, i, Avl);
+  }
 
   // ---- rigid body inertia about the joint point: axisymmetric capsule ----
   const float ml2 = 0.5f * m * l;
@@ -132,31 +138,8 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
 
   // ---- applied body force (input and counter-based random), impulse cap, snapped mask ----
   {
-    V3 F = v3(0, 0, 0), T = v3(0, 0, 0);
-    bool any = false;
-    if (I.wrench) {
-      const float* wp = I.wrench + (int64_t)s_call * I.wrench_stride + 6 * (int64_t)i;
-      F = v3(wp[0], wp[1], wp[2]);
-      T = v3(wp[3], wp[4], wp[5]);
-      any = true;
-    }
-    if (M.use_rng && !snp) {
-      const uint64_t ee = (uint64_t)e, nn = (uint64_t)n, ss = (uint64_t)M.orig[i];
-      if (counter_u24(M.seed, ee, nn, ss, 0) < M.rng_thr) {
-        float uu[4];
-        for (int k = 0; k < 4; ++k) uu[k] = ((float)counter_u24(M.seed, ee, nn, ss, (uint64_t)(k + 1)) + 0.5f) * (1.f / 16777216.f);
-        const float r0 = sqrtf(-2.f * logf(uu[0])), r1 = sqrtf(-2.f * logf(uu[2]));
-        float s1, c1v, s3, c3;
-        sincosf(6.283185307179586f * uu[1], &s1, &c1v);
-        sincosf(6.283185307179586f * uu[3], &s3, &c3);
-        F = F + M.wsig * v3(r0 * c1v, r0 * s1, r1 * c3);
-        any = true;
-      }
-    }
-    if (any && !snp) {
-      const float nF = sqrtf(dot(F, F));
-      const float cap = m * M.vcap / h;
-      if (nF > cap) F = (cap / nF) * F;
+    V3 F, T;
+    if (applied_force(M, I, i, e, n, s_call, m, snp, F, T)) {
       pang = pang - (T + cross(0.5f * lz, F));
       plin = plin - F;
     }
@@ -326,6 +309,14 @@ __device__ void node_up(const DevModel& M, int i) {
     pn = pn + ld3(M, F_P, i);
     pf = pf + ld3(M, F_P + 3, i);
   }
+  if (M.save_adj) {
+    sto(M, F_SIA + 0, i, A.xx); sto(M, F_SIA + 1, i, A.yy); sto(M, F_SIA + 2, i, A.zz);
+    sto(M, F_SIA + 3, i, A.xy); sto(M, F_SIA + 4, i, A.xz); sto(M, F_SIA + 5, i, A.yz);
+    for (int k = 0; k < 9; ++k) sto(M, F_SIA + 6 + k, i, B.m[k]);
+    sto(M, F_SIA + 15, i, Mm.xx); sto(M, F_SIA + 16, i, Mm.yy); sto(M, F_SIA + 17, i, Mm.zz);
+    sto(M, F_SIA + 18, i, Mm.xy); sto(M, F_SIA + 19, i, Mm.xz); sto(M, F_SIA + 20, i, Mm.yz);
+    sto3(M, F_SPA, i, pn); sto3(M, F_SPA + 3, i, pf);
+  }
   const V3 a0 = ld3(M, F_A0, i), a1 = ld3(M, F_A1, i);
   const float dg = ld(M, F_DG, i);
   // U = I^A S,  S = [a0 a1; 0 0]
@@ -384,6 +375,10 @@ __device__ void node_down2(const DevModel& M, const DevState& S, int i) {
   const V3 a0 = ld3(M, F_A0, i), a1 = ld3(M, F_A1, i);
   Aa = fma3(qdd0, a0, fma3(qdd1, a1, Aa));
   const V3 lz = ld3(M, F_LZ, i);
+  if (M.save_adj) {
+    sto3(M, F_SA, i, Aa); sto3(M, F_SA + 3, i, Al);
+    sto(M, F_SQDD, i, qdd0); sto(M, F_SQDD + 1, i, qdd1);
+  }
   sto3(M, F_AT, i, Aa);
   sto3(M, F_AT + 3, i, Al + cross(Aa, lz));
   const float h = M.h;

@@ -35,7 +35,11 @@ class Desc(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("pack_fill", C.c_float), ("steps_per_launch", C.c_int32),
-                ("persistent", C.c_int32)]
+                ("persistent", C.c_int32), ("adjoint_ckpt_max", C.c_int32)]
+
+
+class CAdjoint(C.Structure):
+    _fields_ = [("q", _P), ("qd", _P), ("apple_x", _P), ("apple_v", _P)]
 
 
 class Layout(C.Structure):
@@ -64,7 +68,8 @@ class Event(C.Structure):
 EXPORTS = ("orchard_model_create", "orchard_model_destroy", "orchard_model_layout", "orchard_model_maps",
            "orchard_model_apple_rest",
            "orchard_default_params", "orchard_state_rest", "orchard_step", "orchard_ckpt_words",
-           "orchard_ckpt_load", "orchard_events", "orchard_status", "orchard_last_error")
+           "orchard_ckpt_load", "orchard_events", "orchard_status", "orchard_last_error", "orchard_step_backward",
+           "orchard_tips", "orchard_tips_backward")
 
 _lib = None
 
@@ -110,6 +115,13 @@ def load_library(path: str = LIB_PATH):
     L.orchard_events.restype = st
     L.orchard_status.argtypes = [_P, C.POINTER(CState), _P, _P]
     L.orchard_status.restype = st
+    L.orchard_step_backward.argtypes = [_P, _P, C.c_int32, C.c_int32, C.POINTER(CParams), C.POINTER(CInputs),
+                                        C.POINTER(CAdjoint), _P, _P, _P, _P]
+    L.orchard_step_backward.restype = st
+    L.orchard_tips.argtypes = [_P, _P, C.c_int32, _P, _P, _P]
+    L.orchard_tips.restype = st
+    L.orchard_tips_backward.argtypes = [_P, _P, C.c_int32, _P, _P, _P, _P]
+    L.orchard_tips_backward.restype = st
     L.orchard_last_error.argtypes = []
     L.orchard_last_error.restype = C.c_char_p
     _lib = L
@@ -189,9 +201,10 @@ class Model:
         self.consts = dict(consts)
         tun = None
         if tuning is not None:
-            t = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0)
+            t = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0, adjoint_ckpt_max=0)
             t.update(tuning)
-            tun = Tuning(int(t["threads"]), float(t["pack_fill"]), int(t["steps_per_launch"]), int(t["persistent"]))
+            tun = Tuning(int(t["threads"]), float(t["pack_fill"]), int(t["steps_per_launch"]), int(t["persistent"]),
+                         int(t["adjoint_ckpt_max"]))
         self.tuning = tun
         h = C.c_void_p()
         _check(L.orchard_model_create(C.byref(d), C.byref(tun) if tun is not None else None, C.byref(h)))
@@ -265,6 +278,44 @@ class Model:
         _check(load_library().orchard_step(self.h, C.byref(cs), C.byref(pr), C.byref(inp), int(n_steps),
                                            _tptr(ckpt), int(ckpt_every), _stream(stream)))
         return state
+
+    def _inputs(self, n_steps, wrench, wrench_stride, aforce, aforce_stride):
+        inp = CInputs()
+        if wrench is not None:
+            assert wrench.is_contiguous() and wrench.shape[-2:] == (self.n_seg, 6)
+            assert wrench.dim() == 2 or wrench.shape[0] >= n_steps
+            inp.body_wrench = _tptr(wrench)
+            inp.body_wrench_stride = (0 if wrench.dim() == 2 else self.n_seg * 6) if wrench_stride is None else wrench_stride
+        if aforce is not None and self.n_apple:
+            assert aforce.is_contiguous() and aforce.shape[-2:] == (self.n_apple, 3)
+            assert aforce.dim() == 2 or aforce.shape[0] >= n_steps
+            inp.apple_force = _tptr(aforce)
+            inp.apple_force_stride = (0 if aforce.dim() == 2 else self.n_apple * 3) if aforce_stride is None else aforce_stride
+        return inp
+
+    def step_backward(self, ckpt, ckpt_every: int, n_steps: int, kp, kd, adj: dict, grad_kp, grad_kd,
+                      grad_aforce=None, wrench=None, wrench_stride=None, aforce=None, aforce_stride=None, stream=None):
+        """adj: dict of device tensors q, qd [n_seg, 2], ax, av [3, n_apple] holding dL/dS_T;
+        overwritten with dL/dS_0.  Gradients accumulate into grad_kp, grad_kd, grad_aforce."""
+        inp = self._inputs(n_steps, wrench, wrench_stride, aforce, aforce_stride)
+        ca = CAdjoint(_tptr(adj["q"]), _tptr(adj["qd"]), _tptr(adj["ax"]), _tptr(adj["av"]))
+        pr = CParams(_tptr(kp), _tptr(kd))
+        if grad_aforce is not None:
+            assert grad_aforce.is_contiguous() and grad_aforce.numel() >= n_steps * self.n_apple * 3
+        _check(load_library().orchard_step_backward(self.h, _tptr(ckpt), int(ckpt_every), int(n_steps), C.byref(pr),
+                                                    C.byref(inp), C.byref(ca), _tptr(grad_kp), _tptr(grad_kd),
+                                                    _tptr(grad_aforce), _stream(stream)))
+
+    def tips(self, q, node, stream=None):
+        import torch
+        out = torch.empty(node.numel(), 3, device=q.device)
+        _check(load_library().orchard_tips(self.h, _tptr(q), int(node.numel()), _tptr(node), _tptr(out), _stream(stream)))
+        return out
+
+    def tips_backward(self, q, node, grad_out, grad_q, stream=None):
+        _check(load_library().orchard_tips_backward(self.h, _tptr(q), int(node.numel()), _tptr(node),
+                                                    _tptr(grad_out.contiguous()), _tptr(grad_q), _stream(stream)))
+        return grad_q
 
     def ckpt_load(self, state: State, record, stream=None):
         cs = state.c()

@@ -1,0 +1,150 @@
+"""GPU adjoint (through the C ABI and the autograd wrappers) against the FP64 oracle
+adjoint and against FP64 central differences with the event schedule replayed.
+
+Workload: the differentiable-rollout batch (512 trees of 300 segments and 40 apples),
+200 steps from rest with checkpoints every 20, per-step apple forces N(0, 2 N), loss =
+squared error of 16 tip positions per tree against seeded targets.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from orchard_inputs import assemble, grad_apple_forces, grad_targets, make_batch, step_constants
+from oracle.oracle import Oracle, Record, adjoint, env_state0, loss
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no HIP device", allow_module_level=True)
+
+T, K = 200, 20
+TOL = 1e-3
+
+
+def _rest_tips(batch):
+    """Rest tip positions from the oracle's kinematics (inputs of the seeded targets)."""
+    o = Oracle(batch, step_constants())
+    tips = np.zeros((batch.n_seg, 3))
+    for e in range(batch.n_env):
+        s0, s1 = batch.seg_offset[e], batch.seg_offset[e + 1]
+        R, p = o.fk(e, np.zeros(2 * (s1 - s0)))
+        tips[s0:s1] = p + R[:, :, 2] * batch.seg_length[s0:s1, None]
+    return tips
+
+
+def _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=K, tuning=None):
+    from paper_2607_06337_amd import Model, rollout, tips
+    tun = dict(threads=128, pack_fill=1.0, adjoint_ckpt_max=ckpt_every)
+    tun.update(tuning or {})
+    m = Model(batch, consts, tun)
+    st = m.rest_state()
+    kp0, kd0 = m.default_params()
+    kp = kp0.clone().requires_grad_(True)
+    kd = kd0.clone().requires_grad_(True)
+    Fi = torch.tensor(m.apple_from_desc(F.astype(np.float32), axis=1), device="cuda").contiguous().requires_grad_(True)
+    glob = (batch.seg_offset[:-1, None] + tip_idx).reshape(-1)
+    inv = np.empty(m.n_seg, np.int64)
+    inv[m.seg_map] = np.arange(m.n_seg)
+    node = torch.tensor(inv[glob].astype(np.int32), device="cuda")
+    q, qd, ax, av = rollout(m, st, kp, kd, T, ckpt_every, aforce=Fi)
+    tp = tips(m, q, node)
+    tgt = torch.tensor(target.reshape(-1, 3), dtype=torch.float32, device="cuda")
+    L = ((tp - tgt) ** 2).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    gkp = m.seg_to_desc(kp.grad.cpu().numpy().astype(np.float64))
+    gkd = m.seg_to_desc(kd.grad.cpu().numpy().astype(np.float64))
+    gF = m.apple_to_desc(Fi.grad.cpu().numpy().astype(np.float64), axis=1)
+    kpd = m.seg_to_desc(kp0.cpu().numpy().astype(np.float64))
+    kdd = m.seg_to_desc(kd0.cpu().numpy().astype(np.float64))
+    return float(L.item()), gkp, gkd, gF, kpd, kdd
+
+
+@pytest.fixture(scope="module")
+def grad_setup():
+    batch = make_batch("grad512")
+    consts = step_constants()
+    F = grad_apple_forces(batch, T)
+    tip_idx, target = grad_targets(batch, _rest_tips(batch))
+    res = _gpu_gradients(batch, consts, F, tip_idx, target)
+    return batch, consts, F, tip_idx, target, res
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+def test_adjoint_matches_fp64_oracle_adjoint_on_8_trees(grad_setup):
+    batch, consts, F, tip_idx, target, (L, gkp, gkd, gF, kpd, kdd) = grad_setup
+    envs = [0, 73, 141, 200, 299, 350, 420, 511]
+    sub = assemble([batch.tree(e) for e in envs])
+    o = Oracle(sub, consts)
+    st = o.rest_state()
+
+    def one(k):
+        e = envs[k]
+        s0, s1 = batch.seg_offset[e], batch.seg_offset[e + 1]
+        a0, a1 = batch.apple_offset[e], batch.apple_offset[e + 1]
+        return adjoint(o, k, env_state0(o, st, k), kpd[s0:s1], kdd[s0:s1], F[:, a0:a1], T, tip_idx[e], target[e])
+
+    with ThreadPoolExecutor(8) as ex:
+        outs = list(ex.map(one, range(len(envs))))
+    worst = 0.0
+    for k, e in enumerate(envs):
+        Lo, gkp_o, gkd_o, gF_o, _ = outs[k]
+        s0, s1 = batch.seg_offset[e], batch.seg_offset[e + 1]
+        a0, a1 = batch.apple_offset[e], batch.apple_offset[e + 1]
+        r = (_rel(gkp[s0:s1], gkp_o), _rel(gkd[s0:s1], gkd_o), _rel(gF[:, a0:a1], gF_o))
+        print(f"env {e}: L_oracle {Lo:.6e} rel err kp {r[0]:.2e} kd {r[1]:.2e} F {r[2]:.2e}", flush=True)
+        worst = max(worst, *r)
+    assert worst < TOL
+
+
+def test_adjoint_matches_fp64_central_differences(grad_setup):
+    batch, consts, F, tip_idx, target, (L, gkp, gkd, gF, kpd, kdd) = grad_setup
+    rng = np.random.default_rng(5)
+    for e in (3, 333):
+        sub = assemble([batch.tree(e)])
+        o = Oracle(sub, consts)
+        x0 = env_state0(o, o.rest_state(), 0)
+        s0, s1 = batch.seg_offset[e], batch.seg_offset[e + 1]
+        a0, a1 = batch.apple_offset[e], batch.apple_offset[e + 1]
+        kp, kd, Fe = kpd[s0:s1], kdd[s0:s1], F[:, a0:a1].copy()
+        rec = Record()
+        loss(o, 0, x0, kp, kd, Fe, T, tip_idx[e], target[e], record_out=rec)
+        f = lambda kp_, kd_, F_: loss(o, 0, x0, kp_, kd_, F_, T, tip_idx[e], target[e], record_in=rec)
+        g_kp, g_kd, g_F = gkp[s0:s1], gkd[s0:s1], gF[:, a0:a1]
+        # coordinates: the largest-gradient joints and apple-force entries
+        for i in np.argsort(-np.abs(g_kp))[:4]:
+            h = 1e-4 * kp[i]
+            d = np.zeros_like(kp); d[i] = h
+            fd = (f(kp + d, kd, Fe) - f(kp - d, kd, Fe)) / (2 * h)
+            assert abs(fd - g_kp[i]) <= TOL * np.abs(g_kp).max(), (e, "kp", i, fd, g_kp[i])
+        for i in np.argsort(-np.abs(g_kd))[:4]:
+            h = 1e-4 * kd[i]
+            d = np.zeros_like(kd); d[i] = h
+            fd = (f(kp, kd + d, Fe) - f(kp, kd - d, Fe)) / (2 * h)
+            assert abs(fd - g_kd[i]) <= TOL * np.abs(g_kd).max(), (e, "kd", i, fd, g_kd[i])
+        for i in np.argsort(-np.abs(g_F).reshape(-1))[:4]:
+            d = np.zeros_like(Fe); d.flat[i] = 1e-4
+            fd = (f(kp, kd, Fe + d) - f(kp, kd, Fe - d)) / 2e-4
+            assert abs(fd - g_F.flat[i]) <= TOL * np.abs(g_F).max(), (e, "F", i, fd, g_F.flat[i])
+        # random directions
+        for _ in range(4):
+            dkp, dkd, dF = rng.normal(size=kp.size) * kp, rng.normal(size=kd.size) * kd, rng.normal(size=Fe.shape)
+            ep = 1e-5
+            fd = (f(kp + ep * dkp, kd + ep * dkd, Fe + ep * dF) - f(kp - ep * dkp, kd - ep * dkd, Fe - ep * dF)) / (2 * ep)
+            an = g_kp @ dkp + g_kd @ dkd + np.sum(g_F * dF)
+            assert abs(fd - an) <= TOL * max(abs(an), 1e-12), (e, fd, an)
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    batch = make_batch("grad512", env_ids=range(6))
+    consts = step_constants()
+    F = grad_apple_forces(batch, T)
+    tip_idx, target = grad_targets(batch, _rest_tips(batch))
+    a = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=20)
+    b = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=7)
+    for x, y in zip(a[1:4], b[1:4]):
+        assert np.array_equal(x, y)
