@@ -28,9 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # kernel mapping used by the benchmark (and by the full-size parity test)
-BENCH_TUNING = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0)
-# the plain per-step kernel: one 256-thread workgroup per tree, one launch per step
-PLAIN_TUNING = dict(threads=256, pack_fill=0.0, steps_per_launch=1, persistent=0)
+BENCH_TUNING = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0, lds_width=256)
+# the plain per-step kernel: one 256-thread workgroup per tree, one launch per step,
+# levels exchange through global scratch
+PLAIN_TUNING = dict(threads=256, pack_fill=0.0, steps_per_launch=1, persistent=0, lds_width=0)
 
 HBM_PEAK_GBS = 8000.0
 SEG_BYTES, APPLE_BYTES = 84, 146   # algorithmic bytes per segment-step / apple-step

@@ -85,10 +85,15 @@ typedef struct {
   double wrench_sigma;          /* N(0, sigma) per force component                    */
 } orchard_model_desc_t;
 
-/* Kernel mapping choices (nullable in create: defaults).  threads: workgroup size
- * for the pack kernel (64, 128, 256 or 512).  pack_fill: a pack collects trees of
- * similar depth until it holds about pack_fill * threads * depth nodes (0 = one
- * tree per pack). */
+/* Kernel mapping choices (nullable in create: defaults {128, 1.0, 1, 0, 0, 256}).
+ * threads: workgroup size for the pack kernel (64, 128, 256 or 512).  pack_fill: a
+ * pack collects trees of similar depth until it holds about pack_fill * threads *
+ * depth nodes (0 = one tree per pack).  lds_width: capacity, in nodes per level, of
+ * the LDS buffer through which neighbouring levels of a pack exchange their data
+ * (2 x 27 x lds_width floats of LDS per workgroup); packs are also closed before a
+ * level would exceed it, and a tree wider than it exchanges through global scratch.
+ * 0 = global scratch for every pack.  No mapping choice changes any result bit. */
+#define ORCHARD_LDS_WIDTH_MAX 512
 typedef struct {
   int32_t threads;
   float pack_fill;
@@ -96,6 +101,7 @@ typedef struct {
   int32_t persistent;           /* 1: persistent grid pulling packs from a queue      */
   int32_t adjoint_ckpt_max;     /* > 0: allocate recompute buffers for                */
                                 /*   orchard_step_backward with ckpt_every up to this */
+  int32_t lds_width;            /* 0 .. ORCHARD_LDS_WIDTH_MAX                         */
 } orchard_tuning_t;
 
 typedef struct {
@@ -238,6 +244,36 @@ orchard_status_t orchard_status(orchard_model_t model, const orchard_state_t* st
 
 /* Message of the last error on this thread ("" if none). */
 const char* orchard_last_error(void);
+
+/* ---- K-step rollouts as one HIP graph (uneven batching: launch-bound inner loops) ----
+ * orchard_graph_create captures n_steps of orchard_step (no checkpoints) on a private
+ * stream into a HIP graph of kernel nodes only (no allocation, copy or memset nodes)
+ * and instantiates it.  The state, params and inputs pointers are baked in: each
+ * orchard_graph_launch advances that same state by n_steps on `stream`, reading input
+ * rows 0 .. n_steps-1 again (stride semantics as in orchard_step).  The step counter
+ * lives in device memory, so event stamps and the random wrench keys keep counting
+ * across replays and a replay equals the eager call bit for bit.  The graph holds no
+ * reference to the model's host object but uses its device buffers: destroy it first.
+ * Errors: ORCHARD_ERR_INVALID_ARG as orchard_step, ORCHARD_ERR_HIP if capture or
+ * instantiation fails (the message names the HIP error). */
+typedef struct orchard_graph_s* orchard_graph_t;
+orchard_status_t orchard_graph_create(orchard_model_t model, const orchard_state_t* state, const orchard_params_t* params,
+                                      const orchard_inputs_t* inputs, int32_t n_steps, orchard_graph_t* out);
+orchard_status_t orchard_graph_launch(orchard_graph_t graph, orchard_stream_t stream);
+void orchard_graph_destroy(orchard_graph_t graph);
+
+/* ---- autotuner: pick the kernel mapping for a batch by measurement ----
+ * Builds a model for each of the n_candidates mappings (adjoint_ckpt_max ignored),
+ * runs n_warm steps from rest, then times n_steps steps with HIP events on `stream`
+ * (default params, the descriptor's own random wrenches, no other inputs), and writes
+ * the fastest mapping to *best and every candidate's milliseconds per step to
+ * ms_out[n_candidates] (nullable; a candidate that fails to build gets -1).  Allocates
+ * and frees its own state; synchronises the stream.  Errors: ORCHARD_ERR_INVALID_ARG
+ * for null pointers, n_candidates < 1 or n_steps < 1; the descriptor's own errors if
+ * no candidate builds. */
+orchard_status_t orchard_autotune(const orchard_model_desc_t* desc, const orchard_tuning_t* candidates,
+                                  int32_t n_candidates, int32_t n_warm, int32_t n_steps, orchard_tuning_t* best,
+                                  float* ms_out, orchard_stream_t stream);
 
 #ifdef __cplusplus
 }

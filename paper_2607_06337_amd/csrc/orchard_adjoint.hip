@@ -13,8 +13,8 @@
 
 namespace orchard {
 
-__device__ __forceinline__ float aldf(const DevModel& M, int f, int i) { return M.scr[(size_t)f * M.n_seg + i]; }
-__device__ __forceinline__ void asto(const DevModel& M, int f, int i, float v) { M.scr[(size_t)f * M.n_seg + i] = v; }
+__device__ __forceinline__ float aldf(const DevModel& M, int f, int i) { return M.scr[scr_idx(M, f, i)]; }
+__device__ __forceinline__ void asto(const DevModel& M, int f, int i, float v) { M.scr[scr_idx(M, f, i)] = v; }
 __device__ __forceinline__ V3 ald3(const DevModel& M, int f, int i) { return v3(aldf(M, f, i), aldf(M, f + 1, i), aldf(M, f + 2, i)); }
 __device__ __forceinline__ void asto3(const DevModel& M, int f, int i, V3 v) { asto(M, f, i, v.x); asto(M, f + 1, i, v.y); asto(M, f + 2, i, v.z); }
 
@@ -378,16 +378,16 @@ __global__ void k_tip_seed(DevModel M, int n_tips, const int32_t* node, const fl
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   for (int k = 0; k < n_tips; ++k) {
     const int i = node[k];
-    M.scr[(size_t)(F_LPA + 0) * M.n_seg + i] += g[3 * k];
-    M.scr[(size_t)(F_LPA + 1) * M.n_seg + i] += g[3 * k + 1];
-    M.scr[(size_t)(F_LPA + 2) * M.n_seg + i] += g[3 * k + 2];
+    M.scr[scr_idx(M, F_LPA + 0, i)] += g[3 * k];
+    M.scr[scr_idx(M, F_LPA + 1, i)] += g[3 * k + 1];
+    M.scr[scr_idx(M, F_LPA + 2, i)] += g[3 * k + 2];
   }
 }
 
 __global__ void k_clear_fields(DevModel M, int f0, int nf) {
   const int64_t tot = (int64_t)nf * M.n_seg;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x)
-    M.scr[(size_t)f0 * M.n_seg + k] = 0.f;
+    M.scr[scr_idx(M, f0 + (int)(k / M.n_seg), (int)(k % M.n_seg))] = 0.f;
 }
 
 // up pass: wrench (n, f) of the position adjoints about each joint point; dq_k = a_k . n

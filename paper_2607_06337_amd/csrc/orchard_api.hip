@@ -66,6 +66,7 @@ struct orchard_model_s {
   std::vector<double> apple_hang_rest;                // [n_apple][3] rest hang points
   void* arena = nullptr;
   float* scr = nullptr;
+  size_t lds_bytes = 0;                               // dynamic LDS of the step kernels
   float* kp0 = nullptr;
   float* kd0 = nullptr;
   float* apple_rest = nullptr;
@@ -120,6 +121,18 @@ struct Arena {
 
 }  // namespace
 
+// allow the exchange buffer's dynamic LDS and return resident workgroups per CU
+template <class KP, class KQ>
+static int lds_setup(KP kp, KQ kq, int nt, int lds_bytes) {
+  if (lds_bytes > 65536) {
+    (void)hipFuncSetAttribute((const void*)kp, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    (void)hipFuncSetAttribute((const void*)kq, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  }
+  int per_cu = 1;
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kq, nt, lds_bytes);
+  return per_cu;
+}
+
 extern "C" {
 
 const char* orchard_last_error(void) { return g_err.c_str(); }
@@ -137,8 +150,10 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       !(d->tension_factor > 0) || !(d->v_cap > 0) || !(d->react_max_factor > 0) || d->wrench_fraction < 0 ||
       d->wrench_fraction > 1)
     return fail(ORCHARD_ERR_INVALID_ARG, "step constant out of range");
-  orchard_tuning_t tun{128, 1.0f, 1, 0, 0};
+  orchard_tuning_t tun{128, 1.0f, 1, 0, 0, 256};
   if (tuning) tun = *tuning;
+  if (tun.lds_width < 0 || tun.lds_width > ORCHARD_LDS_WIDTH_MAX)
+    return fail(ORCHARD_ERR_INVALID_ARG, "tuning.lds_width must be in [0, " + std::to_string(ORCHARD_LDS_WIDTH_MAX) + "]");
   if (tun.adjoint_ckpt_max < 0) return fail(ORCHARD_ERR_INVALID_ARG, "tuning.adjoint_ckpt_max < 0");
   if (tun.threads != 64 && tun.threads != 128 && tun.threads != 256 && tun.threads != 512)
     return fail(ORCHARD_ERR_INVALID_ARG, "tuning.threads must be 64, 128, 256 or 512");
@@ -247,7 +262,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     }
   }
   std::vector<float> arest(3 * NA);
-  std::vector<float4> ahang_h(NA), apar_h(NA);
+  std::vector<float4> ahang_h(NA), apar_h(NA), ahrest_h(NA);
   std::vector<int32_t> aseg_g(NA);
   for (int e = 0; e < B; ++e) {
     const int s0 = d->seg_offset[e], S = d->seg_offset[e + 1] - s0;
@@ -293,23 +308,34 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     if (lvlw[a].size() != lvlw[b].size()) return lvlw[a].size() > lvlw[b].size();
     return d->seg_offset[a + 1] - d->seg_offset[a] > d->seg_offset[b + 1] - d->seg_offset[b];
   });
+  // With an LDS exchange, a pack also stops growing once one of its levels would hold
+  // more than lds_width nodes; a single tree wider than that gets a pack of its own
+  // that exchanges through global scratch.
   std::vector<std::vector<int32_t>> packs;
   {
     std::vector<int32_t> cur;
+    std::vector<int64_t> curw;
     int64_t cur_nodes = 0;
     size_t cur_depth = 0;
+    const int64_t W = tun.lds_width;
     for (int t : tord) {
       const int64_t St = d->seg_offset[t + 1] - d->seg_offset[t];
       const size_t dt = lvlw[t].size();
+      bool wide = false;
+      if (W > 0)
+        for (size_t l = 0; l < dt && l < curw.size(); ++l) wide = wide || curw[l] + lvlw[t][l] > W;
       if (!cur.empty() && (tun.pack_fill <= 0.f || cur_nodes + St > (int64_t)(tun.pack_fill * NT * cur_depth) ||
-                           dt * 10 < cur_depth * 7)) {
+                           dt * 10 < cur_depth * 7 || wide)) {
         packs.push_back(cur);
         cur.clear();
+        curw.clear();
         cur_nodes = 0;
       }
       if (cur.empty()) cur_depth = dt;
       cur.push_back(t);
       cur_nodes += St;
+      if (curw.size() < dt) curw.resize(dt, 0);
+      for (size_t l = 0; l < dt; ++l) curw[l] += lvlw[t][l];
     }
     if (!cur.empty()) packs.push_back(cur);
   }
@@ -332,8 +358,9 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
 
   // ---- internal order ----
   std::vector<int32_t> seg_map;  seg_map.reserve(NS);
-  std::vector<int32_t> pack_node, pack_lvl, lvl_off;
+  std::vector<int32_t> pack_node, pack_lvl, lvl_off, pack_lds;
   std::vector<int32_t> int_of(NS, -1);
+  int n_lds_packs = 0;
   for (int pi : pord) {
     const auto& P = packs[pi];
     pack_node.push_back((int32_t)seg_map.size());
@@ -341,6 +368,15 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     size_t L = 0;
     for (int t : P) L = std::max(L, lvlw[t].size());
     std::vector<size_t> pos(P.size(), 0);
+    int64_t wmax = 0;
+    for (size_t l = 0; l < L; ++l) {
+      int64_t w = 0;
+      for (int t : P) if (l < lvlw[t].size()) w += lvlw[t][l];
+      wmax = std::max(wmax, w);
+    }
+    const int fits = tun.lds_width > 0 && wmax <= tun.lds_width;
+    pack_lds.push_back(fits);
+    n_lds_packs += fits;
     for (size_t l = 0; l < L; ++l) {
       lvl_off.push_back((int32_t)seg_map.size());
       for (size_t k = 0; k < P.size(); ++k) {
@@ -401,6 +437,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     // apple hangs m |g| / k_s below it
     const D3 xh0 = add(pw[g], mv(Rw[g], hl));
     ahang_rest[3 * k] = xh0.x; ahang_rest[3 * k + 1] = xh0.y; ahang_rest[3 * k + 2] = xh0.z;
+    ahrest_h[k] = make_float4((float)xh0.x, (float)xh0.y, (float)xh0.z, 0.f);
     arest[k] = (float)(ma / d->tether_k * d->gravity[0]);
     arest[NA + k] = (float)(ma / d->tether_k * d->gravity[1]);
     arest[2 * NA + k] = (float)(ma / d->tether_k * d->gravity[2]);
@@ -430,6 +467,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
          o_rq = ar.put(rq.data(), NS * 16), o_geo = ar.put(geo.data(), NS * 16), o_mm = ar.put(mmax_f.data(), NS * 4),
          o_ah = ar.put(ahang_h.data(), NA * 16), o_ap = ar.put(apar_h.data(), NA * 16),
          o_kp = ar.put(kp_f.data(), NS * 4), o_kd = ar.put(kd_f.data(), NS * 4), o_ar = ar.put(arest.data(), 3 * NA * 4),
+         o_hr = ar.put(ahrest_h.data(), NA * 16), o_pd = ar.put(pack_lds.data(), pack_lds.size() * 4),
          o_q = ar.put(&zero, 4 * 16);
   hipError_t he = hipMalloc(&M->arena, ar.off + 256);
   if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
@@ -441,7 +479,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       if (he != hipSuccess) { (void)hipFree(M->arena); delete M; return fail(ORCHARD_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(he)); }
     }
   }
-  const size_t scr_bytes = (size_t)N_FIELDS_ADJ * (size_t)std::max<int64_t>(NS, 1) * 4;
+  const int scr_nf = tun.adjoint_ckpt_max > 0 ? (int)N_FIELDS_ADJ : (int)N_FIELDS;
+  const size_t scr_bytes = (size_t)scr_nf * (size_t)((std::max<int64_t>(NS, 1) + 63) / 64) * 64 * 4;
   he = hipMalloc(&M->scr, scr_bytes);
   if (he != hipSuccess) { (void)hipFree(M->arena); delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc scratch: ") + hipGetErrorString(he)); }
   M->bytes = (int64_t)(ar.off + scr_bytes);
@@ -455,6 +494,10 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.apple_beg = (const int32_t*)(base + o_ab); dm.rq = (const float4*)(base + o_rq);
   dm.geo = (const float4*)(base + o_geo); dm.mmax = (const float*)(base + o_mm);
   dm.ahang = (const float4*)(base + o_ah); dm.apar = (const float4*)(base + o_ap);
+  dm.ahrest = (const float4*)(base + o_hr); dm.pack_lds = (const int32_t*)(base + o_pd);
+  dm.scr_nf = scr_nf;
+  dm.lds_cap = n_lds_packs > 0 ? tun.lds_width : 0;
+  M->lds_bytes = (size_t)dm.lds_cap * 2 * N_PUB_MAX * 4;
   M->kp0 = (float*)(base + o_kp); M->kd0 = (float*)(base + o_kd); M->apple_rest = (float*)(base + o_ar);
   dm.queue = (int32_t*)(base + o_q);
   dm.h = (float)d->dt;
@@ -470,11 +513,12 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&M->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   int per_cu = 1;
+  const int lb = (int)M->lds_bytes;
   switch (tun.threads) {
-    case 64: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<64>, 64, 0); break;
-    case 128: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<128>, 128, 0); break;
-    case 256: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<256>, 256, 0); break;
-    default: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<512>, 512, 0); break;
+    case 64: per_cu = lds_setup(k_step_packs<64>, k_step_persistent<64>, 64, lb); break;
+    case 128: per_cu = lds_setup(k_step_packs<128>, k_step_persistent<128>, 128, lb); break;
+    case 256: per_cu = lds_setup(k_step_packs<256>, k_step_persistent<256>, 256, lb); break;
+    default: per_cu = lds_setup(k_step_packs<512>, k_step_persistent<512>, 512, lb); break;
   }
   M->persist_blocks = std::max(1, std::min<int>(M->n_pack, std::max(1, per_cu) * std::max(1, M->n_cu)));
   if (tun.adjoint_ckpt_max > 0) {
@@ -564,6 +608,7 @@ int64_t orchard_ckpt_words(orchard_model_t m) {
 static orchard_status_t launch_steps(orchard_model_t m, const DevState& ds, const DevInputs& di, int k, int s_call,
                                      hipStream_t stream, bool save = false) {
   const int NT = m->tun.threads;
+  const unsigned lb = (unsigned)m->lds_bytes;
   if (save) {
     DevModel dm = m->dm;
     dm.save_adj = 1;
@@ -577,18 +622,18 @@ static orchard_status_t launch_steps(orchard_model_t m, const DevState& ds, cons
   } else if (m->tun.persistent) {
     const dim3 g(m->persist_blocks);
     switch (NT) {
-      case 64: hipLaunchKernelGGL(k_step_persistent<64>, g, dim3(64), 0, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
-      case 128: hipLaunchKernelGGL(k_step_persistent<128>, g, dim3(128), 0, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
-      case 256: hipLaunchKernelGGL(k_step_persistent<256>, g, dim3(256), 0, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
-      default: hipLaunchKernelGGL(k_step_persistent<512>, g, dim3(512), 0, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
+      case 64: hipLaunchKernelGGL(k_step_persistent<64>, g, dim3(64), lb, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
+      case 128: hipLaunchKernelGGL(k_step_persistent<128>, g, dim3(128), lb, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
+      case 256: hipLaunchKernelGGL(k_step_persistent<256>, g, dim3(256), lb, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
+      default: hipLaunchKernelGGL(k_step_persistent<512>, g, dim3(512), lb, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
     }
   } else {
     const dim3 g(m->n_pack);
     switch (NT) {
-      case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), 0, stream, m->dm, ds, di, k, s_call); break;
-      case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), 0, stream, m->dm, ds, di, k, s_call); break;
-      case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), 0, stream, m->dm, ds, di, k, s_call); break;
-      default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), 0, stream, m->dm, ds, di, k, s_call); break;
+      case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, stream, m->dm, ds, di, k, s_call); break;
+      case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), lb, stream, m->dm, ds, di, k, s_call); break;
+      case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lb, stream, m->dm, ds, di, k, s_call); break;
+      default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), lb, stream, m->dm, ds, di, k, s_call); break;
     }
   }
   HIPCHK(hipGetLastError());
@@ -777,6 +822,113 @@ orchard_status_t orchard_tips_backward(orchard_model_t m, const float* q, int32_
     default: hipLaunchKernelGGL(k_tip_bwd<512>, g, dim3(512), 0, hs, m->dm, (float2*)grad_q); break;
   }
   HIPCHK(hipGetLastError());
+  return ORCHARD_OK;
+}
+
+
+// ---- K-step graphs ----
+struct orchard_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+void orchard_graph_destroy(orchard_graph_t g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+orchard_status_t orchard_graph_create(orchard_model_t m, const orchard_state_t* s, const orchard_params_t* params,
+                                      const orchard_inputs_t* inputs, int32_t n_steps, orchard_graph_t* out) {
+  if (!m || !out) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  if (n_steps < 1) return fail(ORCHARD_ERR_INVALID_ARG, "n_steps must be >= 1");
+  *out = nullptr;
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  orchard_graph_s* g = new orchard_graph_s();
+  hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (he != hipSuccess) {
+    (void)hipStreamDestroy(cs); delete g;
+    return fail(ORCHARD_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(he));
+  }
+  const orchard_status_t st = orchard_step(m, s, params, inputs, n_steps, nullptr, 0, (orchard_stream_t)cs);
+  const std::string msg = st ? g_err : std::string();
+  he = hipStreamEndCapture(cs, &g->graph);
+  (void)hipStreamDestroy(cs);
+  if (st) { orchard_graph_destroy(g); return fail(st, msg); }
+  if (he != hipSuccess) { orchard_graph_destroy(g); return fail(ORCHARD_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(he)); }
+  he = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (he != hipSuccess) { orchard_graph_destroy(g); return fail(ORCHARD_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(he)); }
+  *out = g;
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_graph_launch(orchard_graph_t g, orchard_stream_t stream) {
+  if (!g || !g->exec) return fail(ORCHARD_ERR_INVALID_ARG, "null graph");
+  HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return ORCHARD_OK;
+}
+
+// ---- autotuner ----
+orchard_status_t orchard_autotune(const orchard_model_desc_t* d, const orchard_tuning_t* cand, int32_t n_cand,
+                                  int32_t n_warm, int32_t n_steps, orchard_tuning_t* best, float* ms_out,
+                                  orchard_stream_t stream) {
+  if (!d || !cand || !best) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  if (n_cand < 1 || n_steps < 1 || n_warm < 0) return fail(ORCHARD_ERR_INVALID_ARG, "need n_candidates >= 1, n_steps >= 1, n_warm >= 0");
+  hipStream_t hs = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(ORCHARD_ERR_HIP, "hipEventCreate"); }
+  void* buf = nullptr;
+  float best_ms = -1.f;
+  orchard_status_t first_err = ORCHARD_OK;
+  std::string first_msg;
+  for (int c = 0; c < n_cand; ++c) {
+    if (ms_out) ms_out[c] = -1.f;
+    orchard_tuning_t t = cand[c];
+    t.adjoint_ckpt_max = 0;
+    orchard_model_t m = nullptr;
+    orchard_status_t st = orchard_model_create(d, &t, &m);
+    if (st) { if (!first_err) { first_err = st; first_msg = g_err; } continue; }
+    const int64_t NS = m->n_seg, NA = m->n_apple, B = m->n_env;
+    auto al = [](int64_t b) { return (size_t)((b + 255) & ~int64_t(255)); };
+    const size_t sz = 4 * al(8 * NS) + al(52 * NA) + al(2 * NS) + al(4 * NA) + al(4 * (NS + NA)) + al(4 * B) + al(8);
+    if (!buf && hipMalloc(&buf, sz) != hipSuccess) {
+      orchard_model_destroy(m); (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+      return fail(ORCHARD_ERR_OUT_OF_MEMORY, "autotune state");
+    }
+    char* w = (char*)buf;
+    auto take = [&](int64_t b) { char* r = w; w += al(b); return r; };
+    orchard_state_t S{};
+    S.q = (float*)take(8 * NS); S.qd = (float*)take(8 * NS);
+    float* kp = (float*)take(8 * NS); float* kd = (float*)take(8 * NS);
+    S.apple = (float*)take(52 * NA); S.seg_evt = (uint8_t*)take(2 * NS); S.apple_evt = (uint8_t*)take(4 * NA);
+    S.evt_step = (int32_t*)take(4 * (NS + NA)); S.env_status = (uint32_t*)take(4 * B); S.step = (int64_t*)take(8);
+    orchard_params_t P{kp, kd};
+    float ms = -1.f;
+    st = orchard_default_params(m, kp, kd, stream);
+    if (!st) st = orchard_state_rest(m, &S, stream);
+    if (!st && n_warm > 0) st = orchard_step(m, &S, &P, nullptr, n_warm, nullptr, 0, stream);
+    if (!st && hipEventRecord(e0, hs) != hipSuccess) st = fail(ORCHARD_ERR_HIP, "hipEventRecord");
+    if (!st) st = orchard_step(m, &S, &P, nullptr, n_steps, nullptr, 0, stream);
+    if (!st && hipEventRecord(e1, hs) != hipSuccess) st = fail(ORCHARD_ERR_HIP, "hipEventRecord");
+    if (!st && hipEventSynchronize(e1) != hipSuccess) st = fail(ORCHARD_ERR_HIP, "hipEventSynchronize");
+    if (!st && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = fail(ORCHARD_ERR_HIP, "hipEventElapsedTime");
+    (void)hipStreamSynchronize(hs);
+    orchard_model_destroy(m);
+    if (st) {
+      (void)hipFree(buf); (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+      return st;
+    }
+    ms /= (float)n_steps;
+    if (ms_out) ms_out[c] = ms;
+    if (best_ms < 0.f || ms < best_ms) { best_ms = ms; *best = cand[c]; }
+  }
+  if (buf) (void)hipFree(buf);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_ms < 0.f) return fail(first_err ? first_err : ORCHARD_ERR_INVALID_ARG, first_msg.empty() ? "no candidate built" : first_msg);
   return ORCHARD_OK;
 }
 

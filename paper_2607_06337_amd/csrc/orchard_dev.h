@@ -6,56 +6,62 @@
 namespace orchard {
 
 // ---- scratch fields: one float per node per field, field f at scr + f * n_seg -----------
-// down-pass publication of a node, read by its children (world axes, at the node's tip)
+// A node's "publication" is what its neighbours on the next level read: children in the
+// down passes, the parent in the up pass.  Packs whose levels fit the workgroup keep
+// publications in LDS (double-buffered by level parity); wide packs and the adjoint's
+// recompute keep them in these global fields.
 enum : int {
+  // down pass 1 publication (25), values at the node's tip point
   F_R = 0,          // 9: body rotation, row major
-  F_DR = 9,         // 9: body rotation minus its rest value, row major
-  F_DPT = 18,       // 3: tip point minus its rest value (= children's joint point)
-  F_W = 21,         // 3: angular velocity
-  F_VT = 24,        // 3: linear velocity of the tip point
-  F_AVA = 27,       // 3: velocity-product (+ base) acceleration at the tip, angular
-  F_AVL = 30,       // 3:   linear
-  F_SNAP = 33,      // 1: snapped flag
+  F_PT = 9,         // 3: tip point (absolute; only detached apples use positions)
+  F_W = 12,         // 3: angular velocity
+  F_VT = 15,        // 3: linear velocity of the tip point
+  F_AVA = 18,       // 3: velocity-product (+ base) acceleration at the tip, angular
+  F_AVL = 21,       // 3:   linear
+  F_SNAP = 24,      // 1: snapped flag
+  N_PUB1 = 25,
   // node-private data kept from the down pass for the up pass
-  F_A0 = 34,        // 3: joint axis x (world)
-  F_A1 = 37,        // 3: joint axis y (world)
-  F_C = 40,         // 6: velocity-product acceleration c (ang, lin)
-  F_P = 46,         // 6: bias force p (ang, lin) incl. applied forces
-  F_MO = 52,        // 1: own mass (+ virtual apple masses)
-  F_HO = 53,        // 3: own first moment about the joint point
-  F_JO = 56,        // 6: own rotational inertia about the joint (xx yy zz xy xz yz)
-  F_TAU = 62,       // 2: spring/damper torque
-  F_DG = 64,        // 1: implicit diagonal h kd + h^2 kp
-  F_LZ = 65,        // 3: l * z (joint point -> tip)
-  F_SKIP = 68,      // 1: env frozen at the start of this step
-  // up-pass publication (articulated inertia and bias at the node's joint point)
-  F_IA = 69,        // 6: A (rotational block, sym)
-  F_IB = 75,        // 9: B (coupling block, row major)
-  F_IM = 84,        // 6: M (linear block, sym)
-  F_PA = 90,        // 6: bias (ang, lin)
+  F_A0 = 25,        // 3: joint axis x (world)
+  F_A1 = 28,        // 3: joint axis y (world)
+  F_C = 31,         // 6: velocity-product acceleration c (ang, lin)
+  F_P = 37,         // 6: bias force p (ang, lin) incl. applied forces
+  F_MO = 43,        // 1: own mass (+ virtual apple masses)
+  F_HO = 44,        // 3: own first moment about the joint point
+  F_JO = 47,        // 6: own rotational inertia about the joint (xx yy zz xy xz yz)
+  F_TAU = 53,       // 2: spring/damper torque
+  F_DG = 55,        // 1: implicit diagonal h kd + h^2 kp
+  F_LZ = 56,        // 3: l * z (joint point -> tip)
+  F_SKIP = 59,      // 1: env frozen at the start of this step
+  // up-pass publication (27): articulated inertia and bias at the node's joint point
+  F_IA = 60,        // 6: A (rotational block, sym)
+  F_IB = 66,        // 9: B (coupling block, row major)
+  F_IM = 75,        // 6: M (linear block, sym)
+  F_PA = 81,        // 6: bias (ang, lin)
+  N_PUBU = 27,
   // node-private factor data for the second down pass
-  F_U = 96,         // 12: U = I^A S (col 0: ang 3 lin 3, col 1: ang 3 lin 3)
-  F_DI = 108,       // 3: D^-1 (00 01 11)
-  F_UU = 111,       // 2: u = tau - S^T p^A
-  N_FIELDS = 113,
-  // second down pass publication overwrites the first six fields
+  F_U = 87,         // 12: U = I^A S (col 0: ang 3 lin 3, col 1: ang 3 lin 3)
+  F_DI = 99,        // 3: D^-1 (00 01 11)
+  F_UU = 102,       // 2: u = tau - S^T p^A
+  N_FIELDS = 104,
+  // second down pass publication (6) overwrites the first six fields
   F_AT = 0,         // 6: acceleration at the tip (ang, lin)
-  // ---- fields of the adjoint (allocated only when the model supports it) ----
+  N_PUB_MAX = 27,
+  // ---- fields of the adjoint ----
   // saved by the forward step in save mode
-  F_SR = 113,       // 9: body rotation, row major
-  F_SAVP = 122,     // 6: velocity-product (+ base) acceleration at the joint point
-  F_SIA = 128,      // 21: articulated inertia before the pivot update (A 6, B 9, M 6)
-  F_SPA = 149,      // 6: articulated bias before the pivot update
-  F_SA = 155,       // 6: total acceleration at the joint point
-  F_SQDD = 161,     // 2: joint accelerations
+  F_SR = 104,       // 9: body rotation, row major
+  F_SAVP = 113,     // 6: velocity-product (+ base) acceleration at the joint point
+  F_SIA = 119,      // 21: articulated inertia before the pivot update (A 6, B 9, M 6)
+  F_SPA = 140,      // 6: articulated bias before the pivot update
+  F_SA = 146,       // 6: total acceleration at the joint point
+  F_SQDD = 152,     // 2: joint accelerations
   // adjoint passes
-  F_LU = 163,       // 2: u of the solve M lambda = qdd_bar
-  F_LPA = 165,      // 6: bias of that solve passed to the parent
-  F_LA = 171,       // 6: acceleration of that solve at the tip
-  F_NU = 177,       // 6: virtual velocity nu at the joint point
-  F_LAM = 183,      // 2: lambda
-  F_RB = 185,       // 24: reverse-pass publication: tau_bar 3, omega_bar 3, vt_bar 3, At_bar 6, Avt_bar 6, f_lin 3
-  N_FIELDS_ADJ = 209
+  F_LU = 154,       // 2: u of the solve M lambda = qdd_bar
+  F_LPA = 156,      // 6: bias of that solve passed to the parent
+  F_LA = 162,       // 6: acceleration of that solve at the tip
+  F_NU = 168,       // 6: virtual velocity nu at the joint point
+  F_LAM = 174,      // 2: lambda
+  F_RB = 176,       // 24: reverse-pass publication: tau_bar 3, omega_bar 3, vt_bar 3, At_bar 6, Avt_bar 6, f_lin 3
+  N_FIELDS_ADJ = 200
 };
 
 struct DevModel {
@@ -65,6 +71,7 @@ struct DevModel {
   const int32_t* pack_node;
   const int32_t* pack_lvl;
   const int32_t* lvl_off;
+  const int32_t* pack_lds;   // 1: every level of the pack fits the workgroup (LDS publications)
   // per node (internal order)
   const int32_t* par;        // parent node, -1 = world
   const int32_t* child;      // first child node
@@ -78,17 +85,27 @@ struct DevModel {
   // per apple (internal order)
   const float4* ahang;       // (hang x, y, z in the segment frame, mass)
   const float4* apar;        // (f_det, c_s, F_max, unused)
+  const float4* ahrest;      // rest hang point (x, y, z, unused): origin of a detached apple's position
   // constants
   float h, gx, gy, gz, ks, alpha, vcap, pad;
   int32_t n_break, n_pull, n_tension, use_rng;
   uint64_t seed;
   uint32_t rng_thr;
   float wsig;
-  float* scr;                // [N_FIELDS or N_FIELDS_ADJ][n_seg]
+  float* scr;                // blocks of 64 nodes, each [scr_nf][64] floats (see scr_idx)
   int32_t* queue;            // persistent-kernel pack counter(s)
-  int32_t save_adj;          // forward step also writes the F_S* fields
+  int32_t save_adj;          // forward step also writes the F_S* fields (global exchange only)
+  int32_t scr_nf;            // fields per node: N_FIELDS, or N_FIELDS_ADJ with adjoint support
+  int32_t lds_cap;           // LDS exchange capacity in nodes per level (0: global exchange)
   int32_t pad1;
 };
+
+// Scratch layout: nodes in blocks of 64 (one wavefront), each block [scr_nf][64].  A node's
+// fields then sit in one ~26-50 KB window instead of scr_nf streams n_seg apart, which keeps
+// DRAM rows and TLB entries shared across the fields a wavefront touches.
+__device__ __forceinline__ size_t scr_idx(const DevModel& M, int f, int i) {
+  return ((size_t)(i >> 6) * (size_t)M.scr_nf + (size_t)f) * 64u + (size_t)(i & 63);
+}
 
 struct DevState {
   float2* q;

@@ -9,40 +9,73 @@
 //          implicit-Euler update of the joint state.
 // Spatial quantities of a node live at its joint point with world-aligned axes, so
 // moving them between parent and child is a pure translation by l z.
+//
+// What a node hands to the next level (its "publication") goes through LDS when every
+// level of the pack fits the workgroup's exchange buffer, double-buffered by level
+// parity and indexed by the node's slot within its level; otherwise (very wide packs,
+// and the adjoint's recompute, which reads these values back) through global scratch.
 #include "orchard_dev.h"
 
 namespace orchard {
 
-__device__ __forceinline__ float ld(const DevModel& M, int f, int i) { return M.scr[(size_t)f * M.n_seg + i]; }
-__device__ __forceinline__ void sto(const DevModel& M, int f, int i, float v) { M.scr[(size_t)f * M.n_seg + i] = v; }
+__device__ __forceinline__ float ld(const DevModel& M, int f, int i) { return M.scr[scr_idx(M, f, i)]; }
+__device__ __forceinline__ void sto(const DevModel& M, int f, int i, float v) { M.scr[scr_idx(M, f, i)] = v; }
 __device__ __forceinline__ V3 ld3(const DevModel& M, int f, int i) { return v3(ld(M, f, i), ld(M, f + 1, i), ld(M, f + 2, i)); }
 __device__ __forceinline__ void sto3(const DevModel& M, int f, int i, V3 v) { sto(M, f, i, v.x); sto(M, f + 1, i, v.y); sto(M, f + 2, i, v.z); }
+
+// publication access: field f of a publication block starting at field f0, of node i
+// (slot s within its level, level-parity buffer b)
+template <bool XL>
+__device__ __forceinline__ float xget(const DevModel& M, const float* X, int f0, int f, int i, int s, int b) {
+  if constexpr (XL) return X[(b * N_PUB_MAX + (f - f0)) * M.lds_cap + s];
+  else return ld(M, f, i);
+}
+template <bool XL>
+__device__ __forceinline__ void xput(const DevModel& M, float* X, int f0, int f, int i, int s, int b, float v) {
+  if constexpr (XL) X[(b * N_PUB_MAX + (f - f0)) * M.lds_cap + s] = v;
+  else sto(M, f, i, v);
+}
+template <bool XL>
+__device__ __forceinline__ V3 xget3(const DevModel& M, const float* X, int f0, int f, int i, int s, int b) {
+  return v3(xget<XL>(M, X, f0, f, i, s, b), xget<XL>(M, X, f0, f + 1, i, s, b), xget<XL>(M, X, f0, f + 2, i, s, b));
+}
+template <bool XL>
+__device__ __forceinline__ void xput3(const DevModel& M, float* X, int f0, int f, int i, int s, int b, V3 v) {
+  xput<XL>(M, X, f0, f, i, s, b, v.x); xput<XL>(M, X, f0, f + 1, i, s, b, v.y); xput<XL>(M, X, f0, f + 2, i, s, b, v.z);
+}
 
 __device__ __forceinline__ bool finite3(V3 a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
 
 // ------------------------------------------------------------------------------------------
 // down pass 1
 // ------------------------------------------------------------------------------------------
-__device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs& I, int i, int64_t n, int s_call) {
+// i: node, s: its slot in its level, b: its level's buffer, pb: first node of the parent level
+template <bool XL>
+__device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs& I, float* X, int i, int s, int b,
+                           int pb, int64_t n, int s_call) {
   const int NS = M.n_seg;
   const int e = M.env[i];
   const bool skip = S.status[e] != 0u;
   sto(M, F_SKIP, i, skip ? 1.f : 0.f);
   if (skip) return;
   const int par = M.par[i];
-  Mat3 Rp, dRp;
-  V3 dpt, w, vt, Aa, Al;
+  Mat3 Rp;
+  V3 pj, w, vt, Aa, Al;
   bool snp;
   if (par < 0) {
-    for (int k = 0; k < 9; ++k) { Rp.m[k] = (k % 4 == 0) ? 1.f : 0.f; dRp.m[k] = 0.f; }
-    dpt = v3(0, 0, 0); w = dpt; vt = dpt; Aa = dpt;
+    for (int k = 0; k < 9; ++k) Rp.m[k] = (k % 4 == 0) ? 1.f : 0.f;
+    pj = v3(0, 0, 0); w = pj; vt = pj; Aa = pj;
     Al = v3(-M.gx, -M.gy, -M.gz);  // gravity as a base acceleration
     snp = false;
   } else {
-    for (int k = 0; k < 9; ++k) { Rp.m[k] = ld(M, F_R + k, par); dRp.m[k] = ld(M, F_DR + k, par); }
-    dpt = ld3(M, F_DPT, par); w = ld3(M, F_W, par); vt = ld3(M, F_VT, par);
-    Aa = ld3(M, F_AVA, par); Al = ld3(M, F_AVL, par);
-    snp = ld(M, F_SNAP, par) != 0.f;
+    const int ps = par - pb, bp = b ^ 1;
+    for (int k = 0; k < 9; ++k) Rp.m[k] = xget<XL>(M, X, F_R, F_R + k, par, ps, bp);
+    pj = xget3<XL>(M, X, F_R, F_PT, par, ps, bp);
+    w = xget3<XL>(M, X, F_R, F_W, par, ps, bp);
+    vt = xget3<XL>(M, X, F_R, F_VT, par, ps, bp);
+    Aa = xget3<XL>(M, X, F_R, F_AVA, par, ps, bp);
+    Al = xget3<XL>(M, X, F_R, F_AVL, par, ps, bp);
+    snp = xget<XL>(M, X, F_R, F_SNAP, par, ps, bp) != 0.f;
   }
   const float2 q = S.q[i], qd = S.qd[i];
   const float kp = I.kp[i], kd = I.kd[i];
@@ -63,10 +96,7 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
   snp = snp || brk;
 
   // ---- kinematics: R = R_parent Q_rest R_x(theta_x) R_y(theta_y) ----
-  // Positions are kept as displacements from the rest pose: with J = R_parent Q and
-  // E = R_x R_y,  R - R_rest = J (E - I) + (R_parent - R_parent,rest) Q, where E - I is
-  // formed from half-angle sines.  The rounding error then scales with the (small)
-  // displacement, which keeps the stiff apple tether free of position round-off.
+  // the joint rotations are formed from half-angle sines (1 - cos = 2 sin^2(theta/2))
   const float4 r = M.rq[i];
   Mat3 Q;
   {
@@ -75,23 +105,18 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
     Q.m[3] = 2.f * (xx * yy + ww * zz); Q.m[4] = 1.f - 2.f * (xx * xx + zz * zz); Q.m[5] = 2.f * (yy * zz - ww * xx);
     Q.m[6] = 2.f * (xx * zz - ww * yy); Q.m[7] = 2.f * (yy * zz + ww * xx); Q.m[8] = 1.f - 2.f * (xx * xx + yy * yy);
   }
-  V3 J0, J1, J2;  // columns of J = R_parent Q
-  const V3 Q0 = v3(Q.m[0], Q.m[3], Q.m[6]), Q1 = v3(Q.m[1], Q.m[4], Q.m[7]), Q2 = v3(Q.m[2], Q.m[5], Q.m[8]);
-  J0 = mul(Rp, Q0);
-  J1 = mul(Rp, Q1);
-  J2 = mul(Rp, Q2);
-  const V3 W0 = mul(dRp, Q0), W1 = mul(dRp, Q1), W2 = mul(dRp, Q2);  // (R_parent - rest) Q
+  // columns of J = R_parent Q
+  const V3 J0 = mul(Rp, v3(Q.m[0], Q.m[3], Q.m[6]));
+  const V3 J1 = mul(Rp, v3(Q.m[1], Q.m[4], Q.m[7]));
+  const V3 J2 = mul(Rp, v3(Q.m[2], Q.m[5], Q.m[8]));
   float shx, chx, shy, chy;
   sincosf(0.5f * q.x, &shx, &chx);
   sincosf(0.5f * q.y, &shy, &chy);
-  const float sx = 2.f * shx * chx, cxm = -2.f * shx * shx, cx = 1.f + cxm;
-  const float sy = 2.f * shy * chy, cym = -2.f * shy * shy, cy = 1.f + cym;
+  const float sx = 2.f * shx * chx, cx = 1.f - 2.f * shx * shx;
+  const float sy = 2.f * shy * chy, cy = 1.f - 2.f * shy * shy;
   const V3 c0 = fma3(cy, J0, fma3(sx * sy, J1, (-cx * sy) * J2));
   const V3 c1 = fma3(cx, J1, sx * J2);
   const V3 c2 = fma3(sy, J0, fma3(-sx * cy, J1, (cx * cy) * J2));
-  const V3 d0 = fma3(cym, J0, fma3(sx * sy, J1, fma3(-cx * sy, J2, W0)));
-  const V3 d1 = fma3(cxm, J1, fma3(sx, J2, W1));
-  const V3 d2 = fma3(sy, J0, fma3(-sx * cy, J1, fma3(fmaf(cxm, cy, cym), J2, W2)));
   const V3 a0 = J0, a1 = c1, z = c2;
 
   // ---- velocities and velocity-product acceleration (at the joint point) ----
@@ -104,19 +129,16 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
 
   // ---- publish for children (values at the tip point) ----
   const V3 lz = l * z;
-  sto(M, F_R + 0, i, c0.x); sto(M, F_R + 1, i, c1.x); sto(M, F_R + 2, i, c2.x);
-  sto(M, F_R + 3, i, c0.y); sto(M, F_R + 4, i, c1.y); sto(M, F_R + 5, i, c2.y);
-  sto(M, F_R + 6, i, c0.z); sto(M, F_R + 7, i, c1.z); sto(M, F_R + 8, i, c2.z);
-  sto(M, F_DR + 0, i, d0.x); sto(M, F_DR + 1, i, d1.x); sto(M, F_DR + 2, i, d2.x);
-  sto(M, F_DR + 3, i, d0.y); sto(M, F_DR + 4, i, d1.y); sto(M, F_DR + 5, i, d2.y);
-  sto(M, F_DR + 6, i, d0.z); sto(M, F_DR + 7, i, d1.z); sto(M, F_DR + 8, i, d2.z);
-  sto3(M, F_DPT, i, fma3(l, d2, dpt));
-  sto3(M, F_W, i, wi);
-  sto3(M, F_VT, i, v + cross(wi, lz));
-  sto3(M, F_AVA, i, Ava);
-  sto3(M, F_AVL, i, Avl + cross(Ava, lz));
-  sto(M, F_SNAP, i, snp ? 1.f : 0.f);
-  if (M.save_adj) {
+  xput<XL>(M, X, F_R, F_R + 0, i, s, b, c0.x); xput<XL>(M, X, F_R, F_R + 1, i, s, b, c1.x); xput<XL>(M, X, F_R, F_R + 2, i, s, b, c2.x);
+  xput<XL>(M, X, F_R, F_R + 3, i, s, b, c0.y); xput<XL>(M, X, F_R, F_R + 4, i, s, b, c1.y); xput<XL>(M, X, F_R, F_R + 5, i, s, b, c2.y);
+  xput<XL>(M, X, F_R, F_R + 6, i, s, b, c0.z); xput<XL>(M, X, F_R, F_R + 7, i, s, b, c1.z); xput<XL>(M, X, F_R, F_R + 8, i, s, b, c2.z);
+  xput3<XL>(M, X, F_R, F_PT, i, s, b, pj + lz);
+  xput3<XL>(M, X, F_R, F_W, i, s, b, wi);
+  xput3<XL>(M, X, F_R, F_VT, i, s, b, v + cross(wi, lz));
+  xput3<XL>(M, X, F_R, F_AVA, i, s, b, Ava);
+  xput3<XL>(M, X, F_R, F_AVL, i, s, b, Avl + cross(Ava, lz));
+  xput<XL>(M, X, F_R, F_SNAP, i, s, b, snp ? 1.f : 0.f);
+  if (!XL && M.save_adj) {
     sto(M, F_SR + 0, i, c0.x); sto(M, F_SR + 1, i, c1.x); sto(M, F_SR + 2, i, c2.x);
     sto(M, F_SR + 3, i, c0.y); sto(M, F_SR + 4, i, c1.y); sto(M, F_SR + 5, i, c2.y);
     sto(M, F_SR + 6, i, c0.z); sto(M, F_SR + 7, i, c1.z); sto(M, F_SR + 8, i, c2.z);
@@ -162,9 +184,7 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
     const V3 sig = v3(P[a], P[NA + a], P[2 * NA + a]);
     V3 va = v3(P[3 * NA + a], P[4 * NA + a], P[5 * NA + a]);
     const uint8_t det0 = S.apple_evt[a];
-    V3 sa;
-    if (det0) sa = sig - (dpt + fma3(hm.x, d0, fma3(hm.y, d1, hm.z * d2)));
-    else sa = fma3(-h, vh, sig);
+    const V3 sa = det0 ? v3(0, 0, 0) : fma3(-h, vh, sig);
     V3 Fa = v3(0, 0, 0);
     if (I.aforce) {
       const float* fp = I.aforce + (int64_t)s_call * I.aforce_stride + 3 * (int64_t)a;
@@ -218,7 +238,14 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
     if (!det) fa = fa - M.ks * sa - cs * va;
     va = fma3(h / ma, fa, va);
     // attached: sigma+ = s + h v+;  detached: (x - x_hang,rest)+ = x - x_hang,rest + h v+
-    const V3 base = det ? (det0 ? sig : (dpt + fma3(hm.x, d0, fma3(hm.y, d1, hm.z * d2))) + sa) : sa;
+    V3 base = sa;
+    if (det) {
+      if (det0) base = sig;
+      else {
+        const float4 hr = M.ahrest[a];
+        base = (pj + d - v3(hr.x, hr.y, hr.z)) + sa;
+      }
+    }
     const V3 x = fma3(h, va, base);
     P[a] = x.x; P[NA + a] = x.y; P[2 * NA + a] = x.z;
     P[3 * NA + a] = va.x; P[4 * NA + a] = va.y; P[5 * NA + a] = va.z;
@@ -262,7 +289,9 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
 // ------------------------------------------------------------------------------------------
 // up pass: gather children's articulated inertia / bias, factor the 2x2 pivot
 // ------------------------------------------------------------------------------------------
-__device__ void node_up(const DevModel& M, int i) {
+// i: node, s: its slot, b: its level's buffer, nb: first node of the next level
+template <bool XL>
+__device__ void node_up(const DevModel& M, float* X, int i, int s, int b, int nb) {
   if (ld(M, F_SKIP, i) != 0.f) return;
   Sym3 A{0, 0, 0, 0, 0, 0}, Mm{0, 0, 0, 0, 0, 0};
   Mat3 B;
@@ -270,13 +299,16 @@ __device__ void node_up(const DevModel& M, int i) {
   V3 pn = v3(0, 0, 0), pf = v3(0, 0, 0);
   const int cb = M.child[i], ce = cb + M.nchild[i];
   for (int c = cb; c < ce; ++c) {
-    A.xx += ld(M, F_IA + 0, c); A.yy += ld(M, F_IA + 1, c); A.zz += ld(M, F_IA + 2, c);
-    A.xy += ld(M, F_IA + 3, c); A.xz += ld(M, F_IA + 4, c); A.yz += ld(M, F_IA + 5, c);
-    for (int k = 0; k < 9; ++k) B.m[k] += ld(M, F_IB + k, c);
-    Mm.xx += ld(M, F_IM + 0, c); Mm.yy += ld(M, F_IM + 1, c); Mm.zz += ld(M, F_IM + 2, c);
-    Mm.xy += ld(M, F_IM + 3, c); Mm.xz += ld(M, F_IM + 4, c); Mm.yz += ld(M, F_IM + 5, c);
-    pn = pn + ld3(M, F_PA, c);
-    pf = pf + ld3(M, F_PA + 3, c);
+    const int cs = c - nb, bc = b ^ 1;
+#define XG(f) xget<XL>(M, X, F_IA, (f), c, cs, bc)
+    A.xx += XG(F_IA + 0); A.yy += XG(F_IA + 1); A.zz += XG(F_IA + 2);
+    A.xy += XG(F_IA + 3); A.xz += XG(F_IA + 4); A.yz += XG(F_IA + 5);
+    for (int k = 0; k < 9; ++k) B.m[k] += XG(F_IB + k);
+    Mm.xx += XG(F_IM + 0); Mm.yy += XG(F_IM + 1); Mm.zz += XG(F_IM + 2);
+    Mm.xy += XG(F_IM + 3); Mm.xz += XG(F_IM + 4); Mm.yz += XG(F_IM + 5);
+    pn = pn + v3(XG(F_PA + 0), XG(F_PA + 1), XG(F_PA + 2));
+    pf = pf + v3(XG(F_PA + 3), XG(F_PA + 4), XG(F_PA + 5));
+#undef XG
   }
   const V3 r = ld3(M, F_LZ, i);
   if (ce > cb) {
@@ -309,7 +341,7 @@ __device__ void node_up(const DevModel& M, int i) {
     pn = pn + ld3(M, F_P, i);
     pf = pf + ld3(M, F_P + 3, i);
   }
-  if (M.save_adj) {
+  if (!XL && M.save_adj) {
     sto(M, F_SIA + 0, i, A.xx); sto(M, F_SIA + 1, i, A.yy); sto(M, F_SIA + 2, i, A.zz);
     sto(M, F_SIA + 3, i, A.xy); sto(M, F_SIA + 4, i, A.xz); sto(M, F_SIA + 5, i, A.yz);
     for (int k = 0; k < 9; ++k) sto(M, F_SIA + 6 + k, i, B.m[k]);
@@ -344,12 +376,15 @@ __device__ void node_up(const DevModel& M, int i) {
   const V3 ca = ld3(M, F_C, i), cl = ld3(M, F_C + 3, i);
   pn = pn + mul(A, ca) + mul(B, cl) + fma3(uu0, W0a, uu1 * W1a);
   pf = pf + mulT(B, ca) + mul(Mm, cl) + fma3(uu0, W0l, uu1 * W1l);
-  sto(M, F_IA + 0, i, A.xx); sto(M, F_IA + 1, i, A.yy); sto(M, F_IA + 2, i, A.zz);
-  sto(M, F_IA + 3, i, A.xy); sto(M, F_IA + 4, i, A.xz); sto(M, F_IA + 5, i, A.yz);
-  for (int k = 0; k < 9; ++k) sto(M, F_IB + k, i, B.m[k]);
-  sto(M, F_IM + 0, i, Mm.xx); sto(M, F_IM + 1, i, Mm.yy); sto(M, F_IM + 2, i, Mm.zz);
-  sto(M, F_IM + 3, i, Mm.xy); sto(M, F_IM + 4, i, Mm.xz); sto(M, F_IM + 5, i, Mm.yz);
-  sto3(M, F_PA, i, pn); sto3(M, F_PA + 3, i, pf);
+#define XP(f, v) xput<XL>(M, X, F_IA, (f), i, s, b, (v))
+  XP(F_IA + 0, A.xx); XP(F_IA + 1, A.yy); XP(F_IA + 2, A.zz);
+  XP(F_IA + 3, A.xy); XP(F_IA + 4, A.xz); XP(F_IA + 5, A.yz);
+  for (int k = 0; k < 9; ++k) XP(F_IB + k, B.m[k]);
+  XP(F_IM + 0, Mm.xx); XP(F_IM + 1, Mm.yy); XP(F_IM + 2, Mm.zz);
+  XP(F_IM + 3, Mm.xy); XP(F_IM + 4, Mm.xz); XP(F_IM + 5, Mm.yz);
+  XP(F_PA + 0, pn.x); XP(F_PA + 1, pn.y); XP(F_PA + 2, pn.z);
+  XP(F_PA + 3, pf.x); XP(F_PA + 4, pf.y); XP(F_PA + 5, pf.z);
+#undef XP
   sto3(M, F_U, i, U0a); sto3(M, F_U + 3, i, U0l); sto3(M, F_U + 6, i, U1a); sto3(M, F_U + 9, i, U1l);
   sto(M, F_DI, i, Di00); sto(M, F_DI + 1, i, Di01); sto(M, F_DI + 2, i, Di11);
   sto(M, F_UU, i, uu0); sto(M, F_UU + 1, i, uu1);
@@ -358,12 +393,18 @@ __device__ void node_up(const DevModel& M, int i) {
 // ------------------------------------------------------------------------------------------
 // down pass 2: accelerations and integration
 // ------------------------------------------------------------------------------------------
-__device__ void node_down2(const DevModel& M, const DevState& S, int i) {
+// i: node, s: its slot, b: its level's buffer, pb: first node of the parent level
+template <bool XL>
+__device__ void node_down2(const DevModel& M, const DevState& S, float* X, int i, int s, int b, int pb) {
   if (ld(M, F_SKIP, i) != 0.f) return;
   const int par = M.par[i];
   V3 Aa, Al;
   if (par < 0) { Aa = v3(0, 0, 0); Al = v3(-M.gx, -M.gy, -M.gz); }
-  else { Aa = ld3(M, F_AT, par); Al = ld3(M, F_AT + 3, par); }
+  else {
+    const int ps = par - pb, bp = b ^ 1;
+    Aa = xget3<XL>(M, X, F_AT, F_AT, par, ps, bp);
+    Al = xget3<XL>(M, X, F_AT, F_AT + 3, par, ps, bp);
+  }
   Aa = Aa + ld3(M, F_C, i);
   Al = Al + ld3(M, F_C + 3, i);
   const V3 U0a = ld3(M, F_U, i), U0l = ld3(M, F_U + 3, i), U1a = ld3(M, F_U + 6, i), U1l = ld3(M, F_U + 9, i);
@@ -375,12 +416,12 @@ __device__ void node_down2(const DevModel& M, const DevState& S, int i) {
   const V3 a0 = ld3(M, F_A0, i), a1 = ld3(M, F_A1, i);
   Aa = fma3(qdd0, a0, fma3(qdd1, a1, Aa));
   const V3 lz = ld3(M, F_LZ, i);
-  if (M.save_adj) {
+  if (!XL && M.save_adj) {
     sto3(M, F_SA, i, Aa); sto3(M, F_SA + 3, i, Al);
     sto(M, F_SQDD, i, qdd0); sto(M, F_SQDD + 1, i, qdd1);
   }
-  sto3(M, F_AT, i, Aa);
-  sto3(M, F_AT + 3, i, Al + cross(Aa, lz));
+  xput3<XL>(M, X, F_AT, F_AT, i, s, b, Aa);
+  xput3<XL>(M, X, F_AT, F_AT + 3, i, s, b, Al + cross(Aa, lz));
   const float h = M.h;
   float2 q = S.q[i], qd = S.qd[i];
   qd.x = fmaf(h, qdd0, qd.x);
@@ -395,41 +436,50 @@ __device__ void node_down2(const DevModel& M, const DevState& S, int i) {
 // ------------------------------------------------------------------------------------------
 // pack kernels
 // ------------------------------------------------------------------------------------------
-template <int NT>
-__device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, const DevInputs& I, int pk,
+template <int NT, bool XL>
+__device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, const DevInputs& I, float* X, int pk,
                                          int64_t n0, int n_inner, int call_step0) {
   const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
-  for (int s = 0; s < n_inner; ++s) {
-    const int64_t n = n0 + s;
+  for (int st = 0; st < n_inner; ++st) {
+    const int64_t n = n0 + st;
     for (int lv = lb; lv < le; ++lv) {
-      const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
-      for (int i = a + (int)threadIdx.x; i < b; i += NT) node_down1(M, S, I, i, n, call_step0 + s);
+      const int a = M.lvl_off[lv], e = M.lvl_off[lv + 1], pb = lv > lb ? M.lvl_off[lv - 1] : a, b = (lv - lb) & 1;
+      for (int i = a + (int)threadIdx.x; i < e; i += NT) node_down1<XL>(M, S, I, X, i, i - a, b, pb, n, call_step0 + st);
       __syncthreads();
     }
     for (int lv = le - 1; lv >= lb; --lv) {
-      const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
-      for (int i = a + (int)threadIdx.x; i < b; i += NT) node_up(M, i);
+      const int a = M.lvl_off[lv], e = M.lvl_off[lv + 1], b = (lv - lb) & 1;
+      for (int i = a + (int)threadIdx.x; i < e; i += NT) node_up<XL>(M, X, i, i - a, b, e);
       __syncthreads();
     }
     for (int lv = lb; lv < le; ++lv) {
-      const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
-      for (int i = a + (int)threadIdx.x; i < b; i += NT) node_down2(M, S, i);
+      const int a = M.lvl_off[lv], e = M.lvl_off[lv + 1], pb = lv > lb ? M.lvl_off[lv - 1] : a, b = (lv - lb) & 1;
+      for (int i = a + (int)threadIdx.x; i < e; i += NT) node_down2<XL>(M, S, X, i, i - a, b, pb);
       __syncthreads();
     }
   }
 }
 
-// one workgroup per pack
+template <int NT>
+__device__ __forceinline__ void run_pack_any(const DevModel& M, const DevState& S, const DevInputs& I, float* X, int pk,
+                                             int64_t n0, int n_inner, int call_step0) {
+  if (M.lds_cap > 0 && !M.save_adj && M.pack_lds[pk]) run_pack<NT, true>(M, S, I, X, pk, n0, n_inner, call_step0);
+  else run_pack<NT, false>(M, S, I, X, pk, n0, n_inner, call_step0);
+}
+
+// one workgroup per pack; dynamic LDS: 2 * N_PUB_MAX * lds_cap floats
 template <int NT>
 __global__ __launch_bounds__(NT) void k_step_packs(DevModel M, DevState S, DevInputs I, int n_inner, int call_step0) {
+  extern __shared__ float xlds[];
   const int64_t n0 = *S.step;
-  run_pack<NT>(M, S, I, (int)blockIdx.x, n0, n_inner, call_step0);
+  run_pack_any<NT>(M, S, I, xlds, (int)blockIdx.x, n0, n_inner, call_step0);
 }
 
 // persistent grid: workgroups pull packs (largest first) from a counter
 template <int NT>
 __global__ __launch_bounds__(NT) void k_step_persistent(DevModel M, DevState S, DevInputs I, int n_inner,
                                                         int call_step0, int32_t* counter) {
+  extern __shared__ float xlds[];
   __shared__ int pk;
   const int64_t n0 = *S.step;
   for (;;) {
@@ -438,7 +488,7 @@ __global__ __launch_bounds__(NT) void k_step_persistent(DevModel M, DevState S, 
     const int p = pk;
     __syncthreads();
     if (p >= M.n_pack) break;
-    run_pack<NT>(M, S, I, p, n0, n_inner, call_step0);
+    run_pack_any<NT>(M, S, I, xlds, p, n0, n_inner, call_step0);
   }
 }
 

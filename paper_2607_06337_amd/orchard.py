@@ -33,9 +33,13 @@ class Desc(C.Structure):
         ("rng_seed", C.c_uint64), ("wrench_fraction", C.c_double), ("wrench_sigma", C.c_double)]
 
 
+# the library's defaults (orchard_model_create with a null tuning)
+DEFAULT_TUNING = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0, adjoint_ckpt_max=0, lds_width=256)
+
+
 class Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("pack_fill", C.c_float), ("steps_per_launch", C.c_int32),
-                ("persistent", C.c_int32), ("adjoint_ckpt_max", C.c_int32)]
+                ("persistent", C.c_int32), ("adjoint_ckpt_max", C.c_int32), ("lds_width", C.c_int32)]
 
 
 class CAdjoint(C.Structure):
@@ -69,7 +73,8 @@ EXPORTS = ("orchard_model_create", "orchard_model_destroy", "orchard_model_layou
            "orchard_model_apple_rest",
            "orchard_default_params", "orchard_state_rest", "orchard_step", "orchard_ckpt_words",
            "orchard_ckpt_load", "orchard_events", "orchard_status", "orchard_last_error", "orchard_step_backward",
-           "orchard_tips", "orchard_tips_backward")
+           "orchard_tips", "orchard_tips_backward", "orchard_graph_create", "orchard_graph_launch",
+           "orchard_graph_destroy", "orchard_autotune")
 
 _lib = None
 
@@ -122,6 +127,16 @@ def load_library(path: str = LIB_PATH):
     L.orchard_tips.restype = st
     L.orchard_tips_backward.argtypes = [_P, _P, C.c_int32, _P, _P, _P, _P]
     L.orchard_tips_backward.restype = st
+    L.orchard_graph_create.argtypes = [_P, C.POINTER(CState), C.POINTER(CParams), C.POINTER(CInputs), C.c_int32,
+                                       C.POINTER(_P)]
+    L.orchard_graph_create.restype = st
+    L.orchard_graph_launch.argtypes = [_P, _P]
+    L.orchard_graph_launch.restype = st
+    L.orchard_graph_destroy.argtypes = [_P]
+    L.orchard_graph_destroy.restype = None
+    L.orchard_autotune.argtypes = [C.POINTER(Desc), C.POINTER(Tuning), C.c_int32, C.c_int32, C.c_int32,
+                                   C.POINTER(Tuning), _P, _P]
+    L.orchard_autotune.restype = st
     L.orchard_last_error.argtypes = []
     L.orchard_last_error.restype = C.c_char_p
     _lib = L
@@ -171,6 +186,105 @@ class State:
         return State(*[getattr(self, f).clone() for f in self.__dataclass_fields__])
 
 
+def _desc(batch, consts: dict, keep: list) -> Desc:
+    """Model descriptor over the batch's host arrays (kept alive in `keep`)."""
+    d = Desc()
+    d.n_env = batch.n_env
+    for name in ("seg_offset", "seg_parent", "apple_offset", "apple_seg"):
+        a = np.ascontiguousarray(getattr(batch, name), dtype=np.int32)
+        keep.append(a)
+        setattr(d, name, _np_ptr(a) if a.size else C.c_void_p(a.ctypes.data))
+    for name in ("seg_rest_quat", "seg_length", "seg_radius", "seg_density", "seg_youngs", "seg_mor",
+                 "apple_hang", "apple_mass", "apple_radius", "apple_detach"):
+        a = np.ascontiguousarray(getattr(batch, name), dtype=np.float64)
+        keep.append(a)
+        setattr(d, name, C.c_void_p(a.ctypes.data))
+    d.dt = consts["dt"]
+    for i in range(3):
+        d.gravity[i] = consts["gravity"][i]
+    for k in ("tether_k", "tether_zeta", "damping_zeta", "damping_cd", "tension_factor", "v_cap",
+              "react_max_factor", "wrench_fraction", "wrench_sigma"):
+        setattr(d, k, float(consts[k]))
+    for k in ("n_break", "n_pull", "n_tension"):
+        setattr(d, k, int(consts[k]))
+    d.rng_seed = int(consts["rng_seed"])
+    return d
+
+
+def _tuning(t: dict) -> Tuning:
+    u = dict(DEFAULT_TUNING)
+    u.update(t)
+    return Tuning(int(u["threads"]), float(u["pack_fill"]), int(u["steps_per_launch"]), int(u["persistent"]),
+                  int(u["adjoint_ckpt_max"]), int(u["lds_width"]))
+
+
+def _tuning_dict(t: Tuning) -> dict:
+    return {f: (float if f == "pack_fill" else int)(getattr(t, f)) for f, _ in Tuning._fields_}
+
+
+class Graph:
+    """n_steps of Model.step captured once into a HIP graph; launch() replays it."""
+
+    def __init__(self, model: "Model", state: "State", kp, kd, n_steps: int, wrench=None, aforce=None):
+        self.model = model  # the graph uses the model's device buffers
+        self._keep = (state, kp, kd, wrench, aforce)
+        inp = model._inputs(n_steps, wrench, None, aforce, None)
+        cs = state.c()
+        pr = CParams(_tptr(kp), _tptr(kd))
+        h = C.c_void_p()
+        _check(load_library().orchard_graph_create(model.h, C.byref(cs), C.byref(pr), C.byref(inp), int(n_steps),
+                                                    C.byref(h)))
+        self.h = h
+        self.n_steps = int(n_steps)
+
+    def launch(self, stream=None):
+        _check(load_library().orchard_graph_launch(self.h, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.orchard_graph_destroy(self.h)
+            self.h = None
+
+
+def autotune(batch, consts: dict, candidates: list | None = None, n_warm: int = 5, n_steps: int = 20,
+             cache: str | None = None, stream=None):
+    """Time candidate kernel mappings on this batch with the library's autotuner and
+    return (best tuning dict, [(candidate, ms per step)]).  With `cache` (a JSON file),
+    a result stored for the same batch signature and device is returned without timing."""
+    import hashlib
+    import json
+    import torch
+    if candidates is None:
+        candidates = [dict(threads=t, pack_fill=f, lds_width=w)
+                      for t in (64, 128, 256) for f in (1.0, 2.0) for w in (0, 128, 256, 384)]
+    sig = hashlib.sha256()
+    for name in ("seg_offset", "seg_parent", "apple_offset"):
+        sig.update(np.ascontiguousarray(getattr(batch, name), dtype=np.int32).tobytes())
+    sig.update(json.dumps([candidates, n_warm, n_steps, sorted((k, str(v)) for k, v in consts.items()),
+                           torch.cuda.get_device_name()], sort_keys=True).encode())
+    key = sig.hexdigest()
+    store = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            store = json.load(f)
+        if key in store:
+            return store[key]["best"], [tuple(x) for x in store[key]["timings"]]
+    keep = []
+    d = _desc(batch, consts, keep)
+    arr = (Tuning * len(candidates))(*[_tuning(c) for c in candidates])
+    best = Tuning()
+    ms = (C.c_float * len(candidates))()
+    _check(load_library().orchard_autotune(C.byref(d), arr, len(candidates), int(n_warm), int(n_steps),
+                                           C.byref(best), ms, _stream(stream)))
+    best_d = _tuning_dict(best)
+    timings = [(dict(c), float(m)) for c, m in zip(candidates, ms)]
+    if cache:
+        store[key] = {"best": best_d, "timings": timings}
+        with open(cache, "w") as f:
+            json.dump(store, f, indent=1)
+    return best_d, timings
+
+
 class Model:
     """A batch of trees on the current HIP device."""
 
@@ -178,33 +292,9 @@ class Model:
         L = load_library()
         self.batch = batch
         self._keep = []
-        d = Desc()
-        d.n_env = batch.n_env
-        for name in ("seg_offset", "seg_parent", "apple_offset", "apple_seg"):
-            a = np.ascontiguousarray(getattr(batch, name), dtype=np.int32)
-            self._keep.append(a)
-            setattr(d, name, _np_ptr(a) if a.size else C.c_void_p(a.ctypes.data))
-        for name in ("seg_rest_quat", "seg_length", "seg_radius", "seg_density", "seg_youngs", "seg_mor",
-                     "apple_hang", "apple_mass", "apple_radius", "apple_detach"):
-            a = np.ascontiguousarray(getattr(batch, name), dtype=np.float64)
-            self._keep.append(a)
-            setattr(d, name, C.c_void_p(a.ctypes.data))
-        d.dt = consts["dt"]
-        for i in range(3):
-            d.gravity[i] = consts["gravity"][i]
-        for k in ("tether_k", "tether_zeta", "damping_zeta", "damping_cd", "tension_factor", "v_cap",
-                  "react_max_factor", "wrench_fraction", "wrench_sigma"):
-            setattr(d, k, float(consts[k]))
-        for k in ("n_break", "n_pull", "n_tension"):
-            setattr(d, k, int(consts[k]))
-        d.rng_seed = int(consts["rng_seed"])
+        d = _desc(batch, consts, self._keep)
         self.consts = dict(consts)
-        tun = None
-        if tuning is not None:
-            t = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0, adjoint_ckpt_max=0)
-            t.update(tuning)
-            tun = Tuning(int(t["threads"]), float(t["pack_fill"]), int(t["steps_per_launch"]), int(t["persistent"]),
-                         int(t["adjoint_ckpt_max"]))
+        tun = None if tuning is None else _tuning(tuning)
         self.tuning = tun
         h = C.c_void_p()
         _check(L.orchard_model_create(C.byref(d), C.byref(tun) if tun is not None else None, C.byref(h)))
@@ -278,6 +368,10 @@ class Model:
         _check(load_library().orchard_step(self.h, C.byref(cs), C.byref(pr), C.byref(inp), int(n_steps),
                                            _tptr(ckpt), int(ckpt_every), _stream(stream)))
         return state
+
+    def graph(self, state: State, kp, kd, n_steps: int, wrench=None, aforce=None) -> Graph:
+        """Capture n_steps of step(state, kp, kd, ...) into a replayable HIP graph."""
+        return Graph(self, state, kp, kd, n_steps, wrench, aforce)
 
     def _inputs(self, n_steps, wrench, wrench_stride, aforce, aforce_stride):
         inp = CInputs()

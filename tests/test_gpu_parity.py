@@ -75,13 +75,17 @@ def test_large_trees_and_small_trees_one_launch():
 @pytest.mark.parametrize("tuning", [
     dict(threads=64, pack_fill=0.0), dict(threads=128, pack_fill=1.0), dict(threads=256, pack_fill=2.0),
     dict(threads=512, pack_fill=1.0, persistent=1), dict(threads=128, pack_fill=1.0, steps_per_launch=7),
-    dict(threads=256, pack_fill=1.0, persistent=1, steps_per_launch=10)])
+    dict(threads=256, pack_fill=1.0, persistent=1, steps_per_launch=10),
+    dict(threads=64, pack_fill=1.0, lds_width=64), dict(threads=256, pack_fill=2.0, lds_width=512),
+    dict(threads=128, pack_fill=1.0, lds_width=0)])
 def test_mappings_are_bitwise_identical(tuning):
-    # the mapping changes which workgroup walks a tree, never the arithmetic of a node
+    # the mapping (workgroup per tree, exchange through LDS or global scratch) changes
+    # which workgroup walks a tree and where levels hand data over, never the
+    # arithmetic of a node
     from paper_2607_06337_amd import Model
     b = make_batch("uneven8192", env_ids=range(40))
     c = step_constants("uneven8192")
-    ref = Model(b, c, dict(threads=128, pack_fill=0.0))
+    ref = Model(b, c, dict(threads=128, pack_fill=0.0, lds_width=0))
     alt = Model(b, c, tuning)
     out = []
     for m in (ref, alt):

@@ -1,0 +1,64 @@
+"""Runtime pieces around the step: K-step HIP graphs and the autotuner (through the C ABI)."""
+import json
+
+import numpy as np
+import pytest
+
+from orchard_inputs import make_batch, step_constants
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no HIP device", allow_module_level=True)
+
+
+def _snapshot(m, st):
+    return (st.q.cpu().numpy().copy(), st.qd.cpu().numpy().copy(), st.apple.cpu().numpy().copy(),
+            st.evt_step.cpu().numpy().copy(), int(st.step.item()))
+
+
+@pytest.mark.parametrize("tuning", [dict(threads=128, pack_fill=1.0, lds_width=256),
+                                    dict(threads=256, pack_fill=1.0, persistent=1, steps_per_launch=4)])
+def test_graph_replays_equal_eager_steps(tuning):
+    from paper_2607_06337_amd import Model
+    b = make_batch("uneven8192", env_ids=range(48))
+    c = step_constants("uneven8192")
+    m = Model(b, c, tuning)
+    K = 25
+    g = torch.Generator().manual_seed(7)
+    af = (torch.randn(K, m.n_apple, 3, generator=g) * 4.0).cuda().contiguous()
+    eager = m.rest_state()
+    graphed = m.rest_state()
+    kp, kd = m.default_params()
+    gr = m.graph(graphed, kp, kd, K, aforce=af)
+    for r in range(4):
+        m.step(eager, kp, kd, K, aforce=af)
+        gr.launch()
+        torch.cuda.synchronize()
+        # eager work between replays
+        x = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        a, bb = _snapshot(m, eager), _snapshot(m, graphed)
+        for u, v in zip(a[:4], bb[:4]):
+            assert np.array_equal(u, v), f"replay {r}"
+        assert a[4] == bb[4] == K * (r + 1)
+        del x
+
+
+def test_autotune_returns_the_fastest_candidate(tmp_path):
+    from paper_2607_06337_amd import autotune
+    b = make_batch("uneven8192", env_ids=range(64))
+    c = step_constants("uneven8192")
+    cands = [dict(threads=64, pack_fill=1.0, lds_width=0), dict(threads=128, pack_fill=1.0, lds_width=256),
+             dict(threads=256, pack_fill=0.0, lds_width=512)]
+    cache = str(tmp_path / "tune.json")
+    best, timings = autotune(b, c, cands, n_warm=2, n_steps=5, cache=cache)
+    ms = [t[1] for t in timings]
+    assert all(x > 0 for x in ms)
+    k = int(np.argmin(ms))
+    for key, v in cands[k].items():
+        assert best[key] == v
+    # cached: same answer without timing
+    best2, timings2 = autotune(b, c, cands, n_warm=2, n_steps=5, cache=cache)
+    assert best2 == best and [t[1] for t in timings2] == ms
+    assert len(json.load(open(cache))) == 1

@@ -51,3 +51,23 @@ def test_create_rejects_invalid_descriptions():
     _bad(apple_seg, 2)
     _bad(lambda b: None, 1, dt=0.0)
     _bad(lambda b: None, 1, wrench_fraction=1.5)
+
+
+def test_create_rejects_invalid_mappings():
+    from paper_2607_06337_amd import Model, OrchardError
+    b = assemble([gen_tree(1, 20, 3)])
+    for tun in (dict(threads=96), dict(lds_width=-1), dict(lds_width=513), dict(adjoint_ckpt_max=-2)):
+        with pytest.raises(OrchardError) as ei:
+            Model(b, step_constants(), tun)
+        assert ei.value.code == 1, (tun, str(ei.value))
+
+
+def test_autotune_and_graph_reject_bad_arguments():
+    from paper_2607_06337_amd import load_library
+    from paper_2607_06337_amd.orchard import Tuning
+    L = load_library()
+    best = Tuning()
+    assert L.orchard_autotune(None, None, 0, 0, 1, C.byref(best), None, None) == 1
+    assert L.orchard_graph_launch(None, None) == 1
+    assert L.orchard_graph_create(None, None, None, None, 5, None) == 1
+    L.orchard_graph_destroy(None)
