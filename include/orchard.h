@@ -85,15 +85,17 @@ typedef struct {
   double wrench_sigma;          /* N(0, sigma) per force component                    */
 } orchard_model_desc_t;
 
-/* Kernel mapping choices (nullable in create: defaults {128, 1.0, 1, 0, 0, 256}).
+/* Kernel mapping choices (nullable in create: defaults {128, 1.0, 1, 0, 0, 128, 0}).
  * threads: workgroup size for the pack kernel (64, 128, 256 or 512).  pack_fill: a
  * pack collects trees of similar depth until it holds about pack_fill * threads *
- * depth nodes (0 = one tree per pack).  lds_width: capacity, in nodes per level, of
- * the LDS buffer through which neighbouring levels of a pack exchange their data
- * (2 x 27 x lds_width floats of LDS per workgroup); packs are also closed before a
- * level would exceed it, and a tree wider than it exchanges through global scratch.
- * 0 = global scratch for every pack.  No mapping choice changes any result bit. */
-#define ORCHARD_LDS_WIDTH_MAX 512
+ * depth nodes (0 = one tree per pack).  lds_width (0 .. threads): capacity, in nodes
+ * per level, of the LDS buffer through which neighbouring levels of a pack exchange
+ * their data (2 x 27 x lds_width floats of LDS per workgroup); packs are then also
+ * closed before a level would exceed it, and a tree wider than it exchanges through
+ * global scratch.  0 = global scratch for every pack.  pack_skew (LDS exchange only):
+ * 1 = place trees at level offsets inside a strip of pack_fill x (deepest tree) levels
+ * so that their widest levels do not coincide.  No mapping choice changes any result
+ * bit. */
 typedef struct {
   int32_t threads;
   float pack_fill;
@@ -101,7 +103,8 @@ typedef struct {
   int32_t persistent;           /* 1: persistent grid pulling packs from a queue      */
   int32_t adjoint_ckpt_max;     /* > 0: allocate recompute buffers for                */
                                 /*   orchard_step_backward with ckpt_every up to this */
-  int32_t lds_width;            /* 0 .. ORCHARD_LDS_WIDTH_MAX                         */
+  int32_t lds_width;
+  int32_t pack_skew;
 } orchard_tuning_t;
 
 typedef struct {
@@ -123,7 +126,9 @@ typedef struct {
   uint8_t* apple_evt;  /* [4][n_apple] detached flag, pull counter, tension counter,   */
                        /*              detach path (1 pull, 2 tension)                  */
   int32_t* evt_step;   /* [n_seg + n_apple] step of break / detach, -1 = none          */
-  uint32_t* env_status;/* [n_env] bit 0: non-finite state produced; env frozen         */
+  uint32_t* env_status;/* [n_env] bit 0: non-finite state produced; env frozen from   */
+                       /*   the next step on; bit 1: an apple state was among the    */
+                       /*   non-finite values (with bit 0)          */
   int64_t* step;       /* device scalar: index of the next step (event stamps, RNG)    */
 } orchard_state_t;
 

@@ -148,9 +148,19 @@ inline uint64_t splitmix64(uint64_t x) {
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
+// Counter-based draws for the in-step random wrenches.  Per (env, segment) a static key
+// H = splitmix64(splitmix64(seed ^ splitmix64(env)) ^ splitmix64(seg)); per step
+// x = splitmix64(H ^ splitmix64(step)).  The top 24 bits of x select the segment; the
+// four 24-bit uniforms of a selected segment are bits 63..40 and 39..16 of
+// y1 = splitmix64(x) and of y2 = splitmix64(y1).  k = 0 returns the selection bits,
+// k = 1..4 the uniforms.
 inline uint32_t rng_u24(uint64_t seed, uint64_t env, uint64_t step, uint64_t seg, uint64_t k) {
-  uint64_t h = splitmix64(seed ^ splitmix64(env ^ splitmix64(step ^ splitmix64(8ull * seg + k))));
-  return (uint32_t)(h >> 40);
+  const uint64_t H = splitmix64(splitmix64(seed ^ splitmix64(env)) ^ splitmix64(seg));
+  const uint64_t x = splitmix64(H ^ splitmix64(step));
+  if (k == 0) return (uint32_t)(x >> 40);
+  const uint64_t y1 = splitmix64(x), y2 = splitmix64(y1);
+  const uint64_t y = k <= 2 ? y1 : y2;
+  return (uint32_t)((k & 1) ? (y >> 40) : ((y >> 16) & 0xFFFFFFull));
 }
 
 }  // namespace orc

@@ -176,7 +176,7 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   {
     V3 F, T;
     const bool snp = aldf(M, F_SNAP, i) != 0.f;
-    if (applied_force(M, I, i, M.env[i], n, s_call, m, snp, F, T)) zb = zb - (0.5f * l) * cross(F, na);
+    if (applied_force(M, I, i, splitmix64((uint64_t)n), s_call, m, snp, M.hkey[i], F, T)) zb = zb - (0.5f * l) * cross(F, na);
   }
   zb = fma3(0.5f * m * l, hb, zb);
 

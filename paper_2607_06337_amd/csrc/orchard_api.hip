@@ -150,10 +150,10 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       !(d->tension_factor > 0) || !(d->v_cap > 0) || !(d->react_max_factor > 0) || d->wrench_fraction < 0 ||
       d->wrench_fraction > 1)
     return fail(ORCHARD_ERR_INVALID_ARG, "step constant out of range");
-  orchard_tuning_t tun{128, 1.0f, 1, 0, 0, 256};
+  orchard_tuning_t tun{128, 1.0f, 1, 0, 0, 128, 0};
   if (tuning) tun = *tuning;
-  if (tun.lds_width < 0 || tun.lds_width > ORCHARD_LDS_WIDTH_MAX)
-    return fail(ORCHARD_ERR_INVALID_ARG, "tuning.lds_width must be in [0, " + std::to_string(ORCHARD_LDS_WIDTH_MAX) + "]");
+  if (tun.lds_width < 0 || tun.lds_width > tun.threads)
+    return fail(ORCHARD_ERR_INVALID_ARG, "tuning.lds_width must be in [0, threads]");
   if (tun.adjoint_ckpt_max < 0) return fail(ORCHARD_ERR_INVALID_ARG, "tuning.adjoint_ckpt_max < 0");
   if (tun.threads != 64 && tun.threads != 128 && tun.threads != 256 && tun.threads != 512)
     return fail(ORCHARD_ERR_INVALID_ARG, "tuning.threads must be 64, 128, 256 or 512");
@@ -300,31 +300,74 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     maxd = std::max(maxd, dmax + 1);
   }
 
-  // ---- packs: trees of similar depth share one workgroup ----
-  const int NT = tun.threads;
-  std::vector<int32_t> tord(B);
-  std::iota(tord.begin(), tord.end(), 0);
-  std::stable_sort(tord.begin(), tord.end(), [&](int a, int b) {
-    if (lvlw[a].size() != lvlw[b].size()) return lvlw[a].size() > lvlw[b].size();
-    return d->seg_offset[a + 1] - d->seg_offset[a] > d->seg_offset[b + 1] - d->seg_offset[b];
-  });
-  // With an LDS exchange, a pack also stops growing once one of its levels would hold
-  // more than lds_width nodes; a single tree wider than that gets a pack of its own
-  // that exchanges through global scratch.
-  std::vector<std::vector<int32_t>> packs;
-  {
-    std::vector<int32_t> cur;
+  // ---- packs: several trees share one workgroup ----
+  // packs[p] lists (tree, level offset): tree t placed at offset o occupies the pack's
+  // levels o .. o + depth_t - 1.  Levels of different trees never depend on each other,
+  // so a pack may run different depths of different trees side by side.
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> packs;
+  const int64_t W = tun.lds_width;
+  if (W > 0 && tun.pack_fill > 0.f && tun.pack_skew) {
+    // depth-offset first fit.  A pack is a strip of V levels of at most W
+    // nodes (V = pack_fill x the deepest tree); trees, largest first, go to the first of
+    // the last few open packs and the lowest offset where every level still fits, so
+    // the wide middle of one tree sits beside the narrow ends of others.  A tree wider
+    // than W gets a pack of its own that exchanges through global scratch.
+    const int V = std::max<int>(maxd, (int)std::ceil(tun.pack_fill * maxd));
+    std::vector<int32_t> sord(B);
+    std::iota(sord.begin(), sord.end(), 0);
+    std::stable_sort(sord.begin(), sord.end(), [&](int a, int b) {
+      return d->seg_offset[a + 1] - d->seg_offset[a] > d->seg_offset[b + 1] - d->seg_offset[b];
+    });
+    std::vector<std::vector<int64_t>> pw;  // level widths of the open strips
+    std::vector<size_t> strip_pack;        // strip -> pack index
+    const int K = 16;
+    for (int t : sord) {
+      const auto& wt = lvlw[t];
+      const int Dt = (int)wt.size();
+      const int64_t wmax_t = *std::max_element(wt.begin(), wt.end());
+      if (wmax_t > W) { packs.push_back({{t, 0}}); continue; }
+      bool placed = false;
+      for (int k = (int)pw.size() - 1; k >= 0 && k >= (int)pw.size() - K && !placed; --k) {
+        auto& w = pw[k];
+        for (int off = 0; off + Dt <= V && !placed; ++off) {
+          bool ok = true;
+          for (int l = 0; l < Dt && ok; ++l) ok = w[off + l] + wt[l] <= W;
+          if (ok) {
+            for (int l = 0; l < Dt; ++l) w[off + l] += wt[l];
+            packs[strip_pack[k]].push_back({t, off});
+            placed = true;
+          }
+        }
+      }
+      if (!placed) {
+        pw.emplace_back(V, 0);
+        for (int l = 0; l < Dt; ++l) pw.back()[l] += wt[l];
+        strip_pack.push_back(packs.size());
+        packs.push_back({{t, 0}});
+      }
+    }
+  } else {
+    // trees of similar depth, about pack_fill * threads * depth nodes; with an LDS
+    // exchange a pack also closes before one of its levels would exceed W nodes (a tree
+    // wider than W gets a pack of its own that exchanges through global scratch)
+    const int NT0 = tun.threads;
+    std::vector<int32_t> tord(B);
+    std::iota(tord.begin(), tord.end(), 0);
+    std::stable_sort(tord.begin(), tord.end(), [&](int a, int b) {
+      if (lvlw[a].size() != lvlw[b].size()) return lvlw[a].size() > lvlw[b].size();
+      return d->seg_offset[a + 1] - d->seg_offset[a] > d->seg_offset[b + 1] - d->seg_offset[b];
+    });
+    std::vector<std::pair<int32_t, int32_t>> cur;
     std::vector<int64_t> curw;
     int64_t cur_nodes = 0;
     size_t cur_depth = 0;
-    const int64_t W = tun.lds_width;
     for (int t : tord) {
       const int64_t St = d->seg_offset[t + 1] - d->seg_offset[t];
       const size_t dt = lvlw[t].size();
       bool wide = false;
       if (W > 0)
         for (size_t l = 0; l < dt && l < curw.size(); ++l) wide = wide || curw[l] + lvlw[t][l] > W;
-      if (!cur.empty() && (tun.pack_fill <= 0.f || cur_nodes + St > (int64_t)(tun.pack_fill * NT * cur_depth) ||
+      if (!cur.empty() && (tun.pack_fill <= 0.f || cur_nodes + St > (int64_t)(tun.pack_fill * NT0 * cur_depth) ||
                            dt * 10 < cur_depth * 7 || wide)) {
         packs.push_back(cur);
         cur.clear();
@@ -332,24 +375,28 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
         cur_nodes = 0;
       }
       if (cur.empty()) cur_depth = dt;
-      cur.push_back(t);
+      cur.push_back({t, 0});
       cur_nodes += St;
       if (curw.size() < dt) curw.resize(dt, 0);
       for (size_t l = 0; l < dt; ++l) curw[l] += lvlw[t][l];
     }
     if (!cur.empty()) packs.push_back(cur);
   }
+  const int NT = tun.threads;
+  // level widths of every pack
+  std::vector<std::vector<int64_t>> packw(packs.size());
+  for (size_t p = 0; p < packs.size(); ++p) {
+    size_t L = 0;
+    for (auto& to : packs[p]) L = std::max(L, (size_t)to.second + lvlw[to.first].size());
+    packw[p].assign(L, 0);
+    for (auto& to : packs[p])
+      for (size_t l = 0; l < lvlw[to.first].size(); ++l) packw[p][to.second + l] += lvlw[to.first][l];
+  }
   // longest-processing-time order: estimated cost = sum over levels of ceil(width / NT)
   std::vector<int64_t> pcost(packs.size());
   for (size_t p = 0; p < packs.size(); ++p) {
-    size_t L = 0;
-    for (int t : packs[p]) L = std::max(L, lvlw[t].size());
     int64_t c = 0;
-    for (size_t l = 0; l < L; ++l) {
-      int64_t w = 0;
-      for (int t : packs[p]) if (l < lvlw[t].size()) w += lvlw[t][l];
-      c += (w + NT - 1) / NT;
-    }
+    for (int64_t w : packw[p]) c += (w + NT - 1) / NT;
     pcost[p] = c;
   }
   std::vector<int32_t> pord(packs.size());
@@ -365,24 +412,18 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     const auto& P = packs[pi];
     pack_node.push_back((int32_t)seg_map.size());
     pack_lvl.push_back((int32_t)lvl_off.size());
-    size_t L = 0;
-    for (int t : P) L = std::max(L, lvlw[t].size());
-    std::vector<size_t> pos(P.size(), 0);
-    int64_t wmax = 0;
-    for (size_t l = 0; l < L; ++l) {
-      int64_t w = 0;
-      for (int t : P) if (l < lvlw[t].size()) w += lvlw[t][l];
-      wmax = std::max(wmax, w);
-    }
+    const size_t L = packw[pi].size();
+    const int64_t wmax = *std::max_element(packw[pi].begin(), packw[pi].end());
     const int fits = tun.lds_width > 0 && wmax <= tun.lds_width;
     pack_lds.push_back(fits);
     n_lds_packs += fits;
+    std::vector<size_t> pos(P.size(), 0);
     for (size_t l = 0; l < L; ++l) {
       lvl_off.push_back((int32_t)seg_map.size());
       for (size_t k = 0; k < P.size(); ++k) {
-        const int t = P[k];
+        const int t = P[k].first, dl = (int)l - P[k].second;
         const auto& ord = bfs[t];
-        while (pos[k] < ord.size() && depth[ord[pos[k]]] == (int)l) {
+        while (dl >= 0 && pos[k] < ord.size() && depth[ord[pos[k]]] == dl) {
           int_of[ord[pos[k]]] = (int32_t)seg_map.size();
           seg_map.push_back(ord[pos[k]]);
           pos[k]++;
@@ -445,6 +486,33 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   }
   for (int64_t i = 0; i < NS; ++i) apple_beg[i + 1] += apple_beg[i];
 
+  // ---- forward-step records ----
+  if (NS > (1LL << 25) || NA > (1LL << 25))
+    return fail(ORCHARD_ERR_INVALID_ARG, "at most 2^25 segments and 2^25 apples per model (32-bit offsets)");
+  std::vector<NodeRec> nrec(NS);
+  std::vector<uint64_t> hkey(NS);
+  for (int64_t i = 0; i < NS; ++i) {
+    const int napp = apple_beg[i + 1] - apple_beg[i];
+    if (nchild_i[i] > 0xFFFF || napp > 0xFFFF)
+      return fail(ORCHARD_ERR_INVALID_TOPOLOGY, "a segment with more than 65535 children or apples");
+    const float inv_mmax = (float)(1.0 / (double)mmax_f[i]);
+    int32_t bits;
+    std::memcpy(&bits, &inv_mmax, 4);
+    hkey[i] = rng_node_key(d->rng_seed, (uint64_t)env_i[i], (uint64_t)orig_i[i]);
+    nrec[i].rq = rq[i];
+    nrec[i].geo = geo[i];
+    nrec[i].topo = make_int4(par_i[i], child_i[i], nchild_i[i] | (napp << 16), env_i[i]);
+    nrec[i].aux = make_int4((int32_t)(uint32_t)(hkey[i] & 0xFFFFFFFFull), (int32_t)(uint32_t)(hkey[i] >> 32), apple_beg[i], bits);
+  }
+  std::vector<AppleRec> arec(NA);
+  for (int64_t k = 0; k < NA; ++k) {
+    const int a = aord[k];
+    const double fdet = d->apple_detach[a], ma = d->apple_mass[a];
+    arec[k].hang = ahang_h[k];
+    arec[k].par = make_float4((float)(1.0 / fdet), apar_h[k].y, apar_h[k].z, (float)(1.0 / (d->tension_factor * fdet)));
+    arec[k].rest = make_float4(ahrest_h[k].x, ahrest_h[k].y, ahrest_h[k].z, (float)(d->dt / ma));
+  }
+
   // ---- device layout ----
   orchard_model_s* M = new orchard_model_s();
   M->tun = tun;
@@ -468,6 +536,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
          o_ah = ar.put(ahang_h.data(), NA * 16), o_ap = ar.put(apar_h.data(), NA * 16),
          o_kp = ar.put(kp_f.data(), NS * 4), o_kd = ar.put(kd_f.data(), NS * 4), o_ar = ar.put(arest.data(), 3 * NA * 4),
          o_hr = ar.put(ahrest_h.data(), NA * 16), o_pd = ar.put(pack_lds.data(), pack_lds.size() * 4),
+         o_nr = ar.put(nrec.data(), NS * sizeof(NodeRec)), o_ar2 = ar.put(arec.data(), NA * sizeof(AppleRec)),
+         o_hk = ar.put(hkey.data(), NS * 8),
          o_q = ar.put(&zero, 4 * 16);
   hipError_t he = hipMalloc(&M->arena, ar.off + 256);
   if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
@@ -495,6 +565,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.geo = (const float4*)(base + o_geo); dm.mmax = (const float*)(base + o_mm);
   dm.ahang = (const float4*)(base + o_ah); dm.apar = (const float4*)(base + o_ap);
   dm.ahrest = (const float4*)(base + o_hr); dm.pack_lds = (const int32_t*)(base + o_pd);
+  dm.nrec = (const NodeRec*)(base + o_nr); dm.arec = (const AppleRec*)(base + o_ar2);
+  dm.hkey = (const uint64_t*)(base + o_hk);
   dm.scr_nf = scr_nf;
   dm.lds_cap = n_lds_packs > 0 ? tun.lds_width : 0;
   M->lds_bytes = (size_t)dm.lds_cap * 2 * N_PUB_MAX * 4;

@@ -64,6 +64,20 @@ enum : int {
   N_FIELDS_ADJ = 200
 };
 
+// Static records read by the forward step: one 64-byte record per node and one 48-byte
+// record per apple (a few wide loads instead of one load per array).
+struct NodeRec {
+  float4 rq;    // rest quaternion (w, x, y, z)
+  float4 geo;   // (l, m, Jt about the joint, Ia)
+  int4 topo;    // (parent, first child, children | apples << 16, env)
+  int4 aux;     // (random-wrench key low, high 32 bits, first apple, 1 / M_max as float bits)
+};
+struct AppleRec {
+  float4 hang;  // hang point in the segment frame, mass
+  float4 par;   // (1 / f_det, c_s, F_max, 1 / (alpha f_det))
+  float4 rest;  // rest hang point (origin of a detached apple's position), h / m
+};
+
 struct DevModel {
   int32_t n_env, n_seg, n_apple, n_pack;
   // packs: nodes [pack_node[p], pack_node[p+1]); levels lvl_off[pack_lvl[p] .. pack_lvl[p+1]-1]
@@ -72,12 +86,15 @@ struct DevModel {
   const int32_t* pack_lvl;
   const int32_t* lvl_off;
   const int32_t* pack_lds;   // 1: every level of the pack fits the workgroup (LDS publications)
+  const NodeRec* nrec;       // per node (internal order)
+  const AppleRec* arec;      // per apple (internal order)
   // per node (internal order)
   const int32_t* par;        // parent node, -1 = world
   const int32_t* child;      // first child node
   const int32_t* nchild;     // number of children (contiguous)
   const int32_t* env;        // descriptor env index
-  const int32_t* orig;       // env-local descriptor segment index (counter generator key)
+  const int32_t* orig;       // env-local descriptor segment index
+  const uint64_t* hkey;      // random-wrench key of the node (rng_node_key)
   const int32_t* apple_beg;  // [n_seg+1] apples of node i: apple_beg[i] .. apple_beg[i+1]-1
   const float4* rq;          // rest quaternion (w, x, y, z)
   const float4* geo;         // (l, m, Jt about the joint, Ia)
@@ -105,6 +122,17 @@ struct DevModel {
 // DRAM rows and TLB entries shared across the fields a wavefront touches.
 __device__ __forceinline__ size_t scr_idx(const DevModel& M, int f, int i) {
   return ((size_t)(i >> 6) * (size_t)M.scr_nf + (size_t)f) * 64u + (size_t)(i & 63);
+}
+
+// element idx of p with the byte offset formed in 32 bits (arrays stay below 4 GiB), so
+// the address is a uniform base plus one 32-bit lane offset
+template <class T>
+__device__ __forceinline__ T& at(T* p, uint32_t idx) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + idx * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T& at(const T* p, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + idx * (uint32_t)sizeof(T));
 }
 
 struct DevState {
@@ -157,40 +185,49 @@ __device__ __forceinline__ V3 mulT(const Mat3& A, V3 v) {
 }
 
 // ---- SplitMix64 (Steele, Lea & Flood 2014): output mix of x + golden gamma ------------------
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
-__device__ __forceinline__ uint32_t counter_u24(uint64_t seed, uint64_t env, uint64_t step, uint64_t seg, uint64_t k) {
-  return (uint32_t)(splitmix64(seed ^ splitmix64(env ^ splitmix64(step ^ splitmix64(8ull * seg + k)))) >> 40);
+// Random-wrench draws: static key of (env, env-local segment) and the per-step draw
+// x = splitmix64(key ^ splitmix64(step)); the top 24 bits select, a selected segment's
+// uniforms are bits 63..40 and 39..16 of y1 = splitmix64(x) and y2 = splitmix64(y1).
+__host__ __device__ __forceinline__ uint64_t rng_node_key(uint64_t seed, uint64_t env, uint64_t seg) {
+  return splitmix64(splitmix64(seed ^ splitmix64(env)) ^ splitmix64(seg));
 }
 
-// Applied force on segment i at step n: the input wrench plus the counter-based random
-// force, disabled on a snapped sub-tree, the force impulse-capped at m v_cap / h.  Returns
-// false if there is none.
-__device__ __forceinline__ bool applied_force(const DevModel& M, const DevInputs& I, int i, int e, int64_t n, int s_call,
-                                              float m, bool snp, V3& F, V3& T) {
+// Applied force on segment i at the step whose key is kstep = splitmix64(step): the input
+// wrench plus the counter-based random force (node key hkey), disabled on a snapped
+// sub-tree, the force impulse-capped at m v_cap / h.  Returns false if there is none.
+__device__ __forceinline__ bool applied_force(const DevModel& M, const DevInputs& I, int i, uint64_t kstep, int s_call,
+                                              float m, bool snp, uint64_t hkey, V3& F, V3& T) {
   F = v3(0, 0, 0);
   T = v3(0, 0, 0);
   if (snp) return false;
   bool any = false;
   if (I.wrench) {
-    const float* wp = I.wrench + (int64_t)s_call * I.wrench_stride + 6 * (int64_t)i;
-    F = v3(wp[0], wp[1], wp[2]);
-    T = v3(wp[3], wp[4], wp[5]);
+    const float* wp = I.wrench + (int64_t)s_call * I.wrench_stride;
+    const uint32_t o = 6u * (uint32_t)i;
+    F = v3(at(wp, o), at(wp, o + 1), at(wp, o + 2));
+    T = v3(at(wp, o + 3), at(wp, o + 4), at(wp, o + 5));
     any = true;
   }
   if (M.use_rng) {
-    const uint64_t ee = (uint64_t)e, nn = (uint64_t)n, ss = (uint64_t)M.orig[i];
-    if (counter_u24(M.seed, ee, nn, ss, 0) < M.rng_thr) {
-      float uu[4];
-      for (int k = 0; k < 4; ++k) uu[k] = ((float)counter_u24(M.seed, ee, nn, ss, (uint64_t)(k + 1)) + 0.5f) * (1.f / 16777216.f);
-      const float r0 = sqrtf(-2.f * logf(uu[0])), r1 = sqrtf(-2.f * logf(uu[2]));
+    const uint64_t x = splitmix64(hkey ^ kstep);
+    if ((uint32_t)(x >> 40) < M.rng_thr) {
+      const uint64_t y1 = splitmix64(x), y2 = splitmix64(y1);
+      const float sc = 1.f / 16777216.f;
+      const float u0 = ((float)(uint32_t)(y1 >> 40) + 0.5f) * sc;
+      const float u1 = ((float)(uint32_t)((y1 >> 16) & 0xFFFFFFu) + 0.5f) * sc;
+      const float u2 = ((float)(uint32_t)(y2 >> 40) + 0.5f) * sc;
+      const float u3 = ((float)(uint32_t)((y2 >> 16) & 0xFFFFFFu) + 0.5f) * sc;
+      // Box-Muller
+      const float r0 = sqrtf(-2.f * logf(u0)), r1 = sqrtf(-2.f * logf(u2));
       float s1, c1v, s3, c3;
-      sincosf(6.283185307179586f * uu[1], &s1, &c1v);
-      sincosf(6.283185307179586f * uu[3], &s3, &c3);
+      sincosf(6.283185307179586f * u1, &s1, &c1v);
+      sincosf(6.283185307179586f * u3, &s3, &c3);
       F = F + M.wsig * v3(r0 * c1v, r0 * s1, r1 * c3);
       any = true;
     }

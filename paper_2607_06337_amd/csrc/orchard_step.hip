@@ -18,47 +18,119 @@
 
 namespace orchard {
 
-__device__ __forceinline__ float ld(const DevModel& M, int f, int i) { return M.scr[scr_idx(M, f, i)]; }
-__device__ __forceinline__ void sto(const DevModel& M, int f, int i, float v) { M.scr[scr_idx(M, f, i)] = v; }
-__device__ __forceinline__ V3 ld3(const DevModel& M, int f, int i) { return v3(ld(M, f, i), ld(M, f + 1, i), ld(M, f + 2, i)); }
-__device__ __forceinline__ void sto3(const DevModel& M, int f, int i, V3 v) { sto(M, f, i, v.x); sto(M, f + 1, i, v.y); sto(M, f + 2, i, v.z); }
+// Scratch of one pack: P points at the pack's first 64-node block and li = node - i0
+// (i0 = that block's first node), so offsets stay 32-bit; the layout is the global one.
+__device__ __forceinline__ uint32_t sidx(int nf, int f, int li) {
+  return ((uint32_t)(li >> 6) * (uint32_t)nf + (uint32_t)f) * 64u + (uint32_t)(li & 63);
+}
+__device__ __forceinline__ float pld(const float* P, int nf, int f, int li) { return at(P, sidx(nf, f, li)); }
+__device__ __forceinline__ void pst(float* P, int nf, int f, int li, float v) { at(P, sidx(nf, f, li)) = v; }
+__device__ __forceinline__ V3 pld3(const float* P, int nf, int f, int li) {
+  return v3(pld(P, nf, f, li), pld(P, nf, f + 1, li), pld(P, nf, f + 2, li));
+}
+__device__ __forceinline__ void pst3(float* P, int nf, int f, int li, V3 v) {
+  pst(P, nf, f, li, v.x); pst(P, nf, f + 1, li, v.y); pst(P, nf, f + 2, li, v.z);
+}
 
-// publication access: field f of a publication block starting at field f0, of node i
-// (slot s within its level, level-parity buffer b)
+// Where a pass stands: the pack's scratch, its exchange buffer and the current level.
+struct Lvl {
+  float* P;    // pack scratch
+  float* X;    // LDS exchange buffer (LDS path)
+  int nf;      // scratch fields per node
+  int cap;     // exchange slots per level
+  int i0;      // first node of the pack's first scratch block
+  int a;       // first node of this level
+  int nbr;     // first node of the neighbouring level that is read (parent or child level)
+  int b;       // this level's exchange buffer (level parity)
+};
+
+// publication access: field f of a publication block starting at field f0, of node j,
+// which lies on this level (own) or on the neighbouring level (nbr)
 template <bool XL>
-__device__ __forceinline__ float xget(const DevModel& M, const float* X, int f0, int f, int i, int s, int b) {
-  if constexpr (XL) return X[(b * N_PUB_MAX + (f - f0)) * M.lds_cap + s];
-  else return ld(M, f, i);
+__device__ __forceinline__ float xget(const Lvl& L, int f0, int f, int j) {
+  if constexpr (XL) return L.X[(uint32_t)(((L.b ^ 1) * N_PUB_MAX + (f - f0)) * L.cap + (j - L.nbr))];
+  else return pld(L.P, L.nf, f, j - L.i0);
 }
 template <bool XL>
-__device__ __forceinline__ void xput(const DevModel& M, float* X, int f0, int f, int i, int s, int b, float v) {
-  if constexpr (XL) X[(b * N_PUB_MAX + (f - f0)) * M.lds_cap + s] = v;
-  else sto(M, f, i, v);
+__device__ __forceinline__ void xput(const Lvl& L, int f0, int f, int i, float v) {
+  if constexpr (XL) L.X[(uint32_t)((L.b * N_PUB_MAX + (f - f0)) * L.cap + (i - L.a))] = v;
+  else pst(L.P, L.nf, f, i - L.i0, v);
 }
 template <bool XL>
-__device__ __forceinline__ V3 xget3(const DevModel& M, const float* X, int f0, int f, int i, int s, int b) {
-  return v3(xget<XL>(M, X, f0, f, i, s, b), xget<XL>(M, X, f0, f + 1, i, s, b), xget<XL>(M, X, f0, f + 2, i, s, b));
+__device__ __forceinline__ V3 xget3(const Lvl& L, int f0, int f, int j) {
+  return v3(xget<XL>(L, f0, f, j), xget<XL>(L, f0, f + 1, j), xget<XL>(L, f0, f + 2, j));
 }
 template <bool XL>
-__device__ __forceinline__ void xput3(const DevModel& M, float* X, int f0, int f, int i, int s, int b, V3 v) {
-  xput<XL>(M, X, f0, f, i, s, b, v.x); xput<XL>(M, X, f0, f + 1, i, s, b, v.y); xput<XL>(M, X, f0, f + 2, i, s, b, v.z);
+__device__ __forceinline__ void xput3(const Lvl& L, int f0, int f, int i, V3 v) {
+  xput<XL>(L, f0, f, i, v.x); xput<XL>(L, f0, f + 1, i, v.y); xput<XL>(L, f0, f + 2, i, v.z);
 }
 
 __device__ __forceinline__ bool finite3(V3 a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
 
+// Status word of an env: bit 0 = frozen (a non-finite state was produced), set at the end
+// of a step; bit 1 = an apple went non-finite during this step, promoted to bit 0 by the
+// tree's root at the end of the step.  A step's frozen test reads bit 0 only, so it never
+// depends on what other nodes of the same step have done.
+enum : uint32_t { ST_FROZEN = 1u, ST_APPLE_BAD = 2u };
+
 // ------------------------------------------------------------------------------------------
 // down pass 1
 // ------------------------------------------------------------------------------------------
-// i: node, s: its slot in its level, b: its level's buffer, pb: first node of the parent level
+// Frozen envs run the arithmetic on whatever their state holds but write no state, event
+// or status; their scratch and publications are read only by nodes of the same env.
+//
+// Each pass is split into a load stage (the node's own inputs, independent of other
+// nodes) and a compute stage, so the LDS path can issue the next level's loads before
+// the current level's arithmetic.
+
+// down 1 inputs that do not depend on other nodes
+struct In1 {
+  NodeRec nr;
+  float2 q, qd;
+  float kp, kd;
+  uint8_t brk, cnt;
+};
+__device__ __forceinline__ In1 load1(const DevModel& M, const DevState& S, const DevInputs& I, int i) {
+  In1 r;
+  r.nr = at(M.nrec, (uint32_t)i);
+  r.q = at(S.q, (uint32_t)i);
+  r.qd = at(S.qd, (uint32_t)i);
+  r.kp = at(I.kp, (uint32_t)i);
+  r.kd = at(I.kd, (uint32_t)i);
+  r.brk = at(S.seg_evt, (uint32_t)i);
+  r.cnt = at(S.seg_evt, (uint32_t)(M.n_seg + i));
+  return r;
+}
+
 template <bool XL>
-__device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs& I, float* X, int i, int s, int b,
-                           int pb, int64_t n, int s_call) {
-  const int NS = M.n_seg;
-  const int e = M.env[i];
-  const bool skip = S.status[e] != 0u;
-  sto(M, F_SKIP, i, skip ? 1.f : 0.f);
-  if (skip) return;
-  const int par = M.par[i];
+__device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L,
+                                           int i, const In1& in, int64_t n, uint64_t kstep, int s_call) {
+  const int NS = M.n_seg, nf = M.scr_nf, li = i - L.i0;
+  const NodeRec& nr = in.nr;
+  const float2 q = in.q, qd = in.qd;
+  const float kp = in.kp, kd = in.kd;
+  uint8_t brk = in.brk;
+  const uint8_t cnt0 = in.cnt;
+  const int par = nr.topo.x, e = nr.topo.w;
+  // loads that depend on the node record, issued before the arithmetic: the env status
+  // (used only for the writes at the end) and the first apple
+  const uint32_t stat = at(S.status, (uint32_t)e);
+  const int ab = nr.aux.z, ae = ab + (nr.topo.z >> 16);
+  const uint32_t NA = (uint32_t)M.n_apple;
+  AppleRec ar0;
+  V3 sig0, va0;
+  uint8_t det00 = 0, cp00 = 0, ct00 = 0;
+  if (ab < ae) {
+    const uint32_t ua = (uint32_t)ab;
+    ar0 = at(M.arec, ua);
+    sig0 = v3(at(S.apple, ua), at(S.apple, NA + ua), at(S.apple, 2 * NA + ua));
+    va0 = v3(at(S.apple, 3 * NA + ua), at(S.apple, 4 * NA + ua), at(S.apple, 5 * NA + ua));
+    det00 = at(S.apple_evt, ua); cp00 = at(S.apple_evt, NA + ua); ct00 = at(S.apple_evt, 2 * NA + ua);
+  }
+  const float l = nr.geo.x, m = nr.geo.y, Jt = nr.geo.z, Ia = nr.geo.w;
+  const float h = M.h;
+
+  // ---- parent publication ----
   Mat3 Rp;
   V3 pj, w, vt, Aa, Al;
   bool snp;
@@ -68,39 +140,32 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
     Al = v3(-M.gx, -M.gy, -M.gz);  // gravity as a base acceleration
     snp = false;
   } else {
-    const int ps = par - pb, bp = b ^ 1;
-    for (int k = 0; k < 9; ++k) Rp.m[k] = xget<XL>(M, X, F_R, F_R + k, par, ps, bp);
-    pj = xget3<XL>(M, X, F_R, F_PT, par, ps, bp);
-    w = xget3<XL>(M, X, F_R, F_W, par, ps, bp);
-    vt = xget3<XL>(M, X, F_R, F_VT, par, ps, bp);
-    Aa = xget3<XL>(M, X, F_R, F_AVA, par, ps, bp);
-    Al = xget3<XL>(M, X, F_R, F_AVL, par, ps, bp);
-    snp = xget<XL>(M, X, F_R, F_SNAP, par, ps, bp) != 0.f;
+    for (int k = 0; k < 9; ++k) Rp.m[k] = xget<XL>(L, F_R, F_R + k, par);
+    pj = xget3<XL>(L, F_R, F_PT, par);
+    w = xget3<XL>(L, F_R, F_W, par);
+    vt = xget3<XL>(L, F_R, F_VT, par);
+    Aa = xget3<XL>(L, F_R, F_AVA, par);
+    Al = xget3<XL>(L, F_R, F_AVL, par);
+    snp = xget<XL>(L, F_R, F_SNAP, par) != 0.f;
   }
-  const float2 q = S.q[i], qd = S.qd[i];
-  const float kp = I.kp[i], kd = I.kd[i];
-  const float4 g4 = M.geo[i];
-  const float l = g4.x, m = g4.y, Jt = g4.z, Ia = g4.w;
-  const float h = M.h;
 
   // ---- rupture test on the state at the start of the step (Eq. break) ----
-  uint8_t brk = S.seg_evt[i];
-  if (!brk) {
+  const bool brk0 = brk != 0;
+  int cnt1 = 0;
+  if (!brk0) {
     const float th = sqrtf(fmaf(q.x, q.x, q.y * q.y));
-    const float mu = kp * th / M.mmax[i];
-    int c = mu > 1.f ? (int)S.seg_evt[NS + i] + 1 : 0;
-    c = c > 255 ? 255 : c;
-    if (c >= M.n_break) { brk = 1; S.seg_evt[i] = 1; S.evt_step[i] = (int32_t)n; }
-    S.seg_evt[NS + i] = (uint8_t)c;
+    const float mu = kp * th * __int_as_float(nr.aux.w);
+    cnt1 = mu > 1.f ? (int)cnt0 + 1 : 0;
+    cnt1 = cnt1 > 255 ? 255 : cnt1;
+    if (cnt1 >= M.n_break) brk = 1;
   }
   snp = snp || brk;
 
   // ---- kinematics: R = R_parent Q_rest R_x(theta_x) R_y(theta_y) ----
   // the joint rotations are formed from half-angle sines (1 - cos = 2 sin^2(theta/2))
-  const float4 r = M.rq[i];
   Mat3 Q;
   {
-    const float ww = r.x, xx = r.y, yy = r.z, zz = r.w;
+    const float ww = nr.rq.x, xx = nr.rq.y, yy = nr.rq.z, zz = nr.rq.w;
     Q.m[0] = 1.f - 2.f * (yy * yy + zz * zz); Q.m[1] = 2.f * (xx * yy - ww * zz); Q.m[2] = 2.f * (xx * zz + ww * yy);
     Q.m[3] = 2.f * (xx * yy + ww * zz); Q.m[4] = 1.f - 2.f * (xx * xx + zz * zz); Q.m[5] = 2.f * (yy * zz - ww * xx);
     Q.m[6] = 2.f * (xx * zz - ww * yy); Q.m[7] = 2.f * (yy * zz + ww * xx); Q.m[8] = 1.f - 2.f * (xx * xx + yy * yy);
@@ -129,20 +194,21 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
 
   // ---- publish for children (values at the tip point) ----
   const V3 lz = l * z;
-  xput<XL>(M, X, F_R, F_R + 0, i, s, b, c0.x); xput<XL>(M, X, F_R, F_R + 1, i, s, b, c1.x); xput<XL>(M, X, F_R, F_R + 2, i, s, b, c2.x);
-  xput<XL>(M, X, F_R, F_R + 3, i, s, b, c0.y); xput<XL>(M, X, F_R, F_R + 4, i, s, b, c1.y); xput<XL>(M, X, F_R, F_R + 5, i, s, b, c2.y);
-  xput<XL>(M, X, F_R, F_R + 6, i, s, b, c0.z); xput<XL>(M, X, F_R, F_R + 7, i, s, b, c1.z); xput<XL>(M, X, F_R, F_R + 8, i, s, b, c2.z);
-  xput3<XL>(M, X, F_R, F_PT, i, s, b, pj + lz);
-  xput3<XL>(M, X, F_R, F_W, i, s, b, wi);
-  xput3<XL>(M, X, F_R, F_VT, i, s, b, v + cross(wi, lz));
-  xput3<XL>(M, X, F_R, F_AVA, i, s, b, Ava);
-  xput3<XL>(M, X, F_R, F_AVL, i, s, b, Avl + cross(Ava, lz));
-  xput<XL>(M, X, F_R, F_SNAP, i, s, b, snp ? 1.f : 0.f);
+  xput<XL>(L, F_R, F_R + 0, i, c0.x); xput<XL>(L, F_R, F_R + 1, i, c1.x); xput<XL>(L, F_R, F_R + 2, i, c2.x);
+  xput<XL>(L, F_R, F_R + 3, i, c0.y); xput<XL>(L, F_R, F_R + 4, i, c1.y); xput<XL>(L, F_R, F_R + 5, i, c2.y);
+  xput<XL>(L, F_R, F_R + 6, i, c0.z); xput<XL>(L, F_R, F_R + 7, i, c1.z); xput<XL>(L, F_R, F_R + 8, i, c2.z);
+  xput3<XL>(L, F_R, F_PT, i, pj + lz);
+  xput3<XL>(L, F_R, F_W, i, wi);
+  xput3<XL>(L, F_R, F_VT, i, v + cross(wi, lz));
+  xput3<XL>(L, F_R, F_AVA, i, Ava);
+  xput3<XL>(L, F_R, F_AVL, i, Avl + cross(Ava, lz));
+  xput<XL>(L, F_R, F_SNAP, i, snp ? 1.f : 0.f);
   if (!XL && M.save_adj) {
-    sto(M, F_SR + 0, i, c0.x); sto(M, F_SR + 1, i, c1.x); sto(M, F_SR + 2, i, c2.x);
-    sto(M, F_SR + 3, i, c0.y); sto(M, F_SR + 4, i, c1.y); sto(M, F_SR + 5, i, c2.y);
-    sto(M, F_SR + 6, i, c0.z); sto(M, F_SR + 7, i, c1.z); sto(M, F_SR + 8, i, c2.z);
-    sto3(M, F_SAVP, i, Ava); sto3(M, F_SAVP + 3, i, Avl);
+    float* P = L.P;
+    pst(P, nf, F_SR + 0, li, c0.x); pst(P, nf, F_SR + 1, li, c1.x); pst(P, nf, F_SR + 2, li, c2.x);
+    pst(P, nf, F_SR + 3, li, c0.y); pst(P, nf, F_SR + 4, li, c1.y); pst(P, nf, F_SR + 5, li, c2.y);
+    pst(P, nf, F_SR + 6, li, c0.z); pst(P, nf, F_SR + 7, li, c1.z); pst(P, nf, F_SR + 8, li, c2.z);
+    pst3(P, nf, F_SAVP, li, Ava); pst3(P, nf, F_SAVP + 3, li, Avl);
   }
 
   // ---- rigid body inertia about the joint point: axisymmetric capsule ----
@@ -154,59 +220,69 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
   float mo = m;
   // bias force p = v x* (I v)
   const V3 K = mul(Jo, wi) + cross(ho, v);
-  const V3 L = m * v - cross(ho, wi);
-  V3 pang = cross(wi, K) + cross(v, L);
-  V3 plin = cross(wi, L);
+  const V3 Lm = m * v - cross(ho, wi);
+  V3 pang = cross(wi, K) + cross(v, Lm);
+  V3 plin = cross(wi, Lm);
 
   // ---- applied body force (input and counter-based random), impulse cap, snapped mask ----
   {
     V3 F, T;
-    if (applied_force(M, I, i, e, n, s_call, m, snp, F, T)) {
+    const uint64_t hkey = (uint64_t)(uint32_t)nr.aux.x | ((uint64_t)(uint32_t)nr.aux.y << 32);
+    if (applied_force(M, I, i, kstep, s_call, m, snp, hkey, F, T)) {
       pang = pang - (T + cross(0.5f * lz, F));
       plin = plin - F;
     }
   }
 
   // ---- apples hanging from this segment ----
-  const int ab = M.apple_beg[i], ae = M.apple_beg[i + 1];
-  const int NA = M.n_apple;
+  const bool live = (stat & ST_FROZEN) == 0u;
   bool apple_bad = false;
   for (int a = ab; a < ae; ++a) {
-    const float4 hm = M.ahang[a];
-    const float4 ap = M.apar[a];
-    const float ma = hm.w, fdet = ap.x, cs = ap.y, fmax = ap.z;
-    const V3 d = fma3(hm.x, c0, fma3(hm.y, c1, hm.z * c2));
-    const V3 vh = v + cross(wi, d);
-    float* P = S.apple;
+    float* Pa = S.apple;
+    const uint32_t ua = (uint32_t)a;
     // position state: while attached sigma = (x - x_hang) + h v from the previous
     // update, so the stretch now is s = sigma - h v_hang; once detached, x minus the
     // rest hang point.  The stretch never passes through absolute positions.
-    const V3 sig = v3(P[a], P[NA + a], P[2 * NA + a]);
-    V3 va = v3(P[3 * NA + a], P[4 * NA + a], P[5 * NA + a]);
-    const uint8_t det0 = S.apple_evt[a];
-    const V3 sa = det0 ? v3(0, 0, 0) : fma3(-h, vh, sig);
+    AppleRec ar;
+    V3 sig;
+    V3 va;
+    uint8_t det0, cp0, ct0;
+    if (a == ab) {
+      ar = ar0; sig = sig0; va = va0; det0 = det00; cp0 = cp00; ct0 = ct00;
+    } else {
+      ar = at(M.arec, ua);
+      sig = v3(at(Pa, ua), at(Pa, NA + ua), at(Pa, 2 * NA + ua));
+      va = v3(at(Pa, 3 * NA + ua), at(Pa, 4 * NA + ua), at(Pa, 5 * NA + ua));
+      det0 = at(S.apple_evt, ua); cp0 = at(S.apple_evt, NA + ua); ct0 = at(S.apple_evt, 2 * NA + ua);
+    }
     V3 Fa = v3(0, 0, 0);
     if (I.aforce) {
-      const float* fp = I.aforce + (int64_t)s_call * I.aforce_stride + 3 * (int64_t)a;
-      Fa = v3(fp[0], fp[1], fp[2]);
+      const float* fp = I.aforce + (int64_t)s_call * I.aforce_stride;
+      Fa = v3(at(fp, 3 * ua), at(fp, 3 * ua + 1), at(fp, 3 * ua + 2));
     }
-    uint8_t det = S.apple_evt[a];
+    const float ma = ar.hang.w, cs = ar.par.y, fmax = ar.par.z;
+    const V3 d = fma3(ar.hang.x, c0, fma3(ar.hang.y, c1, ar.hang.z * c2));
+    const V3 vh = v + cross(wi, d);
+    const V3 sa = det0 ? v3(0, 0, 0) : fma3(-h, vh, sig);
+    uint8_t det = det0;
     if (!det) {
-      const float pi = sqrtf(dot(Fa, Fa)) / fdet;
-      const float tau = M.ks * sqrtf(dot(sa, sa)) / (M.alpha * fdet);
-      int cp = pi > 1.f ? (int)S.apple_evt[NA + a] + 1 : 0;
-      int ct = tau > 1.f ? (int)S.apple_evt[2 * NA + a] + 1 : 0;
+      const float pi = sqrtf(dot(Fa, Fa)) * ar.par.x;
+      const float tau = M.ks * sqrtf(dot(sa, sa)) * ar.par.w;
+      int cp = pi > 1.f ? (int)cp0 + 1 : 0;
+      int ct = tau > 1.f ? (int)ct0 + 1 : 0;
       cp = cp > 255 ? 255 : cp;
       ct = ct > 255 ? 255 : ct;
-      S.apple_evt[NA + a] = (uint8_t)cp;
-      S.apple_evt[2 * NA + a] = (uint8_t)ct;
       const int path = cp >= M.n_pull ? 1 : (ct >= M.n_tension ? 2 : 0);
-      if (path) {
-        det = 1;
-        S.apple_evt[a] = 1;
-        S.apple_evt[3 * NA + a] = (uint8_t)path;
-        S.evt_step[NS + a] = (int32_t)n;
+      if (live) {
+        at(S.apple_evt, NA + ua) = (uint8_t)cp;
+        at(S.apple_evt, 2 * NA + ua) = (uint8_t)ct;
+        if (path) {
+          at(S.apple_evt, ua) = 1;
+          at(S.apple_evt, 3 * NA + ua) = (uint8_t)path;
+          at(S.evt_step, (uint32_t)NS + ua) = (int32_t)n;
+        }
       }
+      if (path) det = 1;
     }
     const V3 gv = v3(M.gx, M.gy, M.gz);
     if (!det) {
@@ -214,8 +290,8 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
       // taken at the end of the step to first order (linearly implicit); the clamp
       // scales explicit part and implicit term alike by s = min(1, F_max / |f|)
       V3 fh = M.ks * fma3(-h, vh, sa) - ma * gv;
-      const float nf = sqrtf(dot(fh, fh));
-      const float sc = nf > fmax ? fmax / nf : 1.f;
+      const float nfh = sqrtf(dot(fh, fh));
+      const float sc = nfh > fmax ? fmax / nfh : 1.f;
       fh = sc * fh;
       pang = pang - cross(d, fh);
       plin = plin - fh;
@@ -236,38 +312,37 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
     // apple update: explicit symplectic Euler
     V3 fa = fma3(ma, gv, Fa);
     if (!det) fa = fa - M.ks * sa - cs * va;
-    va = fma3(h / ma, fa, va);
+    va = fma3(ar.rest.w, fa, va);
     // attached: sigma+ = s + h v+;  detached: (x - x_hang,rest)+ = x - x_hang,rest + h v+
     V3 base = sa;
-    if (det) {
-      if (det0) base = sig;
-      else {
-        const float4 hr = M.ahrest[a];
-        base = (pj + d - v3(hr.x, hr.y, hr.z)) + sa;
-      }
-    }
+    if (det) base = det0 ? sig : (pj + d - v3(ar.rest.x, ar.rest.y, ar.rest.z)) + sa;
     const V3 x = fma3(h, va, base);
-    P[a] = x.x; P[NA + a] = x.y; P[2 * NA + a] = x.z;
-    P[3 * NA + a] = va.x; P[4 * NA + a] = va.y; P[5 * NA + a] = va.z;
-    const V3 om = v3(P[10 * NA + a], P[11 * NA + a], P[12 * NA + a]);
-    const V3 hw = (0.5f * h) * om;
-    const float th = sqrtf(dot(hw, hw));
-    if (th > 0.f) {
-      float sn, cn;
-      sincosf(th, &sn, &cn);
-      const float sc = sn / th;
-      const float ew = cn, ex = sc * hw.x, ey = sc * hw.y, ez = sc * hw.z;
-      const float q0 = P[6 * NA + a], q1 = P[7 * NA + a], q2 = P[8 * NA + a], q3 = P[9 * NA + a];
-      float nw = ew * q0 - ex * q1 - ey * q2 - ez * q3;
-      float nx = ew * q1 + ex * q0 + ey * q3 - ez * q2;
-      float ny = ew * q2 - ex * q3 + ey * q0 + ez * q1;
-      float nz = ew * q3 + ex * q2 - ey * q1 + ez * q0;
-      const float inv = 1.f / sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
-      P[6 * NA + a] = nw * inv; P[7 * NA + a] = nx * inv; P[8 * NA + a] = ny * inv; P[9 * NA + a] = nz * inv;
+    if (live) {
+      at(Pa, ua) = x.x; at(Pa, NA + ua) = x.y; at(Pa, 2 * NA + ua) = x.z;
+      at(Pa, 3 * NA + ua) = va.x; at(Pa, 4 * NA + ua) = va.y; at(Pa, 5 * NA + ua) = va.z;
+      // orientation: no torque acts on an apple, so omega is carried and the quaternion
+      // only turns while omega is non-zero
+      const V3 om = v3(at(Pa, 10 * NA + ua), at(Pa, 11 * NA + ua), at(Pa, 12 * NA + ua));
+      const V3 hw = (0.5f * h) * om;
+      const float th = sqrtf(dot(hw, hw));
+      if (th > 0.f) {
+        float sn, cn;
+        sincosf(th, &sn, &cn);
+        const float scq = sn / th;
+        const float ew = cn, ex = scq * hw.x, ey = scq * hw.y, ez = scq * hw.z;
+        const float q0 = at(Pa, 6 * NA + ua), q1 = at(Pa, 7 * NA + ua), q2 = at(Pa, 8 * NA + ua), q3 = at(Pa, 9 * NA + ua);
+        float nw = ew * q0 - ex * q1 - ey * q2 - ez * q3;
+        float nx = ew * q1 + ex * q0 + ey * q3 - ez * q2;
+        float ny = ew * q2 - ex * q3 + ey * q0 + ez * q1;
+        float nz = ew * q3 + ex * q2 - ey * q1 + ez * q0;
+        const float inv = 1.f / sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
+        at(Pa, 6 * NA + ua) = nw * inv; at(Pa, 7 * NA + ua) = nx * inv; at(Pa, 8 * NA + ua) = ny * inv;
+        at(Pa, 9 * NA + ua) = nz * inv;
+      }
     }
     apple_bad = apple_bad || !finite3(x) || !finite3(va);
   }
-  if (apple_bad) atomicOr(&S.status[e], 1u);
+  if (live && apple_bad) atomicOr(&at(S.status, (uint32_t)e), ST_APPLE_BAD);
 
   // ---- spring / damper, implicit diagonal ----
   const float kpe = brk ? 0.f : kp, kde = brk ? 0.f : kd;
@@ -275,32 +350,71 @@ __device__ void node_down1(const DevModel& M, const DevState& S, const DevInputs
   const float tau1 = -kpe * fmaf(h, qd.y, q.y) - kde * qd.y;
   const float dg = fmaf(h, kde, h * h * kpe);
 
-  sto3(M, F_A0, i, a0); sto3(M, F_A1, i, a1);
-  sto3(M, F_C, i, cang); sto3(M, F_C + 3, i, clin);
-  sto3(M, F_P, i, pang); sto3(M, F_P + 3, i, plin);
-  sto(M, F_MO, i, mo); sto3(M, F_HO, i, ho);
-  sto(M, F_JO + 0, i, Jo.xx); sto(M, F_JO + 1, i, Jo.yy); sto(M, F_JO + 2, i, Jo.zz);
-  sto(M, F_JO + 3, i, Jo.xy); sto(M, F_JO + 4, i, Jo.xz); sto(M, F_JO + 5, i, Jo.yz);
-  sto(M, F_TAU, i, tau0); sto(M, F_TAU + 1, i, tau1);
-  sto(M, F_DG, i, dg);
-  sto3(M, F_LZ, i, lz);
+  // ---- event and frozen-flag writes ----
+  if (live && !brk0) {
+    at(S.seg_evt, (uint32_t)(NS + i)) = (uint8_t)cnt1;
+    if (brk) { at(S.seg_evt, (uint32_t)i) = 1; at(S.evt_step, (uint32_t)i) = (int32_t)n; }
+  }
+  float* P = L.P;
+  pst(P, nf, F_SKIP, li, live ? 0.f : 1.f);
+  pst3(P, nf, F_A0, li, a0); pst3(P, nf, F_A1, li, a1);
+  pst3(P, nf, F_C, li, cang); pst3(P, nf, F_C + 3, li, clin);
+  pst3(P, nf, F_P, li, pang); pst3(P, nf, F_P + 3, li, plin);
+  pst(P, nf, F_MO, li, mo); pst3(P, nf, F_HO, li, ho);
+  pst(P, nf, F_JO + 0, li, Jo.xx); pst(P, nf, F_JO + 1, li, Jo.yy); pst(P, nf, F_JO + 2, li, Jo.zz);
+  pst(P, nf, F_JO + 3, li, Jo.xy); pst(P, nf, F_JO + 4, li, Jo.xz); pst(P, nf, F_JO + 5, li, Jo.yz);
+  pst(P, nf, F_TAU, li, tau0); pst(P, nf, F_TAU + 1, li, tau1);
+  pst(P, nf, F_DG, li, dg);
+  pst3(P, nf, F_LZ, li, lz);
 }
 
 // ------------------------------------------------------------------------------------------
 // up pass: gather children's articulated inertia / bias, factor the 2x2 pivot
 // ------------------------------------------------------------------------------------------
-// i: node, s: its slot, b: its level's buffer, nb: first node of the next level
+// up-pass inputs: the node's own data from down 1
+struct InU {
+  int4 topo;
+  V3 r, ho, pon, pof, a0, a1, ca, cl;
+  Sym3 Jo;
+  float mo, dg, tau0, tau1;
+};
+__device__ __forceinline__ InU loadU(const DevModel& M, const Lvl& L, int i) {
+  const int nf = M.scr_nf, li = i - L.i0;
+  const float* P = L.P;
+  InU u;
+  u.topo = at(M.nrec, (uint32_t)i).topo;
+  u.r = pld3(P, nf, F_LZ, li);
+  u.mo = pld(P, nf, F_MO, li);
+  u.ho = pld3(P, nf, F_HO, li);
+  u.Jo = Sym3{pld(P, nf, F_JO + 0, li), pld(P, nf, F_JO + 1, li), pld(P, nf, F_JO + 2, li),
+              pld(P, nf, F_JO + 3, li), pld(P, nf, F_JO + 4, li), pld(P, nf, F_JO + 5, li)};
+  u.pon = pld3(P, nf, F_P, li);
+  u.pof = pld3(P, nf, F_P + 3, li);
+  u.a0 = pld3(P, nf, F_A0, li);
+  u.a1 = pld3(P, nf, F_A1, li);
+  u.dg = pld(P, nf, F_DG, li);
+  u.tau0 = pld(P, nf, F_TAU, li);
+  u.tau1 = pld(P, nf, F_TAU + 1, li);
+  u.ca = pld3(P, nf, F_C, li);
+  u.cl = pld3(P, nf, F_C + 3, li);
+  return u;
+}
+
 template <bool XL>
-__device__ void node_up(const DevModel& M, float* X, int i, int s, int b, int nb) {
-  if (ld(M, F_SKIP, i) != 0.f) return;
+__device__ __forceinline__ void node_up(const DevModel& M, const Lvl& L, int i, const InU& in) {
+  const int nf = M.scr_nf, li = i - L.i0;
+  const int4 topo = in.topo;
+  const V3 r = in.r, ho = in.ho, pon = in.pon, pof = in.pof, a0 = in.a0, a1 = in.a1, ca = in.ca, cl = in.cl;
+  const float mo = in.mo, dg = in.dg, tau0 = in.tau0, tau1 = in.tau1;
+  const Sym3 Jo = in.Jo;
+
   Sym3 A{0, 0, 0, 0, 0, 0}, Mm{0, 0, 0, 0, 0, 0};
   Mat3 B;
   for (int k = 0; k < 9; ++k) B.m[k] = 0.f;
   V3 pn = v3(0, 0, 0), pf = v3(0, 0, 0);
-  const int cb = M.child[i], ce = cb + M.nchild[i];
+  const int cb = topo.y, ce = cb + (topo.z & 0xFFFF);
   for (int c = cb; c < ce; ++c) {
-    const int cs = c - nb, bc = b ^ 1;
-#define XG(f) xget<XL>(M, X, F_IA, (f), c, cs, bc)
+#define XG(f) xget<XL>(L, F_IA, (f), c)
     A.xx += XG(F_IA + 0); A.yy += XG(F_IA + 1); A.zz += XG(F_IA + 2);
     A.xy += XG(F_IA + 3); A.xz += XG(F_IA + 4); A.yz += XG(F_IA + 5);
     for (int k = 0; k < 9; ++k) B.m[k] += XG(F_IB + k);
@@ -310,7 +424,6 @@ __device__ void node_up(const DevModel& M, float* X, int i, int s, int b, int nb
     pf = pf + v3(XG(F_PA + 3), XG(F_PA + 4), XG(F_PA + 5));
 #undef XG
   }
-  const V3 r = ld3(M, F_LZ, i);
   if (ce > cb) {
     // move the children's sum from the tip to the joint point (translation by r):
     // A' = A - B[r] - (B[r])^T - [r]M[r],  B' = B + [r]M,  M' = M,  n' = n + r x f
@@ -330,35 +443,29 @@ __device__ void node_up(const DevModel& M, float* X, int i, int s, int b, int nb
     pn = pn + cross(r, pf);
   }
   // add the node's own body (+ virtual apple masses) and bias
-  {
-    const float mo = ld(M, F_MO, i);
-    const V3 ho = ld3(M, F_HO, i);
-    A.xx += ld(M, F_JO + 0, i); A.yy += ld(M, F_JO + 1, i); A.zz += ld(M, F_JO + 2, i);
-    A.xy += ld(M, F_JO + 3, i); A.xz += ld(M, F_JO + 4, i); A.yz += ld(M, F_JO + 5, i);
-    // B += [h]
-    B.m[1] -= ho.z; B.m[2] += ho.y; B.m[3] += ho.z; B.m[5] -= ho.x; B.m[6] -= ho.y; B.m[7] += ho.x;
-    Mm.xx += mo; Mm.yy += mo; Mm.zz += mo;
-    pn = pn + ld3(M, F_P, i);
-    pf = pf + ld3(M, F_P + 3, i);
-  }
+  A.xx += Jo.xx; A.yy += Jo.yy; A.zz += Jo.zz; A.xy += Jo.xy; A.xz += Jo.xz; A.yz += Jo.yz;
+  // B += [h]
+  B.m[1] -= ho.z; B.m[2] += ho.y; B.m[3] += ho.z; B.m[5] -= ho.x; B.m[6] -= ho.y; B.m[7] += ho.x;
+  Mm.xx += mo; Mm.yy += mo; Mm.zz += mo;
+  pn = pn + pon;
+  pf = pf + pof;
   if (!XL && M.save_adj) {
-    sto(M, F_SIA + 0, i, A.xx); sto(M, F_SIA + 1, i, A.yy); sto(M, F_SIA + 2, i, A.zz);
-    sto(M, F_SIA + 3, i, A.xy); sto(M, F_SIA + 4, i, A.xz); sto(M, F_SIA + 5, i, A.yz);
-    for (int k = 0; k < 9; ++k) sto(M, F_SIA + 6 + k, i, B.m[k]);
-    sto(M, F_SIA + 15, i, Mm.xx); sto(M, F_SIA + 16, i, Mm.yy); sto(M, F_SIA + 17, i, Mm.zz);
-    sto(M, F_SIA + 18, i, Mm.xy); sto(M, F_SIA + 19, i, Mm.xz); sto(M, F_SIA + 20, i, Mm.yz);
-    sto3(M, F_SPA, i, pn); sto3(M, F_SPA + 3, i, pf);
+    float* Pw = L.P;
+    pst(Pw, nf, F_SIA + 0, li, A.xx); pst(Pw, nf, F_SIA + 1, li, A.yy); pst(Pw, nf, F_SIA + 2, li, A.zz);
+    pst(Pw, nf, F_SIA + 3, li, A.xy); pst(Pw, nf, F_SIA + 4, li, A.xz); pst(Pw, nf, F_SIA + 5, li, A.yz);
+    for (int k = 0; k < 9; ++k) pst(Pw, nf, F_SIA + 6 + k, li, B.m[k]);
+    pst(Pw, nf, F_SIA + 15, li, Mm.xx); pst(Pw, nf, F_SIA + 16, li, Mm.yy); pst(Pw, nf, F_SIA + 17, li, Mm.zz);
+    pst(Pw, nf, F_SIA + 18, li, Mm.xy); pst(Pw, nf, F_SIA + 19, li, Mm.xz); pst(Pw, nf, F_SIA + 20, li, Mm.yz);
+    pst3(Pw, nf, F_SPA, li, pn); pst3(Pw, nf, F_SPA + 3, li, pf);
   }
-  const V3 a0 = ld3(M, F_A0, i), a1 = ld3(M, F_A1, i);
-  const float dg = ld(M, F_DG, i);
   // U = I^A S,  S = [a0 a1; 0 0]
   const V3 U0a = mul(A, a0), U1a = mul(A, a1);
   const V3 U0l = mulT(B, a0), U1l = mulT(B, a1);
   const float D00 = dot(a0, U0a) + dg, D01 = dot(a0, U1a), D11 = dot(a1, U1a) + dg;
   const float idet = 1.f / fmaf(D00, D11, -D01 * D01);
   const float Di00 = D11 * idet, Di01 = -D01 * idet, Di11 = D00 * idet;
-  const float uu0 = ld(M, F_TAU, i) - dot(a0, pn);
-  const float uu1 = ld(M, F_TAU + 1, i) - dot(a1, pn);
+  const float uu0 = tau0 - dot(a0, pn);
+  const float uu1 = tau1 - dot(a1, pn);
   // W = U D^-1
   const V3 W0a = fma3(Di00, U0a, Di01 * U1a), W1a = fma3(Di01, U0a, Di11 * U1a);
   const V3 W0l = fma3(Di00, U0l, Di01 * U1l), W1l = fma3(Di01, U0l, Di11 * U1l);
@@ -373,10 +480,9 @@ __device__ void node_up(const DevModel& M, float* X, int i, int s, int b, int nb
   Mm.zz -= W0l.z * U0l.z + W1l.z * U1l.z; Mm.xy -= W0l.x * U0l.y + W1l.x * U1l.y;
   Mm.xz -= W0l.x * U0l.z + W1l.x * U1l.z; Mm.yz -= W0l.y * U0l.z + W1l.y * U1l.z;
   // bias passed to the parent: p^A + I^a c + W u
-  const V3 ca = ld3(M, F_C, i), cl = ld3(M, F_C + 3, i);
   pn = pn + mul(A, ca) + mul(B, cl) + fma3(uu0, W0a, uu1 * W1a);
   pf = pf + mulT(B, ca) + mul(Mm, cl) + fma3(uu0, W0l, uu1 * W1l);
-#define XP(f, v) xput<XL>(M, X, F_IA, (f), i, s, b, (v))
+#define XP(f, v) xput<XL>(L, F_IA, (f), i, (v))
   XP(F_IA + 0, A.xx); XP(F_IA + 1, A.yy); XP(F_IA + 2, A.zz);
   XP(F_IA + 3, A.xy); XP(F_IA + 4, A.xz); XP(F_IA + 5, A.yz);
   for (int k = 0; k < 9; ++k) XP(F_IB + k, B.m[k]);
@@ -385,79 +491,222 @@ __device__ void node_up(const DevModel& M, float* X, int i, int s, int b, int nb
   XP(F_PA + 0, pn.x); XP(F_PA + 1, pn.y); XP(F_PA + 2, pn.z);
   XP(F_PA + 3, pf.x); XP(F_PA + 4, pf.y); XP(F_PA + 5, pf.z);
 #undef XP
-  sto3(M, F_U, i, U0a); sto3(M, F_U + 3, i, U0l); sto3(M, F_U + 6, i, U1a); sto3(M, F_U + 9, i, U1l);
-  sto(M, F_DI, i, Di00); sto(M, F_DI + 1, i, Di01); sto(M, F_DI + 2, i, Di11);
-  sto(M, F_UU, i, uu0); sto(M, F_UU + 1, i, uu1);
+  float* Pw = L.P;
+  pst3(Pw, nf, F_U, li, U0a); pst3(Pw, nf, F_U + 3, li, U0l); pst3(Pw, nf, F_U + 6, li, U1a); pst3(Pw, nf, F_U + 9, li, U1l);
+  pst(Pw, nf, F_DI, li, Di00); pst(Pw, nf, F_DI + 1, li, Di01); pst(Pw, nf, F_DI + 2, li, Di11);
+  pst(Pw, nf, F_UU, li, uu0); pst(Pw, nf, F_UU + 1, li, uu1);
 }
 
 // ------------------------------------------------------------------------------------------
 // down pass 2: accelerations and integration
 // ------------------------------------------------------------------------------------------
-// i: node, s: its slot, b: its level's buffer, pb: first node of the parent level
+// down 2 inputs: the node's factor data from the up pass and its state
+struct In2 {
+  int4 topo;
+  float skip, uu0, uu1, Di00, Di01, Di11;
+  V3 ca, cl, U0a, U0l, U1a, U1l, a0, a1, lz;
+  float2 q, qd;
+};
+__device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const Lvl& L, int i) {
+  const int nf = M.scr_nf, li = i - L.i0;
+  const float* P = L.P;
+  In2 d;
+  d.topo = at(M.nrec, (uint32_t)i).topo;
+  d.skip = pld(P, nf, F_SKIP, li);
+  d.ca = pld3(P, nf, F_C, li);
+  d.cl = pld3(P, nf, F_C + 3, li);
+  d.U0a = pld3(P, nf, F_U, li);
+  d.U0l = pld3(P, nf, F_U + 3, li);
+  d.U1a = pld3(P, nf, F_U + 6, li);
+  d.U1l = pld3(P, nf, F_U + 9, li);
+  d.uu0 = pld(P, nf, F_UU, li);
+  d.uu1 = pld(P, nf, F_UU + 1, li);
+  d.Di00 = pld(P, nf, F_DI, li);
+  d.Di01 = pld(P, nf, F_DI + 1, li);
+  d.Di11 = pld(P, nf, F_DI + 2, li);
+  d.a0 = pld3(P, nf, F_A0, li);
+  d.a1 = pld3(P, nf, F_A1, li);
+  d.lz = pld3(P, nf, F_LZ, li);
+  d.q = at(S.q, (uint32_t)i);
+  d.qd = at(S.qd, (uint32_t)i);
+  return d;
+}
+
 template <bool XL>
-__device__ void node_down2(const DevModel& M, const DevState& S, float* X, int i, int s, int b, int pb) {
-  if (ld(M, F_SKIP, i) != 0.f) return;
-  const int par = M.par[i];
+__device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S, const Lvl& L, int i, const In2& in) {
+  const int nf = M.scr_nf, li = i - L.i0;
+  const int par = in.topo.x, e = in.topo.w;
+  const bool live = in.skip == 0.f;
+  const V3 ca = in.ca, cl = in.cl, U0a = in.U0a, U0l = in.U0l, U1a = in.U1a, U1l = in.U1l;
+  const float uu0 = in.uu0, uu1 = in.uu1, Di00 = in.Di00, Di01 = in.Di01, Di11 = in.Di11;
+  const V3 a0 = in.a0, a1 = in.a1, lz = in.lz;
+  float2 q = in.q, qd = in.qd;
   V3 Aa, Al;
   if (par < 0) { Aa = v3(0, 0, 0); Al = v3(-M.gx, -M.gy, -M.gz); }
   else {
-    const int ps = par - pb, bp = b ^ 1;
-    Aa = xget3<XL>(M, X, F_AT, F_AT, par, ps, bp);
-    Al = xget3<XL>(M, X, F_AT, F_AT + 3, par, ps, bp);
+    Aa = xget3<XL>(L, F_AT, F_AT, par);
+    Al = xget3<XL>(L, F_AT, F_AT + 3, par);
   }
-  Aa = Aa + ld3(M, F_C, i);
-  Al = Al + ld3(M, F_C + 3, i);
-  const V3 U0a = ld3(M, F_U, i), U0l = ld3(M, F_U + 3, i), U1a = ld3(M, F_U + 6, i), U1l = ld3(M, F_U + 9, i);
-  const float t0 = ld(M, F_UU, i) - (dot(U0a, Aa) + dot(U0l, Al));
-  const float t1 = ld(M, F_UU + 1, i) - (dot(U1a, Aa) + dot(U1l, Al));
-  const float Di00 = ld(M, F_DI, i), Di01 = ld(M, F_DI + 1, i), Di11 = ld(M, F_DI + 2, i);
+  Aa = Aa + ca;
+  Al = Al + cl;
+  const float t0 = uu0 - (dot(U0a, Aa) + dot(U0l, Al));
+  const float t1 = uu1 - (dot(U1a, Aa) + dot(U1l, Al));
   const float qdd0 = fmaf(Di00, t0, Di01 * t1);
   const float qdd1 = fmaf(Di01, t0, Di11 * t1);
-  const V3 a0 = ld3(M, F_A0, i), a1 = ld3(M, F_A1, i);
   Aa = fma3(qdd0, a0, fma3(qdd1, a1, Aa));
-  const V3 lz = ld3(M, F_LZ, i);
   if (!XL && M.save_adj) {
-    sto3(M, F_SA, i, Aa); sto3(M, F_SA + 3, i, Al);
-    sto(M, F_SQDD, i, qdd0); sto(M, F_SQDD + 1, i, qdd1);
+    float* Pw = L.P;
+    pst3(Pw, nf, F_SA, li, Aa); pst3(Pw, nf, F_SA + 3, li, Al);
+    pst(Pw, nf, F_SQDD, li, qdd0); pst(Pw, nf, F_SQDD + 1, li, qdd1);
   }
-  xput3<XL>(M, X, F_AT, F_AT, i, s, b, Aa);
-  xput3<XL>(M, X, F_AT, F_AT + 3, i, s, b, Al + cross(Aa, lz));
+  xput3<XL>(L, F_AT, F_AT, i, Aa);
+  xput3<XL>(L, F_AT, F_AT + 3, i, Al + cross(Aa, lz));
+  if (!live) return;
   const float h = M.h;
-  float2 q = S.q[i], qd = S.qd[i];
   qd.x = fmaf(h, qdd0, qd.x);
   qd.y = fmaf(h, qdd1, qd.y);
   q.x = fmaf(h, qd.x, q.x);
   q.y = fmaf(h, qd.y, q.y);
-  S.q[i] = q;
-  S.qd[i] = qd;
-  if (!(isfinite(q.x) && isfinite(q.y) && isfinite(qd.x) && isfinite(qd.y))) atomicOr(&S.status[M.env[i]], 1u);
+  at(S.q, (uint32_t)i) = q;
+  at(S.qd, (uint32_t)i) = qd;
+  uint32_t* st = &at(S.status, (uint32_t)e);
+  if (!(isfinite(q.x) && isfinite(q.y) && isfinite(qd.x) && isfinite(qd.y))) atomicOr(st, ST_FROZEN);
+  // the root promotes this step's apple flag once every node of the step has run down 1
+  if (par < 0 && (*st & ST_APPLE_BAD)) atomicOr(st, ST_FROZEN);
 }
 
 // ------------------------------------------------------------------------------------------
 // pack kernels
 // ------------------------------------------------------------------------------------------
+// Between levels the LDS path needs only the LDS exchange to be complete (node-private
+// scratch is written and read back by the same thread); pass ends are full barriers.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+template <bool XL>
+__device__ __forceinline__ void level_barrier() {
+  if constexpr (XL) lds_barrier();
+  else __syncthreads();
+}
+
+// Global exchange: any number of nodes per thread and level, loads then arithmetic.
+template <int NT>
+__device__ __forceinline__ void run_pack_global(const DevModel& M, const DevState& S, const DevInputs& I, Lvl& L,
+                                                int lb, int le, int64_t n0, int n_inner, int call_step0) {
+  for (int st = 0; st < n_inner; ++st) {
+    const int64_t n = n0 + st;
+    const uint64_t kstep = splitmix64((uint64_t)n);
+    for (int lv = lb; lv < le; ++lv) {
+      L.a = M.lvl_off[lv];
+      const int e = M.lvl_off[lv + 1];
+      L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
+      for (int i = L.a + (int)threadIdx.x; i < e; i += NT)
+        node_down1<false>(M, S, I, L, i, load1(M, S, I, i), n, kstep, call_step0 + st);
+      __syncthreads();
+    }
+    for (int lv = le - 1; lv >= lb; --lv) {
+      L.a = M.lvl_off[lv];
+      const int e = M.lvl_off[lv + 1];
+      L.nbr = e;
+      for (int i = L.a + (int)threadIdx.x; i < e; i += NT) node_up<false>(M, L, i, loadU(M, L, i));
+      __syncthreads();
+    }
+    for (int lv = lb; lv < le; ++lv) {
+      L.a = M.lvl_off[lv];
+      const int e = M.lvl_off[lv + 1];
+      L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
+      for (int i = L.a + (int)threadIdx.x; i < e; i += NT) node_down2<false>(M, S, L, i, load2(M, S, L, i));
+      __syncthreads();
+    }
+  }
+}
+
+// LDS exchange: at most one node per thread and level (level width <= lds_width <=
+// threads).  Each pass is software-pipelined: the loads of this thread's node on the
+// next level are issued before the current level's arithmetic; they read only static
+// data, data this thread wrote itself, or data completed before the pass began.
+template <int NT>
+__device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& S, const DevInputs& I, Lvl& L,
+                                             int lb, int le, int64_t n0, int n_inner, int call_step0) {
+  const int t = (int)threadIdx.x;
+  for (int st = 0; st < n_inner; ++st) {
+    const int64_t n = n0 + st;
+    const uint64_t kstep = splitmix64((uint64_t)n);
+    {
+      int i = M.lvl_off[lb] + t;
+      bool has = i < M.lvl_off[lb + 1];
+      In1 cur{};
+      if (has) cur = load1(M, S, I, i);
+      for (int lv = lb; lv < le; ++lv) {
+        L.a = M.lvl_off[lv];
+        L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
+        L.b = (lv - lb) & 1;
+        const int in_ = M.lvl_off[lv + 1] + t;
+        const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
+        In1 nxt{};
+        if (hn) nxt = load1(M, S, I, in_);
+        if (has) node_down1<true>(M, S, I, L, i, cur, n, kstep, call_step0 + st);
+        if (lv + 1 < le) lds_barrier();
+        i = in_; has = hn; cur = nxt;
+      }
+    }
+    __syncthreads();
+    {
+      int i = M.lvl_off[le - 1] + t;
+      bool has = i < M.lvl_off[le];
+      InU cur{};
+      if (has) cur = loadU(M, L, i);
+      for (int lv = le - 1; lv >= lb; --lv) {
+        L.a = M.lvl_off[lv];
+        L.nbr = M.lvl_off[lv + 1];
+        L.b = (lv - lb) & 1;
+        const int in_ = lv > lb ? M.lvl_off[lv - 1] + t : 0;
+        const bool hn = lv > lb && in_ < M.lvl_off[lv];
+        InU nxt{};
+        if (hn) nxt = loadU(M, L, in_);
+        if (has) node_up<true>(M, L, i, cur);
+        if (lv > lb) lds_barrier();
+        i = in_; has = hn; cur = nxt;
+      }
+    }
+    __syncthreads();
+    {
+      int i = M.lvl_off[lb] + t;
+      bool has = i < M.lvl_off[lb + 1];
+      In2 cur{};
+      if (has) cur = load2(M, S, L, i);
+      for (int lv = lb; lv < le; ++lv) {
+        L.a = M.lvl_off[lv];
+        L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
+        L.b = (lv - lb) & 1;
+        const int in_ = M.lvl_off[lv + 1] + t;
+        const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
+        In2 nxt{};
+        if (hn) nxt = load2(M, S, L, in_);
+        if (has) node_down2<true>(M, S, L, i, cur);
+        if (lv + 1 < le) lds_barrier();
+        i = in_; has = hn; cur = nxt;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int NT, bool XL>
 __device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, const DevInputs& I, float* X, int pk,
                                          int64_t n0, int n_inner, int call_step0) {
   const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
-  for (int st = 0; st < n_inner; ++st) {
-    const int64_t n = n0 + st;
-    for (int lv = lb; lv < le; ++lv) {
-      const int a = M.lvl_off[lv], e = M.lvl_off[lv + 1], pb = lv > lb ? M.lvl_off[lv - 1] : a, b = (lv - lb) & 1;
-      for (int i = a + (int)threadIdx.x; i < e; i += NT) node_down1<XL>(M, S, I, X, i, i - a, b, pb, n, call_step0 + st);
-      __syncthreads();
-    }
-    for (int lv = le - 1; lv >= lb; --lv) {
-      const int a = M.lvl_off[lv], e = M.lvl_off[lv + 1], b = (lv - lb) & 1;
-      for (int i = a + (int)threadIdx.x; i < e; i += NT) node_up<XL>(M, X, i, i - a, b, e);
-      __syncthreads();
-    }
-    for (int lv = lb; lv < le; ++lv) {
-      const int a = M.lvl_off[lv], e = M.lvl_off[lv + 1], pb = lv > lb ? M.lvl_off[lv - 1] : a, b = (lv - lb) & 1;
-      for (int i = a + (int)threadIdx.x; i < e; i += NT) node_down2<XL>(M, S, X, i, i - a, b, pb);
-      __syncthreads();
-    }
-  }
+  Lvl L;
+  L.i0 = M.pack_node[pk] & ~63;
+  L.nf = M.scr_nf;
+  L.P = M.scr + (size_t)(L.i0 >> 6) * (size_t)L.nf * 64u;
+  L.X = X;
+  L.cap = M.lds_cap;
+  L.b = 0;
+  if constexpr (XL) run_pack_lds<NT>(M, S, I, L, lb, le, n0, n_inner, call_step0);
+  else run_pack_global<NT>(M, S, I, L, lb, le, n0, n_inner, call_step0);
 }
 
 template <int NT>

@@ -34,12 +34,14 @@ class Desc(C.Structure):
 
 
 # the library's defaults (orchard_model_create with a null tuning)
-DEFAULT_TUNING = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0, adjoint_ckpt_max=0, lds_width=256)
+DEFAULT_TUNING = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0, adjoint_ckpt_max=0, lds_width=128,
+                      pack_skew=0)
 
 
 class Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("pack_fill", C.c_float), ("steps_per_launch", C.c_int32),
-                ("persistent", C.c_int32), ("adjoint_ckpt_max", C.c_int32), ("lds_width", C.c_int32)]
+                ("persistent", C.c_int32), ("adjoint_ckpt_max", C.c_int32), ("lds_width", C.c_int32),
+                ("pack_skew", C.c_int32)]
 
 
 class CAdjoint(C.Structure):
@@ -214,8 +216,10 @@ def _desc(batch, consts: dict, keep: list) -> Desc:
 def _tuning(t: dict) -> Tuning:
     u = dict(DEFAULT_TUNING)
     u.update(t)
+    if "lds_width" not in t:
+        u["lds_width"] = min(int(u["lds_width"]), int(u["threads"]))
     return Tuning(int(u["threads"]), float(u["pack_fill"]), int(u["steps_per_launch"]), int(u["persistent"]),
-                  int(u["adjoint_ckpt_max"]), int(u["lds_width"]))
+                  int(u["adjoint_ckpt_max"]), int(u["lds_width"]), int(u["pack_skew"]))
 
 
 def _tuning_dict(t: Tuning) -> dict:
@@ -256,7 +260,7 @@ def autotune(batch, consts: dict, candidates: list | None = None, n_warm: int = 
     import torch
     if candidates is None:
         candidates = [dict(threads=t, pack_fill=f, lds_width=w)
-                      for t in (64, 128, 256) for f in (1.0, 2.0) for w in (0, 128, 256, 384)]
+                      for t in (64, 128, 256) for f in (1.0, 2.0) for w in (0, t)]
     sig = hashlib.sha256()
     for name in ("seg_offset", "seg_parent", "apple_offset"):
         sig.update(np.ascontiguousarray(getattr(batch, name), dtype=np.int32).tobytes())

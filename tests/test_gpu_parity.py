@@ -76,8 +76,9 @@ def test_large_trees_and_small_trees_one_launch():
     dict(threads=64, pack_fill=0.0), dict(threads=128, pack_fill=1.0), dict(threads=256, pack_fill=2.0),
     dict(threads=512, pack_fill=1.0, persistent=1), dict(threads=128, pack_fill=1.0, steps_per_launch=7),
     dict(threads=256, pack_fill=1.0, persistent=1, steps_per_launch=10),
-    dict(threads=64, pack_fill=1.0, lds_width=64), dict(threads=256, pack_fill=2.0, lds_width=512),
-    dict(threads=128, pack_fill=1.0, lds_width=0)])
+    dict(threads=64, pack_fill=1.0, lds_width=64), dict(threads=256, pack_fill=2.0, lds_width=256),
+    dict(threads=128, pack_fill=1.0, lds_width=0), dict(threads=128, pack_fill=1.0, lds_width=48),
+    dict(threads=128, pack_fill=1.0, lds_width=128, pack_skew=1), dict(threads=64, pack_fill=2.0, lds_width=64, pack_skew=1)])
 def test_mappings_are_bitwise_identical(tuning):
     # the mapping (workgroup per tree, exchange through LDS or global scratch) changes
     # which workgroup walks a tree and where levels hand data over, never the
@@ -140,7 +141,7 @@ def test_nonfinite_env_is_flagged_and_frozen():
     st.q.copy_(q)
     m.step(st, kp, kd, 3)
     status = m.status(st)
-    assert status[bad_env] == 1 and np.all(np.delete(status, bad_env) == 0)
+    assert status[bad_env] & 1 and np.all(np.delete(status, bad_env) == 0)
     frozen = st.q.cpu().numpy()
     m.step(st, kp, kd, 4)
     mine = np.flatnonzero(np.isin(m.seg_map, np.arange(b.seg_offset[bad_env], b.seg_offset[bad_env + 1])))

@@ -17,7 +17,7 @@ def _snapshot(m, st):
             st.evt_step.cpu().numpy().copy(), int(st.step.item()))
 
 
-@pytest.mark.parametrize("tuning", [dict(threads=128, pack_fill=1.0, lds_width=256),
+@pytest.mark.parametrize("tuning", [dict(threads=128, pack_fill=1.0, lds_width=128),
                                     dict(threads=256, pack_fill=1.0, persistent=1, steps_per_launch=4)])
 def test_graph_replays_equal_eager_steps(tuning):
     from paper_2607_06337_amd import Model
@@ -49,8 +49,8 @@ def test_autotune_returns_the_fastest_candidate(tmp_path):
     from paper_2607_06337_amd import autotune
     b = make_batch("uneven8192", env_ids=range(64))
     c = step_constants("uneven8192")
-    cands = [dict(threads=64, pack_fill=1.0, lds_width=0), dict(threads=128, pack_fill=1.0, lds_width=256),
-             dict(threads=256, pack_fill=0.0, lds_width=512)]
+    cands = [dict(threads=64, pack_fill=1.0, lds_width=0), dict(threads=128, pack_fill=1.0, lds_width=128),
+             dict(threads=256, pack_fill=0.0, lds_width=256)]
     cache = str(tmp_path / "tune.json")
     best, timings = autotune(b, c, cands, n_warm=2, n_steps=5, cache=cache)
     ms = [t[1] for t in timings]
