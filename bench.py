@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # kernel mapping used by the benchmark (and by the full-size parity test)
-BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=1, persistent=0, lds_width=256)
+BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=1, persistent=0, lds_width=240)
 # the plain per-step kernel: one 256-thread workgroup per tree, one launch per step,
 # levels exchange through global scratch
 PLAIN_TUNING = dict(threads=256, pack_fill=0.0, steps_per_launch=1, persistent=0, lds_width=0)

@@ -511,7 +511,12 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     arec[k].hang = ahang_h[k];
     arec[k].par = make_float4((float)(1.0 / fdet), apar_h[k].y, apar_h[k].z, (float)(1.0 / (d->tension_factor * fdet)));
     arec[k].rest = make_float4(ahrest_h[k].x, ahrest_h[k].y, ahrest_h[k].z, (float)(d->dt / ma));
+    const int node = int_of[aseg_g[a]];
+    arec[k].link = make_int4(node, apple_env[k], 0, 0);
   }
+  std::vector<int32_t> pack_apl(pack_node.size());
+  for (size_t p = 0; p + 1 < pack_node.size(); ++p) pack_apl[p] = apple_beg[pack_node[p]];
+  pack_apl.back() = (int32_t)NA;
 
   // ---- device layout ----
   orchard_model_s* M = new orchard_model_s();
@@ -537,7 +542,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
          o_kp = ar.put(kp_f.data(), NS * 4), o_kd = ar.put(kd_f.data(), NS * 4), o_ar = ar.put(arest.data(), 3 * NA * 4),
          o_hr = ar.put(ahrest_h.data(), NA * 16), o_pd = ar.put(pack_lds.data(), pack_lds.size() * 4),
          o_nr = ar.put(nrec.data(), NS * sizeof(NodeRec)), o_ar2 = ar.put(arec.data(), NA * sizeof(AppleRec)),
-         o_hk = ar.put(hkey.data(), NS * 8),
+         o_hk = ar.put(hkey.data(), NS * 8), o_pa = ar.put(pack_apl.data(), pack_apl.size() * 4),
          o_q = ar.put(&zero, 4 * 16);
   hipError_t he = hipMalloc(&M->arena, ar.off + 256);
   if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
@@ -567,9 +572,11 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.ahrest = (const float4*)(base + o_hr); dm.pack_lds = (const int32_t*)(base + o_pd);
   dm.nrec = (const NodeRec*)(base + o_nr); dm.arec = (const AppleRec*)(base + o_ar2);
   dm.hkey = (const uint64_t*)(base + o_hk);
+  dm.pack_apl = (const int32_t*)(base + o_pa);
   dm.scr_nf = scr_nf;
   dm.lds_cap = n_lds_packs > 0 ? tun.lds_width : 0;
-  M->lds_bytes = (size_t)dm.lds_cap * 2 * N_PUB_MAX * 4;
+  // dynamic LDS of the step kernels: the level exchange, reused by the apple phase
+  M->lds_bytes = std::max((size_t)dm.lds_cap * 2 * N_PUB_MAX, (size_t)11 * tun.threads) * 4;
   M->kp0 = (float*)(base + o_kp); M->kd0 = (float*)(base + o_kd); M->apple_rest = (float*)(base + o_ar);
   dm.queue = (int32_t*)(base + o_q);
   dm.h = (float)d->dt;
@@ -597,9 +604,11 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     const int64_t words = orchard_ckpt_words(M);
     M->adj_kmax = tun.adjoint_ckpt_max;
     const size_t rb = (size_t)M->adj_kmax * (size_t)words * 4;
-    // work state: q, qd (float2), apple (13A), seg_evt (2S), apple_evt (4A), evt_step (S+A), status (B), step
-    const size_t wb = 16 * (size_t)NS + 52 * (size_t)NA + 256 + 2 * (size_t)NS + 4 * (size_t)NA + 256 +
-                      4 * (size_t)(NS + NA) + 256 + 4 * (size_t)B + 256 + 64;
+    // work state: q, qd (float2), apple (13A), seg_evt (2S), apple_evt (4A), evt_step (S+A), status (B),
+    // step; every piece starts on a 256-byte boundary
+    auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t wb = 2 * r256(8 * (size_t)NS) + r256(52 * (size_t)NA) + r256(2 * (size_t)NS) + r256(4 * (size_t)NA) +
+                      r256(4 * (size_t)(NS + NA)) + r256(4 * (size_t)B) + r256(8);
     if (hipMalloc(&M->recs, rb) != hipSuccess || hipMalloc(&M->work, wb) != hipSuccess) {
       orchard_model_destroy(M);
       return fail(ORCHARD_ERR_OUT_OF_MEMORY, "adjoint buffers");
@@ -686,10 +695,10 @@ static orchard_status_t launch_steps(orchard_model_t m, const DevState& ds, cons
     dm.save_adj = 1;
     const dim3 g(m->n_pack);
     switch (NT) {
-      case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), 0, stream, dm, ds, di, k, s_call); break;
-      case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), 0, stream, dm, ds, di, k, s_call); break;
-      case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), 0, stream, dm, ds, di, k, s_call); break;
-      default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), 0, stream, dm, ds, di, k, s_call); break;
+      case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, stream, dm, ds, di, k, s_call); break;
+      case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), lb, stream, dm, ds, di, k, s_call); break;
+      case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lb, stream, dm, ds, di, k, s_call); break;
+      default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), lb, stream, dm, ds, di, k, s_call); break;
     }
   } else if (m->tun.persistent) {
     const dim3 g(m->persist_blocks);

@@ -42,30 +42,37 @@ enum : int {
   F_U = 87,         // 12: U = I^A S (col 0: ang 3 lin 3, col 1: ang 3 lin 3)
   F_DI = 99,        // 3: D^-1 (00 01 11)
   F_UU = 102,       // 2: u = tau - S^T p^A
-  N_FIELDS = 104,
+  // kinematics of a node that carries apples, kept for the apple phase
+  F_KR = 104,       // 9: body rotation, row major
+  F_KW = 113,       // 3: angular velocity
+  F_KV = 116,       // 3: velocity of the joint point
+  F_KAA = 119,      // 3: velocity-product (+ base) acceleration at the joint point, angular
+  F_KAL = 122,      // 3:   linear
+  F_KPJ = 125,      // 3: joint point (absolute)
+  N_FIELDS = 128,
   // second down pass publication (6) overwrites the first six fields
   F_AT = 0,         // 6: acceleration at the tip (ang, lin)
   N_PUB_MAX = 27,
   // ---- fields of the adjoint ----
   // saved by the forward step in save mode
-  F_SR = 104,       // 9: body rotation, row major
-  F_SAVP = 113,     // 6: velocity-product (+ base) acceleration at the joint point
-  F_SIA = 119,      // 21: articulated inertia before the pivot update (A 6, B 9, M 6)
-  F_SPA = 140,      // 6: articulated bias before the pivot update
-  F_SA = 146,       // 6: total acceleration at the joint point
-  F_SQDD = 152,     // 2: joint accelerations
+  F_SR = 128,       // 9: body rotation, row major
+  F_SAVP = 137,     // 6: velocity-product (+ base) acceleration at the joint point
+  F_SIA = 143,      // 21: articulated inertia before the pivot update (A 6, B 9, M 6)
+  F_SPA = 164,      // 6: articulated bias before the pivot update
+  F_SA = 170,       // 6: total acceleration at the joint point
+  F_SQDD = 176,     // 2: joint accelerations
   // adjoint passes
-  F_LU = 154,       // 2: u of the solve M lambda = qdd_bar
-  F_LPA = 156,      // 6: bias of that solve passed to the parent
-  F_LA = 162,       // 6: acceleration of that solve at the tip
-  F_NU = 168,       // 6: virtual velocity nu at the joint point
-  F_LAM = 174,      // 2: lambda
-  F_RB = 176,       // 24: reverse-pass publication: tau_bar 3, omega_bar 3, vt_bar 3, At_bar 6, Avt_bar 6, f_lin 3
-  N_FIELDS_ADJ = 200
+  F_LU = 178,       // 2: u of the solve M lambda = qdd_bar
+  F_LPA = 180,      // 6: bias of that solve passed to the parent
+  F_LA = 186,       // 6: acceleration of that solve at the tip
+  F_NU = 192,       // 6: virtual velocity nu at the joint point
+  F_LAM = 198,      // 2: lambda
+  F_RB = 200,       // 24: reverse-pass publication: tau_bar 3, omega_bar 3, vt_bar 3, At_bar 6, Avt_bar 6, f_lin 3
+  N_FIELDS_ADJ = 224
 };
 
-// Static records read by the forward step: one 64-byte record per node and one 48-byte
-// record per apple (a few wide loads instead of one load per array).
+// Static records read by the forward step: one 64-byte record per node and one per apple
+// (a few wide loads instead of one load per array).
 struct NodeRec {
   float4 rq;    // rest quaternion (w, x, y, z)
   float4 geo;   // (l, m, Jt about the joint, Ia)
@@ -76,6 +83,7 @@ struct AppleRec {
   float4 hang;  // hang point in the segment frame, mass
   float4 par;   // (1 / f_det, c_s, F_max, 1 / (alpha f_det))
   float4 rest;  // rest hang point (origin of a detached apple's position), h / m
+  int4 link;    // (node, env, unused, unused)
 };
 
 struct DevModel {
@@ -86,6 +94,7 @@ struct DevModel {
   const int32_t* pack_lvl;
   const int32_t* lvl_off;
   const int32_t* pack_lds;   // 1: every level of the pack fits the workgroup (LDS publications)
+  const int32_t* pack_apl;   // [n_pack+1] apples of pack p: pack_apl[p] .. pack_apl[p+1]-1
   const NodeRec* nrec;       // per node (internal order)
   const AppleRec* arec;      // per apple (internal order)
   // per node (internal order)

@@ -112,21 +112,9 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   uint8_t brk = in.brk;
   const uint8_t cnt0 = in.cnt;
   const int par = nr.topo.x, e = nr.topo.w;
-  // loads that depend on the node record, issued before the arithmetic: the env status
-  // (used only for the writes at the end) and the first apple
+  // the env status depends on the node record; it is issued before the arithmetic and
+  // used only by the writes at the end
   const uint32_t stat = at(S.status, (uint32_t)e);
-  const int ab = nr.aux.z, ae = ab + (nr.topo.z >> 16);
-  const uint32_t NA = (uint32_t)M.n_apple;
-  AppleRec ar0;
-  V3 sig0, va0;
-  uint8_t det00 = 0, cp00 = 0, ct00 = 0;
-  if (ab < ae) {
-    const uint32_t ua = (uint32_t)ab;
-    ar0 = at(M.arec, ua);
-    sig0 = v3(at(S.apple, ua), at(S.apple, NA + ua), at(S.apple, 2 * NA + ua));
-    va0 = v3(at(S.apple, 3 * NA + ua), at(S.apple, 4 * NA + ua), at(S.apple, 5 * NA + ua));
-    det00 = at(S.apple_evt, ua); cp00 = at(S.apple_evt, NA + ua); ct00 = at(S.apple_evt, 2 * NA + ua);
-  }
   const float l = nr.geo.x, m = nr.geo.y, Jt = nr.geo.z, Ia = nr.geo.w;
   const float h = M.h;
 
@@ -213,11 +201,11 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
 
   // ---- rigid body inertia about the joint point: axisymmetric capsule ----
   const float ml2 = 0.5f * m * l;
-  V3 ho = ml2 * z;
+  const V3 ho = ml2 * z;
   const float dJ = Ia - Jt;
-  Sym3 Jo{fmaf(dJ, z.x * z.x, Jt), fmaf(dJ, z.y * z.y, Jt), fmaf(dJ, z.z * z.z, Jt), dJ * z.x * z.y, dJ * z.x * z.z,
+  const Sym3 Jo{fmaf(dJ, z.x * z.x, Jt), fmaf(dJ, z.y * z.y, Jt), fmaf(dJ, z.z * z.z, Jt), dJ * z.x * z.y, dJ * z.x * z.z,
           dJ * z.y * z.z};
-  float mo = m;
+  const float mo = m;
   // bias force p = v x* (I v)
   const V3 K = mul(Jo, wi) + cross(ho, v);
   const V3 Lm = m * v - cross(ho, wi);
@@ -234,115 +222,17 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     }
   }
 
-  // ---- apples hanging from this segment ----
   const bool live = (stat & ST_FROZEN) == 0u;
-  bool apple_bad = false;
-  for (int a = ab; a < ae; ++a) {
-    float* Pa = S.apple;
-    const uint32_t ua = (uint32_t)a;
-    // position state: while attached sigma = (x - x_hang) + h v from the previous
-    // update, so the stretch now is s = sigma - h v_hang; once detached, x minus the
-    // rest hang point.  The stretch never passes through absolute positions.
-    AppleRec ar;
-    V3 sig;
-    V3 va;
-    uint8_t det0, cp0, ct0;
-    if (a == ab) {
-      ar = ar0; sig = sig0; va = va0; det0 = det00; cp0 = cp00; ct0 = ct00;
-    } else {
-      ar = at(M.arec, ua);
-      sig = v3(at(Pa, ua), at(Pa, NA + ua), at(Pa, 2 * NA + ua));
-      va = v3(at(Pa, 3 * NA + ua), at(Pa, 4 * NA + ua), at(Pa, 5 * NA + ua));
-      det0 = at(S.apple_evt, ua); cp0 = at(S.apple_evt, NA + ua); ct0 = at(S.apple_evt, 2 * NA + ua);
-    }
-    V3 Fa = v3(0, 0, 0);
-    if (I.aforce) {
-      const float* fp = I.aforce + (int64_t)s_call * I.aforce_stride;
-      Fa = v3(at(fp, 3 * ua), at(fp, 3 * ua + 1), at(fp, 3 * ua + 2));
-    }
-    const float ma = ar.hang.w, cs = ar.par.y, fmax = ar.par.z;
-    const V3 d = fma3(ar.hang.x, c0, fma3(ar.hang.y, c1, ar.hang.z * c2));
-    const V3 vh = v + cross(wi, d);
-    const V3 sa = det0 ? v3(0, 0, 0) : fma3(-h, vh, sig);
-    uint8_t det = det0;
-    if (!det) {
-      const float pi = sqrtf(dot(Fa, Fa)) * ar.par.x;
-      const float tau = M.ks * sqrtf(dot(sa, sa)) * ar.par.w;
-      int cp = pi > 1.f ? (int)cp0 + 1 : 0;
-      int ct = tau > 1.f ? (int)ct0 + 1 : 0;
-      cp = cp > 255 ? 255 : cp;
-      ct = ct > 255 ? 255 : ct;
-      const int path = cp >= M.n_pull ? 1 : (ct >= M.n_tension ? 2 : 0);
-      if (live) {
-        at(S.apple_evt, NA + ua) = (uint8_t)cp;
-        at(S.apple_evt, 2 * NA + ua) = (uint8_t)ct;
-        if (path) {
-          at(S.apple_evt, ua) = 1;
-          at(S.apple_evt, 3 * NA + ua) = (uint8_t)path;
-          at(S.evt_step, (uint32_t)NS + ua) = (int32_t)n;
-        }
-      }
-      if (path) det = 1;
-    }
-    const V3 gv = v3(M.gx, M.gy, M.gz);
-    if (!det) {
-      // reaction on the spur: elastic tether force minus static weight, hang point
-      // taken at the end of the step to first order (linearly implicit); the clamp
-      // scales explicit part and implicit term alike by s = min(1, F_max / |f|)
-      V3 fh = M.ks * fma3(-h, vh, sa) - ma * gv;
-      const float nfh = sqrtf(dot(fh, fh));
-      const float sc = nfh > fmax ? fmax / nfh : 1.f;
-      fh = sc * fh;
-      pang = pang - cross(d, fh);
-      plin = plin - fh;
-      {
-        // virtual point mass s h^2 k_s at the hang point (only its q-acceleration part)
-        const float mv = sc * h * h * M.ks;
-        mo += mv;
-        ho = fma3(mv, d, ho);
-        const float dd = dot(d, d);
-        Jo.xx = fmaf(mv, dd - d.x * d.x, Jo.xx); Jo.yy = fmaf(mv, dd - d.y * d.y, Jo.yy);
-        Jo.zz = fmaf(mv, dd - d.z * d.z, Jo.zz); Jo.xy = fmaf(-mv, d.x * d.y, Jo.xy);
-        Jo.xz = fmaf(-mv, d.x * d.z, Jo.xz); Jo.yz = fmaf(-mv, d.y * d.z, Jo.yz);
-        const V3 wvp = Avl + cross(Ava, d);
-        pang = pang - mv * cross(d, wvp);
-        plin = plin - mv * wvp;
-      }
-    }
-    // apple update: explicit symplectic Euler
-    V3 fa = fma3(ma, gv, Fa);
-    if (!det) fa = fa - M.ks * sa - cs * va;
-    va = fma3(ar.rest.w, fa, va);
-    // attached: sigma+ = s + h v+;  detached: (x - x_hang,rest)+ = x - x_hang,rest + h v+
-    V3 base = sa;
-    if (det) base = det0 ? sig : (pj + d - v3(ar.rest.x, ar.rest.y, ar.rest.z)) + sa;
-    const V3 x = fma3(h, va, base);
-    if (live) {
-      at(Pa, ua) = x.x; at(Pa, NA + ua) = x.y; at(Pa, 2 * NA + ua) = x.z;
-      at(Pa, 3 * NA + ua) = va.x; at(Pa, 4 * NA + ua) = va.y; at(Pa, 5 * NA + ua) = va.z;
-      // orientation: no torque acts on an apple, so omega is carried and the quaternion
-      // only turns while omega is non-zero
-      const V3 om = v3(at(Pa, 10 * NA + ua), at(Pa, 11 * NA + ua), at(Pa, 12 * NA + ua));
-      const V3 hw = (0.5f * h) * om;
-      const float th = sqrtf(dot(hw, hw));
-      if (th > 0.f) {
-        float sn, cn;
-        sincosf(th, &sn, &cn);
-        const float scq = sn / th;
-        const float ew = cn, ex = scq * hw.x, ey = scq * hw.y, ez = scq * hw.z;
-        const float q0 = at(Pa, 6 * NA + ua), q1 = at(Pa, 7 * NA + ua), q2 = at(Pa, 8 * NA + ua), q3 = at(Pa, 9 * NA + ua);
-        float nw = ew * q0 - ex * q1 - ey * q2 - ez * q3;
-        float nx = ew * q1 + ex * q0 + ey * q3 - ez * q2;
-        float ny = ew * q2 - ex * q3 + ey * q0 + ez * q1;
-        float nz = ew * q3 + ex * q2 - ey * q1 + ez * q0;
-        const float inv = 1.f / sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
-        at(Pa, 6 * NA + ua) = nw * inv; at(Pa, 7 * NA + ua) = nx * inv; at(Pa, 8 * NA + ua) = ny * inv;
-        at(Pa, 9 * NA + ua) = nz * inv;
-      }
-    }
-    apple_bad = apple_bad || !finite3(x) || !finite3(va);
+  // apples are handled by the apple phase after this pass; keep what it needs
+  if (nr.topo.z >> 16) {
+    float* P = L.P;
+    pst(P, nf, F_KR + 0, li, c0.x); pst(P, nf, F_KR + 1, li, c1.x); pst(P, nf, F_KR + 2, li, c2.x);
+    pst(P, nf, F_KR + 3, li, c0.y); pst(P, nf, F_KR + 4, li, c1.y); pst(P, nf, F_KR + 5, li, c2.y);
+    pst(P, nf, F_KR + 6, li, c0.z); pst(P, nf, F_KR + 7, li, c1.z); pst(P, nf, F_KR + 8, li, c2.z);
+    pst3(P, nf, F_KW, li, wi); pst3(P, nf, F_KV, li, v);
+    pst3(P, nf, F_KAA, li, Ava); pst3(P, nf, F_KAL, li, Avl);
+    pst3(P, nf, F_KPJ, li, pj);
   }
-  if (live && apple_bad) atomicOr(&at(S.status, (uint32_t)e), ST_APPLE_BAD);
 
   // ---- spring / damper, implicit diagonal ----
   const float kpe = brk ? 0.f : kp, kde = brk ? 0.f : kd;
@@ -371,6 +261,174 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
 // ------------------------------------------------------------------------------------------
 // up pass: gather children's articulated inertia / bias, factor the 2x2 pivot
 // ------------------------------------------------------------------------------------------
+// Between levels the LDS path needs only the LDS exchange to be complete (node-private
+// scratch is written and read back by the same thread); pass ends are full barriers.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ------------------------------------------------------------------------------------------
+// apple phase (between down 1 and up): every apple of the pack at once
+// ------------------------------------------------------------------------------------------
+// Thread per apple over chunks of NT apples: events, the reaction on the spur and the
+// virtual point mass at the hang point (from the node's kinematics kept by down 1), and
+// the apple's own update.  A node's apples are contiguous; the thread holding a node's
+// first apple of the chunk adds the chunk's contributions to the node's bias and own
+// inertia in apple order, so the sums do not depend on the mapping.
+struct AppleCon { float mv; V3 d, pang, plin; };
+
+template <int NT>
+__device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L,
+                                            float* C, int pk, int64_t n, int s_call) {
+  const int A0 = M.pack_apl[pk], A1 = M.pack_apl[pk + 1];
+  const int NS = M.n_seg, nf = M.scr_nf, t = (int)threadIdx.x;
+  const uint32_t NA = (uint32_t)M.n_apple;
+  const float h = M.h;
+  const V3 gv = v3(M.gx, M.gy, M.gz);
+  // C: [11][NT] LDS, the chunk's contributions and node ids
+  for (int c0 = A0; c0 < A1; c0 += NT) {
+    const int a = c0 + t;
+    const bool has = a < A1;
+    AppleCon con{0.f, v3(0, 0, 0), v3(0, 0, 0), v3(0, 0, 0)};
+    int node = -1;
+    if (has) {
+      const uint32_t ua = (uint32_t)a;
+      const AppleRec ar = at(M.arec, ua);
+      node = ar.link.x;
+      const int li = node - L.i0;
+      const float* P = L.P;
+      const bool live = pld(P, nf, F_SKIP, li) == 0.f;
+      Mat3 R;
+      for (int k = 0; k < 9; ++k) R.m[k] = pld(P, nf, F_KR + k, li);
+      const V3 wi = pld3(P, nf, F_KW, li), v = pld3(P, nf, F_KV, li);
+      const V3 Ava = pld3(P, nf, F_KAA, li), Avl = pld3(P, nf, F_KAL, li), pj = pld3(P, nf, F_KPJ, li);
+      float* Pa = S.apple;
+      // position state: while attached sigma = (x - x_hang) + h v from the previous
+      // update, so the stretch now is s = sigma - h v_hang; once detached, x minus the
+      // rest hang point.  The stretch never passes through absolute positions.
+      const V3 sig = v3(at(Pa, ua), at(Pa, NA + ua), at(Pa, 2 * NA + ua));
+      V3 va = v3(at(Pa, 3 * NA + ua), at(Pa, 4 * NA + ua), at(Pa, 5 * NA + ua));
+      const uint8_t det0 = at(S.apple_evt, ua), cp0 = at(S.apple_evt, NA + ua), ct0 = at(S.apple_evt, 2 * NA + ua);
+      V3 Fa = v3(0, 0, 0);
+      if (I.aforce) {
+        const float* fp = I.aforce + (int64_t)s_call * I.aforce_stride;
+        Fa = v3(at(fp, 3 * ua), at(fp, 3 * ua + 1), at(fp, 3 * ua + 2));
+      }
+      const float ma = ar.hang.w, cs = ar.par.y, fmax = ar.par.z;
+      // hang point offset from the joint point: R (hx, hy, hz) by columns of R
+      const V3 d = fma3(ar.hang.x, v3(R.m[0], R.m[3], R.m[6]),
+                        fma3(ar.hang.y, v3(R.m[1], R.m[4], R.m[7]), ar.hang.z * v3(R.m[2], R.m[5], R.m[8])));
+      const V3 vh = v + cross(wi, d);
+      const V3 sa = det0 ? v3(0, 0, 0) : fma3(-h, vh, sig);
+      uint8_t det = det0;
+      if (!det) {
+        const float pi = sqrtf(dot(Fa, Fa)) * ar.par.x;
+        const float tau = M.ks * sqrtf(dot(sa, sa)) * ar.par.w;
+        int cp = pi > 1.f ? (int)cp0 + 1 : 0;
+        int ct = tau > 1.f ? (int)ct0 + 1 : 0;
+        cp = cp > 255 ? 255 : cp;
+        ct = ct > 255 ? 255 : ct;
+        const int path = cp >= M.n_pull ? 1 : (ct >= M.n_tension ? 2 : 0);
+        if (live) {
+          at(S.apple_evt, NA + ua) = (uint8_t)cp;
+          at(S.apple_evt, 2 * NA + ua) = (uint8_t)ct;
+          if (path) {
+            at(S.apple_evt, ua) = 1;
+            at(S.apple_evt, 3 * NA + ua) = (uint8_t)path;
+            at(S.evt_step, (uint32_t)NS + ua) = (int32_t)n;
+          }
+        }
+        if (path) det = 1;
+      }
+      if (!det) {
+        // reaction on the spur: elastic tether force minus static weight, hang point
+        // taken at the end of the step to first order (linearly implicit); the clamp
+        // scales explicit part and implicit term alike by s = min(1, F_max / |f|)
+        V3 fh = M.ks * fma3(-h, vh, sa) - ma * gv;
+        const float nfh = sqrtf(dot(fh, fh));
+        const float sc = nfh > fmax ? fmax / nfh : 1.f;
+        fh = sc * fh;
+        // virtual point mass s h^2 k_s at the hang point (only its q-acceleration part)
+        const float mv = sc * h * h * M.ks;
+        const V3 wvp = Avl + cross(Ava, d);
+        con.mv = mv;
+        con.d = d;
+        con.pang = (-1.f) * (cross(d, fh) + mv * cross(d, wvp));
+        con.plin = (-1.f) * (fh + mv * wvp);
+      }
+      // apple update: explicit symplectic Euler
+      V3 fa = fma3(ma, gv, Fa);
+      if (!det) fa = fa - M.ks * sa - cs * va;
+      va = fma3(ar.rest.w, fa, va);
+      // attached: sigma+ = s + h v+;  detached: (x - x_hang,rest)+ = x - x_hang,rest + h v+
+      V3 base = sa;
+      if (det) base = det0 ? sig : (pj + d - v3(ar.rest.x, ar.rest.y, ar.rest.z)) + sa;
+      const V3 x = fma3(h, va, base);
+      if (live) {
+        at(Pa, ua) = x.x; at(Pa, NA + ua) = x.y; at(Pa, 2 * NA + ua) = x.z;
+        at(Pa, 3 * NA + ua) = va.x; at(Pa, 4 * NA + ua) = va.y; at(Pa, 5 * NA + ua) = va.z;
+        // orientation: no torque acts on an apple, so omega is carried and the
+        // quaternion only turns while omega is non-zero
+        const V3 om = v3(at(Pa, 10 * NA + ua), at(Pa, 11 * NA + ua), at(Pa, 12 * NA + ua));
+        const V3 hw = (0.5f * h) * om;
+        const float th = sqrtf(dot(hw, hw));
+        if (th > 0.f) {
+          float sn, cn;
+          sincosf(th, &sn, &cn);
+          const float scq = sn / th;
+          const float ew = cn, ex = scq * hw.x, ey = scq * hw.y, ez = scq * hw.z;
+          const float q0 = at(Pa, 6 * NA + ua), q1 = at(Pa, 7 * NA + ua), q2 = at(Pa, 8 * NA + ua), q3 = at(Pa, 9 * NA + ua);
+          float nw = ew * q0 - ex * q1 - ey * q2 - ez * q3;
+          float nx = ew * q1 + ex * q0 + ey * q3 - ez * q2;
+          float ny = ew * q2 - ex * q3 + ey * q0 + ez * q1;
+          float nz = ew * q3 + ex * q2 - ey * q1 + ez * q0;
+          const float inv = 1.f / sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
+          at(Pa, 6 * NA + ua) = nw * inv; at(Pa, 7 * NA + ua) = nx * inv; at(Pa, 8 * NA + ua) = ny * inv;
+          at(Pa, 9 * NA + ua) = nz * inv;
+        }
+        if (!finite3(x) || !finite3(va)) atomicOr(&at(S.status, (uint32_t)ar.link.y), ST_APPLE_BAD);
+      }
+    }
+    C[0 * NT + t] = con.mv;
+    C[1 * NT + t] = con.d.x; C[2 * NT + t] = con.d.y; C[3 * NT + t] = con.d.z;
+    C[4 * NT + t] = con.pang.x; C[5 * NT + t] = con.pang.y; C[6 * NT + t] = con.pang.z;
+    C[7 * NT + t] = con.plin.x; C[8 * NT + t] = con.plin.y; C[9 * NT + t] = con.plin.z;
+    C[10 * NT + t] = __int_as_float(node);
+    lds_barrier();
+    // the thread with a node's first apple in this chunk adds the chunk's contributions
+    if (has && (t == 0 || __float_as_int(C[10 * NT + t - 1]) != node)) {
+      float* P = L.P;
+      const int li = node - L.i0;
+      float mo = pld(P, nf, F_MO, li);
+      V3 ho = pld3(P, nf, F_HO, li);
+      Sym3 Jo{pld(P, nf, F_JO + 0, li), pld(P, nf, F_JO + 1, li), pld(P, nf, F_JO + 2, li),
+              pld(P, nf, F_JO + 3, li), pld(P, nf, F_JO + 4, li), pld(P, nf, F_JO + 5, li)};
+      V3 pang = pld3(P, nf, F_P, li), plin = pld3(P, nf, F_P + 3, li);
+      for (int k = t; k < NT && c0 + k < A1 && __float_as_int(C[10 * NT + k]) == node; ++k) {
+        const float mv = C[0 * NT + k];
+        const V3 d = v3(C[1 * NT + k], C[2 * NT + k], C[3 * NT + k]);
+        mo += mv;
+        ho = fma3(mv, d, ho);
+        const float dd = dot(d, d);
+        Jo.xx = fmaf(mv, dd - d.x * d.x, Jo.xx); Jo.yy = fmaf(mv, dd - d.y * d.y, Jo.yy);
+        Jo.zz = fmaf(mv, dd - d.z * d.z, Jo.zz); Jo.xy = fmaf(-mv, d.x * d.y, Jo.xy);
+        Jo.xz = fmaf(-mv, d.x * d.z, Jo.xz); Jo.yz = fmaf(-mv, d.y * d.z, Jo.yz);
+        pang = pang + v3(C[4 * NT + k], C[5 * NT + k], C[6 * NT + k]);
+        plin = plin + v3(C[7 * NT + k], C[8 * NT + k], C[9 * NT + k]);
+      }
+      pst(P, nf, F_MO, li, mo);
+      pst3(P, nf, F_HO, li, ho);
+      pst(P, nf, F_JO + 0, li, Jo.xx); pst(P, nf, F_JO + 1, li, Jo.yy); pst(P, nf, F_JO + 2, li, Jo.zz);
+      pst(P, nf, F_JO + 3, li, Jo.xy); pst(P, nf, F_JO + 4, li, Jo.xz); pst(P, nf, F_JO + 5, li, Jo.yz);
+      pst3(P, nf, F_P, li, pang); pst3(P, nf, F_P + 3, li, plin);
+    }
+    // node sums of this chunk are visible to the next chunk's threads; the LDS can be reused
+    __syncthreads();
+  }
+}
+
 // up-pass inputs: the node's own data from down 1
 struct InU {
   int4 topo;
@@ -578,13 +636,6 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
 // ------------------------------------------------------------------------------------------
 // pack kernels
 // ------------------------------------------------------------------------------------------
-// Between levels the LDS path needs only the LDS exchange to be complete (node-private
-// scratch is written and read back by the same thread); pass ends are full barriers.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 template <bool XL>
 __device__ __forceinline__ void level_barrier() {
   if constexpr (XL) lds_barrier();
@@ -594,7 +645,8 @@ __device__ __forceinline__ void level_barrier() {
 // Global exchange: any number of nodes per thread and level, loads then arithmetic.
 template <int NT>
 __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevState& S, const DevInputs& I, Lvl& L,
-                                                int lb, int le, int64_t n0, int n_inner, int call_step0) {
+                                                float* Abuf, int pk, int lb, int le, int64_t n0, int n_inner,
+                                                int call_step0) {
   for (int st = 0; st < n_inner; ++st) {
     const int64_t n = n0 + st;
     const uint64_t kstep = splitmix64((uint64_t)n);
@@ -606,6 +658,7 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
         node_down1<false>(M, S, I, L, i, load1(M, S, I, i), n, kstep, call_step0 + st);
       __syncthreads();
     }
+    apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
     for (int lv = le - 1; lv >= lb; --lv) {
       L.a = M.lvl_off[lv];
       const int e = M.lvl_off[lv + 1];
@@ -629,7 +682,8 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
 // data, data this thread wrote itself, or data completed before the pass began.
 template <int NT>
 __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& S, const DevInputs& I, Lvl& L,
-                                             int lb, int le, int64_t n0, int n_inner, int call_step0) {
+                                             float* Abuf, int pk, int lb, int le, int64_t n0, int n_inner,
+                                             int call_step0) {
   const int t = (int)threadIdx.x;
   for (int st = 0; st < n_inner; ++st) {
     const int64_t n = n0 + st;
@@ -653,6 +707,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
       }
     }
     __syncthreads();
+    apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
     {
       int i = M.lvl_off[le - 1] + t;
       bool has = i < M.lvl_off[le];
@@ -695,8 +750,8 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
 }
 
 template <int NT, bool XL>
-__device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, const DevInputs& I, float* X, int pk,
-                                         int64_t n0, int n_inner, int call_step0) {
+__device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, const DevInputs& I, float* X,
+                                         float* Abuf, int pk, int64_t n0, int n_inner, int call_step0) {
   const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
   Lvl L;
   L.i0 = M.pack_node[pk] & ~63;
@@ -705,30 +760,31 @@ __device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, c
   L.X = X;
   L.cap = M.lds_cap;
   L.b = 0;
-  if constexpr (XL) run_pack_lds<NT>(M, S, I, L, lb, le, n0, n_inner, call_step0);
-  else run_pack_global<NT>(M, S, I, L, lb, le, n0, n_inner, call_step0);
+  if constexpr (XL) run_pack_lds<NT>(M, S, I, L, Abuf, pk, lb, le, n0, n_inner, call_step0);
+  else run_pack_global<NT>(M, S, I, L, Abuf, pk, lb, le, n0, n_inner, call_step0);
 }
 
 template <int NT>
-__device__ __forceinline__ void run_pack_any(const DevModel& M, const DevState& S, const DevInputs& I, float* X, int pk,
-                                             int64_t n0, int n_inner, int call_step0) {
-  if (M.lds_cap > 0 && !M.save_adj && M.pack_lds[pk]) run_pack<NT, true>(M, S, I, X, pk, n0, n_inner, call_step0);
-  else run_pack<NT, false>(M, S, I, X, pk, n0, n_inner, call_step0);
+__device__ __forceinline__ void run_pack_any(const DevModel& M, const DevState& S, const DevInputs& I, float* X,
+                                             float* Abuf, int pk, int64_t n0, int n_inner, int call_step0) {
+  if (M.lds_cap > 0 && !M.save_adj && M.pack_lds[pk]) run_pack<NT, true>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
+  else run_pack<NT, false>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
 }
 
-// one workgroup per pack; dynamic LDS: 2 * N_PUB_MAX * lds_cap floats
+// one workgroup per pack; dynamic LDS: max(2 * N_PUB_MAX * lds_cap, 11 * NT) floats, the
+// level exchange and, between down 1 and up, the apple phase's chunk buffer
 template <int NT>
 __global__ __launch_bounds__(NT) void k_step_packs(DevModel M, DevState S, DevInputs I, int n_inner, int call_step0) {
-  extern __shared__ float xlds[];
+  HIP_DYNAMIC_SHARED(float, xlds)
   const int64_t n0 = *S.step;
-  run_pack_any<NT>(M, S, I, xlds, (int)blockIdx.x, n0, n_inner, call_step0);
+  run_pack_any<NT>(M, S, I, xlds, xlds, (int)blockIdx.x, n0, n_inner, call_step0);
 }
 
 // persistent grid: workgroups pull packs (largest first) from a counter
 template <int NT>
 __global__ __launch_bounds__(NT) void k_step_persistent(DevModel M, DevState S, DevInputs I, int n_inner,
                                                         int call_step0, int32_t* counter) {
-  extern __shared__ float xlds[];
+  HIP_DYNAMIC_SHARED(float, xlds)
   __shared__ int pk;
   const int64_t n0 = *S.step;
   for (;;) {
@@ -737,7 +793,7 @@ __global__ __launch_bounds__(NT) void k_step_persistent(DevModel M, DevState S, 
     const int p = pk;
     __syncthreads();
     if (p >= M.n_pack) break;
-    run_pack_any<NT>(M, S, I, xlds, p, n0, n_inner, call_step0);
+    run_pack_any<NT>(M, S, I, xlds, xlds, p, n0, n_inner, call_step0);
   }
 }
 
