@@ -103,6 +103,7 @@ typedef struct {
   int32_t persistent;           /* 1: persistent grid pulling packs from a queue      */
   int32_t adjoint_ckpt_max;     /* > 0: allocate recompute buffers for                */
                                 /*   orchard_step_backward with ckpt_every up to this */
+                                /*   (K scratch copies and K + 1 state records)       */
   int32_t lds_width;
   int32_t pack_skew;
 } orchard_tuning_t;
@@ -204,7 +205,8 @@ typedef struct {
 /* Reverse-mode gradient of a rollout (growth direction "differentiation"):
  * given the checkpoints a forward orchard_step call wrote (ckpt, ckpt_every <=
  * tuning.adjoint_ckpt_max) and, in adj, dL/dS_T of the state after its n_steps
- * steps, recompute each checkpoint segment and walk the steps backwards: per step
+ * steps, recompute each checkpoint segment once (every step keeps what its reverse
+ * pass reads in a scratch copy of its own) and walk the steps backwards: per step
  * lambda = Mt^-1 (h dL/dqd+) with the step's own factorisation (Mt is symmetric),
  * then the reverse of the inverse dynamics, kinematics, apple tether and reaction
  * and of the implicit-Euler update, with every discrete switch of the forward

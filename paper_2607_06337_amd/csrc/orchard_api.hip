@@ -75,7 +75,9 @@ struct orchard_model_s {
   int persist_blocks = 0;
   // adjoint support
   int32_t adj_kmax = 0;
-  float* recs = nullptr;       // [adj_kmax][ckpt words]
+  float* recs = nullptr;       // [adj_kmax + 1][ckpt words]
+  float* reps = nullptr;       // [adj_kmax - 1] scratch replicas (the main scratch is replica 0)
+  size_t scr_bytes = 0;
   void* work = nullptr;        // work state
   DevState ws{};
 };
@@ -490,6 +492,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   if (NS > (1LL << 25) || NA > (1LL << 25))
     return fail(ORCHARD_ERR_INVALID_ARG, "at most 2^25 segments and 2^25 apples per model (32-bit offsets)");
   std::vector<NodeRec> nrec(NS);
+  std::vector<int4> ntopo(NS);
   std::vector<uint64_t> hkey(NS);
   for (int64_t i = 0; i < NS; ++i) {
     const int napp = apple_beg[i + 1] - apple_beg[i];
@@ -503,6 +506,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     nrec[i].geo = geo[i];
     nrec[i].topo = make_int4(par_i[i], child_i[i], nchild_i[i] | (napp << 16), env_i[i]);
     nrec[i].aux = make_int4((int32_t)(uint32_t)(hkey[i] & 0xFFFFFFFFull), (int32_t)(uint32_t)(hkey[i] >> 32), apple_beg[i], bits);
+    ntopo[i] = nrec[i].topo;
   }
   std::vector<AppleRec> arec(NA);
   for (int64_t k = 0; k < NA; ++k) {
@@ -543,6 +547,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
          o_hr = ar.put(ahrest_h.data(), NA * 16), o_pd = ar.put(pack_lds.data(), pack_lds.size() * 4),
          o_nr = ar.put(nrec.data(), NS * sizeof(NodeRec)), o_ar2 = ar.put(arec.data(), NA * sizeof(AppleRec)),
          o_hk = ar.put(hkey.data(), NS * 8), o_pa = ar.put(pack_apl.data(), pack_apl.size() * 4),
+         o_nt = ar.put(ntopo.data(), NS * 16),
          o_q = ar.put(&zero, 4 * 16);
   hipError_t he = hipMalloc(&M->arena, ar.off + 256);
   if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
@@ -557,6 +562,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   const int scr_nf = tun.adjoint_ckpt_max > 0 ? (int)N_FIELDS_ADJ : (int)N_FIELDS;
   const size_t scr_bytes = (size_t)scr_nf * (size_t)((std::max<int64_t>(NS, 1) + 63) / 64) * 64 * 4;
   he = hipMalloc(&M->scr, scr_bytes);
+  M->scr_bytes = scr_bytes;
   if (he != hipSuccess) { (void)hipFree(M->arena); delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc scratch: ") + hipGetErrorString(he)); }
   M->bytes = (int64_t)(ar.off + scr_bytes);
   char* base = (char*)M->arena;
@@ -573,6 +579,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.nrec = (const NodeRec*)(base + o_nr); dm.arec = (const AppleRec*)(base + o_ar2);
   dm.hkey = (const uint64_t*)(base + o_hk);
   dm.pack_apl = (const int32_t*)(base + o_pa);
+  dm.ntopo = (const int4*)(base + o_nt);
   dm.scr_nf = scr_nf;
   dm.lds_cap = n_lds_packs > 0 ? tun.lds_width : 0;
   // dynamic LDS of the step kernels: the level exchange, reused by the apple phase
@@ -603,13 +610,17 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   if (tun.adjoint_ckpt_max > 0) {
     const int64_t words = orchard_ckpt_words(M);
     M->adj_kmax = tun.adjoint_ckpt_max;
-    const size_t rb = (size_t)M->adj_kmax * (size_t)words * 4;
+    const size_t rb = (size_t)(M->adj_kmax + 1) * (size_t)words * 4;
+    // one scratch per step of a checkpoint interval: the backward sweep runs each step's
+    // forward once, keeping what the reverse pass reads back
+    const size_t pb = (size_t)(M->adj_kmax - 1) * M->scr_bytes;
     // work state: q, qd (float2), apple (13A), seg_evt (2S), apple_evt (4A), evt_step (S+A), status (B),
     // step; every piece starts on a 256-byte boundary
     auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t wb = 2 * r256(8 * (size_t)NS) + r256(52 * (size_t)NA) + r256(2 * (size_t)NS) + r256(4 * (size_t)NA) +
                       r256(4 * (size_t)(NS + NA)) + r256(4 * (size_t)B) + r256(8);
-    if (hipMalloc(&M->recs, rb) != hipSuccess || hipMalloc(&M->work, wb) != hipSuccess) {
+    if (hipMalloc(&M->recs, rb) != hipSuccess || hipMalloc(&M->work, wb) != hipSuccess ||
+        (pb > 0 && hipMalloc(&M->reps, pb) != hipSuccess)) {
       orchard_model_destroy(M);
       return fail(ORCHARD_ERR_OUT_OF_MEMORY, "adjoint buffers");
     }
@@ -618,7 +629,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     M->ws.q = (float2*)take(8 * NS); M->ws.qd = (float2*)take(8 * NS); M->ws.apple = (float*)take(52 * NA);
     M->ws.seg_evt = (uint8_t*)take(2 * NS); M->ws.apple_evt = (uint8_t*)take(4 * NA);
     M->ws.evt_step = (int32_t*)take(4 * (NS + NA)); M->ws.status = (uint32_t*)take(4 * B); M->ws.step = (int64_t*)take(8);
-    M->bytes += (int64_t)(rb + wb);
+    M->bytes += (int64_t)(rb + wb + pb);
   }
   *out = M;
   return ORCHARD_OK;
@@ -627,6 +638,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
 void orchard_model_destroy(orchard_model_t m) {
   if (!m) return;
   if (m->recs) (void)hipFree(m->recs);
+  if (m->reps) (void)hipFree(m->reps);
   if (m->work) (void)hipFree(m->work);
   if (m->arena) (void)hipFree(m->arena);
   if (m->scr) (void)hipFree(m->scr);
@@ -687,12 +699,13 @@ int64_t orchard_ckpt_words(orchard_model_t m) {
 }
 
 static orchard_status_t launch_steps(orchard_model_t m, const DevState& ds, const DevInputs& di, int k, int s_call,
-                                     hipStream_t stream, bool save = false) {
+                                     hipStream_t stream, bool save = false, float* scr = nullptr) {
   const int NT = m->tun.threads;
   const unsigned lb = (unsigned)m->lds_bytes;
   if (save) {
     DevModel dm = m->dm;
     dm.save_adj = 1;
+    if (scr) dm.scr = scr;
     const dim3 g(m->n_pack);
     switch (NT) {
       case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, stream, dm, ds, di, k, s_call); break;
@@ -837,26 +850,32 @@ orchard_status_t orchard_step_backward(orchard_model_t m, const float* ckpt, int
   const int NT = m->tun.threads;
   const int nseg = (n_steps + ckpt_every - 1) / ckpt_every;
   const DevState& W = m->ws;
+  auto rep = [&](int j) { return j == 0 ? m->scr : (float*)((char*)m->reps + (size_t)(j - 1) * m->scr_bytes); };
+  auto rec_at = [&](int j) { return (uint32_t*)m->recs + (int64_t)j * words; };
   for (int sg = nseg - 1; sg >= 0; --sg) {
     const int n0 = sg * ckpt_every, nk = std::min(ckpt_every, n_steps - n0);
+    // forward sweep: every step once, in save mode into its own scratch; records hold the
+    // state before each step and after the last
     hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (const uint32_t*)ckpt + (int64_t)sg * words);
-    hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (uint32_t*)m->recs);
-    for (int j = 0; j + 1 < nk; ++j) {
-      orchard_status_t st = launch_steps(m, W, di, 1, n0 + j, hs);
+    hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, rec_at(0));
+    for (int j = 0; j < nk; ++j) {
+      orchard_status_t st = launch_steps(m, W, di, 1, n0 + j, hs, true, rep(j));
       if (st) return st;
-      hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (uint32_t*)m->recs + (int64_t)(j + 1) * words);
+      hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, rec_at(j + 1));
     }
+    // reverse sweep: W holds the state after step j (event flags, step counter)
     for (int j = nk - 1; j >= 0; --j) {
-      const float* rec = m->recs + (int64_t)j * words;
-      hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (const uint32_t*)rec);
-      orchard_status_t st = launch_steps(m, W, di, 1, n0 + j, hs, true);
-      if (st) return st;
+      if (j < nk - 1)
+        hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (const uint32_t*)rec_at(j + 1));
+      DevModel dm = m->dm;
+      dm.scr = rep(j);
+      const float* rec = (const float*)rec_at(j);
       const dim3 g(m->n_pack);
       switch (NT) {
-        case 64: hipLaunchKernelGGL(k_adjoint_packs<64>, g, dim3(64), 0, hs, m->dm, W, rec, di, X, n0 + j); break;
-        case 128: hipLaunchKernelGGL(k_adjoint_packs<128>, g, dim3(128), 0, hs, m->dm, W, rec, di, X, n0 + j); break;
-        case 256: hipLaunchKernelGGL(k_adjoint_packs<256>, g, dim3(256), 0, hs, m->dm, W, rec, di, X, n0 + j); break;
-        default: hipLaunchKernelGGL(k_adjoint_packs<512>, g, dim3(512), 0, hs, m->dm, W, rec, di, X, n0 + j); break;
+        case 64: hipLaunchKernelGGL(k_adjoint_packs<64>, g, dim3(64), 0, hs, dm, W, rec, di, X, n0 + j); break;
+        case 128: hipLaunchKernelGGL(k_adjoint_packs<128>, g, dim3(128), 0, hs, dm, W, rec, di, X, n0 + j); break;
+        case 256: hipLaunchKernelGGL(k_adjoint_packs<256>, g, dim3(256), 0, hs, dm, W, rec, di, X, n0 + j); break;
+        default: hipLaunchKernelGGL(k_adjoint_packs<512>, g, dim3(512), 0, hs, dm, W, rec, di, X, n0 + j); break;
       }
       HIPCHK(hipGetLastError());
     }

@@ -8,8 +8,8 @@ namespace orchard {
 // ---- scratch fields: one float per node per field, field f at scr + f * n_seg -----------
 // A node's "publication" is what its neighbours on the next level read: children in the
 // down passes, the parent in the up pass.  Packs whose levels fit the workgroup keep
-// publications in LDS (double-buffered by level parity); wide packs and the adjoint's
-// recompute keep them in these global fields.
+// publications in LDS (double-buffered by level parity); wide packs keep them in these
+// global fields.
 enum : int {
   // down pass 1 publication (25), values at the node's tip point
   F_R = 0,          // 9: body rotation, row major
@@ -96,6 +96,7 @@ struct DevModel {
   const int32_t* pack_lds;   // 1: every level of the pack fits the workgroup (LDS publications)
   const int32_t* pack_apl;   // [n_pack+1] apples of pack p: pack_apl[p] .. pack_apl[p+1]-1
   const NodeRec* nrec;       // per node (internal order)
+  const int4* ntopo;         // per node: the topology word of its record (read by up and down 2)
   const AppleRec* arec;      // per apple (internal order)
   // per node (internal order)
   const int32_t* par;        // parent node, -1 = world
@@ -120,7 +121,7 @@ struct DevModel {
   float wsig;
   float* scr;                // blocks of 64 nodes, each [scr_nf][64] floats (see scr_idx)
   int32_t* queue;            // persistent-kernel pack counter(s)
-  int32_t save_adj;          // forward step also writes the F_S* fields (global exchange only)
+  int32_t save_adj;          // forward step also writes the fields the adjoint reads back
   int32_t scr_nf;            // fields per node: N_FIELDS, or N_FIELDS_ADJ with adjoint support
   int32_t lds_cap;           // LDS exchange capacity in nodes per level (0: global exchange)
   int32_t pad1;

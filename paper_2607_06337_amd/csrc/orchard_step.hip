@@ -12,8 +12,9 @@
 //
 // What a node hands to the next level (its "publication") goes through LDS when every
 // level of the pack fits the workgroup's exchange buffer, double-buffered by level
-// parity and indexed by the node's slot within its level; otherwise (very wide packs,
-// and the adjoint's recompute, which reads these values back) through global scratch.
+// parity and indexed by the node's slot within its level; otherwise (very wide packs)
+// through global scratch.  For the adjoint's recompute the step also stores the values
+// the reverse pass reads back.
 #include "orchard_dev.h"
 
 namespace orchard {
@@ -191,8 +192,14 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   xput3<XL>(L, F_R, F_AVA, i, Ava);
   xput3<XL>(L, F_R, F_AVL, i, Avl + cross(Ava, lz));
   xput<XL>(L, F_R, F_SNAP, i, snp ? 1.f : 0.f);
-  if (!XL && M.save_adj) {
+  if (M.save_adj) {
+    // the adjoint reads these from global scratch whichever way levels exchange
     float* P = L.P;
+    if constexpr (XL) {
+      pst3(P, nf, F_W, li, wi);
+      pst3(P, nf, F_VT, li, v + cross(wi, lz));
+      pst(P, nf, F_SNAP, li, snp ? 1.f : 0.f);
+    }
     pst(P, nf, F_SR + 0, li, c0.x); pst(P, nf, F_SR + 1, li, c1.x); pst(P, nf, F_SR + 2, li, c2.x);
     pst(P, nf, F_SR + 3, li, c0.y); pst(P, nf, F_SR + 4, li, c1.y); pst(P, nf, F_SR + 5, li, c2.y);
     pst(P, nf, F_SR + 6, li, c0.z); pst(P, nf, F_SR + 7, li, c1.z); pst(P, nf, F_SR + 8, li, c2.z);
@@ -440,7 +447,7 @@ __device__ __forceinline__ InU loadU(const DevModel& M, const Lvl& L, int i) {
   const int nf = M.scr_nf, li = i - L.i0;
   const float* P = L.P;
   InU u;
-  u.topo = at(M.nrec, (uint32_t)i).topo;
+  u.topo = at(M.ntopo, (uint32_t)i);
   u.r = pld3(P, nf, F_LZ, li);
   u.mo = pld(P, nf, F_MO, li);
   u.ho = pld3(P, nf, F_HO, li);
@@ -507,7 +514,7 @@ __device__ __forceinline__ void node_up(const DevModel& M, const Lvl& L, int i, 
   Mm.xx += mo; Mm.yy += mo; Mm.zz += mo;
   pn = pn + pon;
   pf = pf + pof;
-  if (!XL && M.save_adj) {
+  if (M.save_adj) {
     float* Pw = L.P;
     pst(Pw, nf, F_SIA + 0, li, A.xx); pst(Pw, nf, F_SIA + 1, li, A.yy); pst(Pw, nf, F_SIA + 2, li, A.zz);
     pst(Pw, nf, F_SIA + 3, li, A.xy); pst(Pw, nf, F_SIA + 4, li, A.xz); pst(Pw, nf, F_SIA + 5, li, A.yz);
@@ -569,7 +576,7 @@ __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const
   const int nf = M.scr_nf, li = i - L.i0;
   const float* P = L.P;
   In2 d;
-  d.topo = at(M.nrec, (uint32_t)i).topo;
+  d.topo = at(M.ntopo, (uint32_t)i);
   d.skip = pld(P, nf, F_SKIP, li);
   d.ca = pld3(P, nf, F_C, li);
   d.cl = pld3(P, nf, F_C + 3, li);
@@ -612,7 +619,7 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
   const float qdd0 = fmaf(Di00, t0, Di01 * t1);
   const float qdd1 = fmaf(Di01, t0, Di11 * t1);
   Aa = fma3(qdd0, a0, fma3(qdd1, a1, Aa));
-  if (!XL && M.save_adj) {
+  if (M.save_adj) {
     float* Pw = L.P;
     pst3(Pw, nf, F_SA, li, Aa); pst3(Pw, nf, F_SA + 3, li, Al);
     pst(Pw, nf, F_SQDD, li, qdd0); pst(Pw, nf, F_SQDD + 1, li, qdd1);
@@ -767,7 +774,7 @@ __device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, c
 template <int NT>
 __device__ __forceinline__ void run_pack_any(const DevModel& M, const DevState& S, const DevInputs& I, float* X,
                                              float* Abuf, int pk, int64_t n0, int n_inner, int call_step0) {
-  if (M.lds_cap > 0 && !M.save_adj && M.pack_lds[pk]) run_pack<NT, true>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
+  if (M.lds_cap > 0 && M.pack_lds[pk]) run_pack<NT, true>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
   else run_pack<NT, false>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
 }
 
