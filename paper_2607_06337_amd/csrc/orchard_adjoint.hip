@@ -39,20 +39,23 @@ struct RecView {
 };
 
 // ---- lambda solve, up pass: forward substitution with the stored factor ------------------
+// Frozen envs: the loads are issued unconditionally (so they overlap) and only the writes
+// that change the adjoint state or the gradients are skipped; scratch of a frozen env is
+// read only by nodes of the same env.
 __device__ void node_lam_up(const DevModel& M, const DevAdj& X, int i) {
-  if (aldf(M, F_SKIP, i) != 0.f) return;
-  V3 pn = v3(0, 0, 0), pf = v3(0, 0, 0);
-  const int cb = M.child[i], ce = cb + M.nchild[i];
-  for (int c = cb; c < ce; ++c) { pn = pn + ald3(M, F_LPA, c); pf = pf + ald3(M, F_LPA + 3, c); }
+  const int4 topo = at(M.ntopo, (uint32_t)i);
   const V3 lz = ald3(M, F_LZ, i);
-  pn = pn + cross(lz, pf);
-  const float h = M.h;
   const float2 qb = X.q[i], qdb = X.qd[i];
-  const float b0 = h * fmaf(h, qb.x, qdb.x), b1 = h * fmaf(h, qb.y, qdb.y);  // qdd_bar
   const V3 a0 = ald3(M, F_A0, i), a1 = ald3(M, F_A1, i);
-  const float u0 = b0 - dot(a0, pn), u1 = b1 - dot(a1, pn);
   const V3 U0a = ald3(M, F_U, i), U0l = ald3(M, F_U + 3, i), U1a = ald3(M, F_U + 6, i), U1l = ald3(M, F_U + 9, i);
   const float Di00 = aldf(M, F_DI, i), Di01 = aldf(M, F_DI + 1, i), Di11 = aldf(M, F_DI + 2, i);
+  V3 pn = v3(0, 0, 0), pf = v3(0, 0, 0);
+  const int cb = topo.y, ce = cb + (topo.z & 0xFFFF);
+  for (int c = cb; c < ce; ++c) { pn = pn + ald3(M, F_LPA, c); pf = pf + ald3(M, F_LPA + 3, c); }
+  pn = pn + cross(lz, pf);
+  const float h = M.h;
+  const float b0 = h * fmaf(h, qb.x, qdb.x), b1 = h * fmaf(h, qb.y, qdb.y);  // qdd_bar
+  const float u0 = b0 - dot(a0, pn), u1 = b1 - dot(a1, pn);
   const float w0 = fmaf(Di00, u0, Di01 * u1), w1 = fmaf(Di01, u0, Di11 * u1);
   pn = fma3(w0, U0a, fma3(w1, U1a, pn));
   pf = fma3(w0, U0l, fma3(w1, U1l, pf));
@@ -62,28 +65,29 @@ __device__ void node_lam_up(const DevModel& M, const DevAdj& X, int i) {
 
 // ---- lambda solve, down pass: back substitution; the field is the virtual velocity nu --
 __device__ void node_lam_down(const DevModel& M, int i) {
-  if (aldf(M, F_SKIP, i) != 0.f) return;
-  const int par = M.par[i];
+  const int par = at(M.ntopo, (uint32_t)i).x;
+  const V3 U0a = ald3(M, F_U, i), U0l = ald3(M, F_U + 3, i), U1a = ald3(M, F_U + 6, i), U1l = ald3(M, F_U + 9, i);
+  const float lu0 = aldf(M, F_LU, i), lu1 = aldf(M, F_LU + 1, i);
+  const float Di00 = aldf(M, F_DI, i), Di01 = aldf(M, F_DI + 1, i), Di11 = aldf(M, F_DI + 2, i);
+  const V3 a0 = ald3(M, F_A0, i), a1 = ald3(M, F_A1, i), lz = ald3(M, F_LZ, i);
   V3 aa = v3(0, 0, 0), al = v3(0, 0, 0);
   if (par >= 0) { aa = ald3(M, F_LA, par); al = ald3(M, F_LA + 3, par); }
-  const V3 U0a = ald3(M, F_U, i), U0l = ald3(M, F_U + 3, i), U1a = ald3(M, F_U + 6, i), U1l = ald3(M, F_U + 9, i);
-  const float t0 = aldf(M, F_LU, i) - (dot(U0a, aa) + dot(U0l, al));
-  const float t1 = aldf(M, F_LU + 1, i) - (dot(U1a, aa) + dot(U1l, al));
-  const float Di00 = aldf(M, F_DI, i), Di01 = aldf(M, F_DI + 1, i), Di11 = aldf(M, F_DI + 2, i);
+  const float t0 = lu0 - (dot(U0a, aa) + dot(U0l, al));
+  const float t1 = lu1 - (dot(U1a, aa) + dot(U1l, al));
   const float l0 = fmaf(Di00, t0, Di01 * t1), l1 = fmaf(Di01, t0, Di11 * t1);
-  aa = fma3(l0, ald3(M, F_A0, i), fma3(l1, ald3(M, F_A1, i), aa));
+  aa = fma3(l0, a0, fma3(l1, a1, aa));
   asto3(M, F_NU, i, aa); asto3(M, F_NU + 3, i, al);
   asto(M, F_LAM, i, l0); asto(M, F_LAM + 1, i, l1);
-  const V3 lz = ald3(M, F_LZ, i);
   asto3(M, F_LA, i, aa); asto3(M, F_LA + 3, i, al + cross(aa, lz));
 }
 
 // ---- reverse pass (leaf -> root) ---------------------------------------------------------
 __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView& R0, const DevInputs& I,
                              const DevAdj& X, int i, int64_t n, int s_call) {
-  if (aldf(M, F_SKIP, i) != 0.f) return;  // frozen env: the step is the identity
+  const int4 topo = at(M.ntopo, (uint32_t)i);
+  const bool skip = aldf(M, F_SKIP, i) != 0.f;  // frozen env: the step is the identity
   const float h = M.h;
-  const int par = M.par[i];
+  const int par = topo.x;
   // forward quantities of this node
   V3 c0, c1, c2;
   c0 = v3(aldf(M, F_SR + 0, i), aldf(M, F_SR + 3, i), aldf(M, F_SR + 6, i));
@@ -125,7 +129,7 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   float qdb0 = 0.f, qdb1 = 0.f;
   // ---- gather the children ----
   V3 vtb = v3(0, 0, 0), Atba = v3(0, 0, 0), Atbl = v3(0, 0, 0), Avtba = v3(0, 0, 0), Avtbl = v3(0, 0, 0), Fch = v3(0, 0, 0);
-  const int cb = M.child[i], ce = cb + M.nchild[i];
+  const int cb = topo.y, ce = cb + (topo.z & 0xFFFF);
   for (int c = cb; c < ce; ++c) {
     tau = tau + ald3(M, F_RB + 0, c);
     omb = omb + ald3(M, F_RB + 3, c);
@@ -242,9 +246,11 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
     omb = omb + cross(d, vhb);
     db = db + cross(vhb, om);
     tau = tau + cross(d, db);
-    X.ax[a] = sigb.x; X.ax[NA + a] = sigb.y; X.ax[2 * NA + a] = sigb.z;
-    X.av[a] = vab.x; X.av[NA + a] = vab.y; X.av[2 * NA + a] = vab.z;
-    if (gF) { gF[3 * a] += Fb.x; gF[3 * a + 1] += Fb.y; gF[3 * a + 2] += Fb.z; }
+    if (!skip) {
+      X.ax[a] = sigb.x; X.ax[NA + a] = sigb.y; X.ax[2 * NA + a] = sigb.z;
+      X.av[a] = vab.x; X.av[NA + a] = vab.y; X.av[2 * NA + a] = vab.z;
+      if (gF) { gF[3 * a] += Fb.x; gF[3 * a + 1] += Fb.y; gF[3 * a + 2] += Fb.z; }
+    }
   }
 
   // ---- c, A, Avp, omega, v recursions ----
@@ -275,7 +281,7 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
 
   // ---- springs, dampers, implicit diagonal; parameter gradients ----
   const float h2 = h * h;
-  if (!brk) {
+  if (!brk && !skip) {
     X.gkp[i] -= l0 * (h2 * qdd0 + q.x + h * qd.x) + l1 * (h2 * qdd1 + q.y + h * qd.y);
     X.gkd[i] -= l0 * (h * qdd0 + qd.x) + l1 * (h * qdd1 + qd.y);
   }
@@ -287,8 +293,10 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   // ---- state adjoint before the step ----
   const float2 qbn = X.q[i], qdbn = X.qd[i];
   const float qdp0 = fmaf(h, qbn.x, qdbn.x), qdp1 = fmaf(h, qbn.y, qdbn.y);
-  X.q[i] = make_float2(qbn.x - qb0, qbn.y - qb1);
-  X.qd[i] = make_float2(qdp0 - qdb0, qdp1 - qdb1);
+  if (!skip) {
+    X.q[i] = make_float2(qbn.x - qb0, qbn.y - qb1);
+    X.qd[i] = make_float2(qdp0 - qdb0, qdp1 - qdb1);
+  }
 
   // ---- publish for the parent ----
   asto3(M, F_RB + 0, i, tau_par);
