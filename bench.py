@@ -27,8 +27,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# kernel mapping used by the benchmark (and by the full-size parity test)
+# kernel mapping used by the full-size parity test and the adjoint ratio, and the first of
+# the candidates the autotuner times for the benchmark
 BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=1, persistent=0, lds_width=240)
+AUTOTUNE_CANDIDATES = [BENCH_TUNING,
+                       dict(threads=256, pack_fill=1.0, lds_width=256), dict(threads=256, pack_fill=1.0, lds_width=224),
+                       dict(threads=256, pack_fill=1.0, lds_width=192), dict(threads=128, pack_fill=1.0, lds_width=128),
+                       dict(threads=256, pack_fill=1.0, lds_width=0), dict(threads=128, pack_fill=1.0, lds_width=0)]
+GRAPH_STEPS = 100  # steps per captured HIP graph in the timed rollout
 # the plain per-step kernel: one 256-thread workgroup per tree, one launch per step,
 # levels exchange through global scratch
 PLAIN_TUNING = dict(threads=256, pack_fill=0.0, steps_per_launch=1, persistent=0, lds_width=0)
@@ -51,41 +57,50 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kernel: str):
+def profiled_traffic(kernel: str, tuning: dict):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel,
-    or None if there is none for the current kernel source."""
+    or None if there is none for the current kernel source and mapping."""
     cur = kernel_source_hash()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(f):
             if line.startswith("machine-readable: "):
                 rec = json.loads(line[len("machine-readable: "):])
-                if rec.get("kernel") == kernel and rec.get("src_hash") == cur:
+                if rec.get("kernel") == kernel and rec.get("src_hash") == cur and rec.get("tuning") == tuning:
                     return rec["hbm_bytes_per_launch"]
     return None
 
 
-def time_gpu(model, n_steps, warmup, reps=1):
+def time_gpu(model, n_steps, warmup, graph_steps=0):
+    """Time n_steps after warmup eager steps.  With graph_steps > 0 the rollout is a HIP
+    graph of graph_steps steps replayed (capture and one replay happen before the timed
+    region; a remainder runs eagerly inside it)."""
     import torch
     st = model.rest_state()
     kp, kd = model.default_params()
     model.step(st, kp, kd, warmup)
+    g = None
+    if graph_steps > 0 and n_steps >= graph_steps:
+        g = model.graph(st, kp, kd, graph_steps)
+        g.launch()  # the first replay is not timed
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    best = None
-    for _ in range(reps):
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev0.record(stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    if g is not None:
+        for _ in range(n_steps // graph_steps):
+            g.launch(stream)
+        if n_steps % graph_steps:
+            model.step(st, kp, kd, n_steps % graph_steps)
+    else:
         model.step(st, kp, kd, n_steps)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = ev0.elapsed_time(ev1)
-        best = (ms, wall) if best is None or ms < best[0] else best
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
     status = model.status(st)
-    return best[0], best[1], int((status != 0).sum()), st
+    return ms, wall, int((status != 0).sum()), st
 
 
 def cpu_baseline(batch, consts, n_envs=64, n_steps=1500):
@@ -149,6 +164,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="kernel mapping as JSON (skips the autotuner), e.g. the one a profile was taken with")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB read + 256 MiB write kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -166,10 +183,18 @@ def main():
           file=sys.stderr, flush=True)
 
     import torch
-    from paper_2607_06337_amd import Model
+    from paper_2607_06337_amd import DEFAULT_TUNING, Model, autotune
     torch.cuda.init()
-    model = Model(batch, consts, BENCH_TUNING)
-    ms, wall, n_bad, _ = time_gpu(model, args.steps, args.warmup)
+    if args.tuning:
+        tuning, tune_log = dict(DEFAULT_TUNING, **json.loads(args.tuning)), None
+    else:
+        t_tune = time.perf_counter()
+        tuning, timings = autotune(batch, consts, AUTOTUNE_CANDIDATES, n_warm=3, n_steps=20)
+        tune_log = [dict(c, ms_per_step=round(ms, 4)) for c, ms in timings]
+        print(f"# autotune {time.perf_counter() - t_tune:.1f} s: {tuning}", file=sys.stderr, flush=True)
+    tuning = {k: tuning[k] for k in ("threads", "pack_fill", "steps_per_launch", "persistent", "lds_width", "pack_skew")}
+    model = Model(batch, consts, tuning)
+    ms, wall, n_bad, _ = time_gpu(model, args.steps, args.warmup, GRAPH_STEPS)
     print(f"# optimized: {args.steps} steps in {ms:.1f} ms ({wall:.2f} s wall), packs={model.n_pack}", file=sys.stderr,
           flush=True)
     plain = None
@@ -189,11 +214,11 @@ def main():
         del x, y
     ms_step = ms / args.steps
     value = batch.n_env * args.steps / (ms / 1e3)
-    spl = BENCH_TUNING["steps_per_launch"]
+    spl = tuning["steps_per_launch"]
     per_launch_bytes = algorithmic_bytes(batch) * spl
     launch_ms = ms_step * spl
     achieved = per_launch_bytes / (launch_ms / 1e3) / 1e9
-    traffic = profiled_traffic("k_step_packs")
+    traffic = profiled_traffic("k_step_packs", tuning)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel="k_step_packs", bytes_per_launch=per_launch_bytes,
@@ -212,7 +237,8 @@ def main():
                dtype="f32", data="synthetic",
                config=dict(workload=f"{WORKLOAD}: 8192 seeded L-system trees, log-uniform 50-1500 segments, "
                                     f"10-120 apples, in-step random body forces 5% N(0,5N), dt 1 ms",
-                           n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=BENCH_TUNING),
+                           n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=tuning,
+                           rollout=f"HIP graph of {GRAPH_STEPS} steps, replayed", autotune=tune_log),
                adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
                roofline=roof, cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
