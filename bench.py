@@ -156,6 +156,48 @@ def adjoint_ratio(reps: int = 3):
                 workload="grad512: 512 trees x 300 segments x 40 apples, 200 steps, checkpoints every 20")
 
 
+def row_scale(fwd_steps: int = 200, warm: int = 10, lead: int = 900, tail: int = 100, K: int = 20):
+    """Orchard-row batch (64 trees of 5000 segments + 16384 of 80) in one launch: forward
+    throughput, then the 64 large trees alone: forward to step lead + tail with checkpoints
+    over the final tail steps, and the adjoint over those steps (recompute included).
+    Algorithmic-byte rates use the same per-segment / per-apple bytes as the main figure."""
+    import torch
+    from orchard_inputs import make_batch, step_constants
+    from paper_2607_06337_amd import Model
+    batch = make_batch("row64x16k")
+    consts = step_constants()
+    m = Model(batch, consts, BENCH_TUNING)
+    ms, _, n_bad, _ = time_gpu(m, fwd_steps, warm, GRAPH_STEPS)
+    fwd = dict(ms_per_step=round(ms / fwd_steps, 4), env_steps_per_s=round(batch.n_env * fwd_steps / (ms / 1e3), 1),
+               alg_GBps=round(algorithmic_bytes(batch) * fwd_steps / (ms / 1e3) / 1e9, 1), nonfinite_envs=n_bad)
+    del m
+    large = make_batch("row64x16k", env_ids=range(64))
+    ml = Model(large, consts, dict(BENCH_TUNING, adjoint_ckpt_max=K))
+    st = ml.rest_state()
+    kp, kd = ml.default_params()
+    ml.step(st, kp, kd, lead)
+    ck = torch.empty(-(-tail // K) * ml.ckpt_words, device="cuda")
+    adj = dict(q=torch.randn(ml.n_seg, 2, device="cuda"), qd=torch.zeros(ml.n_seg, 2, device="cuda"),
+               ax=torch.zeros(3, ml.n_apple, device="cuda"), av=torch.zeros(3, ml.n_apple, device="cuda"))
+    gkp, gkd = torch.zeros_like(kp), torch.zeros_like(kd)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    e0.record()
+    ml.step(st, kp, kd, tail, ckpt=ck, ckpt_every=K)
+    e1.record()
+    ml.step_backward(ck, K, tail, kp, kd, adj, gkp, gkd)
+    e2.record()
+    torch.cuda.synchronize()
+    fw, bw = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    lb = algorithmic_bytes(large) * tail
+    return dict(workload="row64x16k: 64 trees x 5000 segments x 400 apples + 16384 trees x 80 segments x 8 apples, "
+                         "one launch, gravity and breakage",
+                forward=fwd,
+                adjoint_large=dict(steps=f"{lead}..{lead + tail}", forward_ms=round(fw, 2), backward_ms=round(bw, 2),
+                                   ratio=round(bw / fw, 3), forward_alg_GBps=round(lb / (fw / 1e3) / 1e9, 1),
+                                   backward_alg_GBps=round(lb / (bw / 1e3) / 1e9, 1)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +206,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-row-scale", action="store_true")
     ap.add_argument("--tuning", type=str, default=None,
                     help="kernel mapping as JSON (skips the autotuner), e.g. the one a profile was taken with")
     ap.add_argument("--copy-probe", action="store_true",
@@ -227,6 +270,10 @@ def main():
     if not args.no_adjoint:
         adj = adjoint_ratio()
         print(f"# adjoint/forward: {adj}", file=sys.stderr, flush=True)
+    rows = None
+    if not args.no_row_scale:
+        rows = row_scale()
+        print(f"# row scale: {rows}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, consts)
@@ -240,7 +287,7 @@ def main():
                            n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=tuning,
                            rollout=f"HIP graph of {GRAPH_STEPS} steps, replayed", autotune=tune_log),
                adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
-               roofline=roof, cpu_baseline=cpu)
+               roofline=roof, cpu_baseline=cpu, row_scale=rows)
     print(json.dumps(out), flush=True)
 
 

@@ -33,7 +33,7 @@ def _rest_tips(batch):
     return tips
 
 
-def _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=K, tuning=None):
+def _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=K, tuning=None, T=T):
     from paper_2607_06337_amd import Model, rollout, tips
     tun = dict(threads=128, pack_fill=1.0, adjoint_ckpt_max=ckpt_every)
     tun.update(tuning or {})
@@ -148,3 +148,29 @@ def test_checkpoint_interval_does_not_change_gradients():
     b = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=7)
     for x, y in zip(a[1:4], b[1:4]):
         assert np.array_equal(x, y)
+
+
+def test_large_tree_adjoint_matches_fp64_central_differences():
+    # a 5000-segment tree of the orchard-row batch (wide levels: global exchange), 60 steps
+    # with checkpoints every 20, directional derivatives against FP64 central differences
+    from orchard_inputs import make_trees
+    Tl = 60
+    batch = assemble(make_trees("row64x16k", env_ids=[5]))
+    consts = step_constants()
+    rng = np.random.default_rng(21)
+    F = rng.normal(0, 2, (Tl, batch.n_apple, 3))
+    tip_idx, target = grad_targets(batch, _rest_tips(batch))
+    L, gkp, gkd, gF, kpd, kdd = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=20, T=Tl)
+    o = Oracle(batch, consts)
+    x0 = env_state0(o, o.rest_state(), 0)
+    rec = Record()
+    Lo = loss(o, 0, x0, kpd, kdd, F, Tl, tip_idx[0], target[0], record_out=rec)
+    assert abs(L - Lo) <= 1e-4 * abs(Lo), (L, Lo)
+    f = lambda kp_, kd_, F_: loss(o, 0, x0, kp_, kd_, F_, Tl, tip_idx[0], target[0], record_in=rec)
+    for _ in range(3):
+        dkp, dkd, dF = rng.normal(size=kpd.size) * kpd, rng.normal(size=kdd.size) * kdd, rng.normal(size=F.shape)
+        ep = 1e-5
+        fd = (f(kpd + ep * dkp, kdd + ep * dkd, F + ep * dF) - f(kpd - ep * dkp, kdd - ep * dkd, F - ep * dF)) / (2 * ep)
+        an = gkp @ dkp + gkd @ dkd + np.sum(gF * dF)
+        print(f"large tree: fd {fd:.6e} adjoint {an:.6e}", flush=True)
+        assert abs(fd - an) <= TOL * max(abs(an), 1e-12), (fd, an)

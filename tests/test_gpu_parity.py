@@ -61,13 +61,16 @@ def test_uneven_workload_full_batch_random_wrenches():
     assert not bad
 
 
-def test_large_trees_and_small_trees_one_launch():
-    # 5000-segment trees next to 80-segment ones (ragged packs, wide levels)
-    from orchard_inputs import make_trees
-    trees = make_trees("row64x16k", env_ids=[0, 1, 64, 65, 66, 67])
-    b = assemble(trees)
-    errs, bad, n_band, *_ = run_parity(b, step_constants(), 100, 25)
-    wq, wqd = _report("row-mix", errs, bad, n_band)
+def test_row_scale_batch_one_launch():
+    # the orchard-row batch in one launch: 64 trees of 5000 segments next to 16384 of 80
+    # (wide levels that take the global exchange next to LDS packs); the oracle follows
+    # 4 large and 28 small trees over 300 steps with breakage enabled
+    from bench import BENCH_TUNING
+    b = make_batch("row64x16k")
+    rng = np.random.default_rng(11)
+    envs = [0, 21, 42, 63] + sorted(int(e) for e in rng.choice(np.arange(64, b.n_env), 28, replace=False))
+    errs, bad, n_band, *_ = run_parity(b, step_constants(), 300, 50, envs=envs, tuning=BENCH_TUNING, threads=8)
+    wq, wqd = _report("row-scale", errs, bad, n_band)
     assert wq < TOL and wqd < TOL
     assert not bad
 
