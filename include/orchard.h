@@ -90,7 +90,7 @@ typedef struct {
  * pack collects trees of similar depth until it holds about pack_fill * threads *
  * depth nodes (0 = one tree per pack).  lds_width (0 .. threads): capacity, in nodes
  * per level, of the LDS buffer through which neighbouring levels of a pack exchange
- * their data (2 x 27 x lds_width floats of LDS per workgroup); packs are then also
+ * their data (2 x 28 x lds_width floats of LDS per workgroup); packs are then also
  * closed before a level would exceed it, and a tree wider than it exchanges through
  * global scratch.  0 = global scratch for every pack.  pack_skew (LDS exchange only):
  * 1 = place trees at level offsets inside a strip of pack_fill x (deepest tree) levels

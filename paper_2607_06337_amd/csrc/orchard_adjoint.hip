@@ -44,10 +44,10 @@ struct RecView {
 // read only by nodes of the same env.
 __device__ void node_lam_up(const DevModel& M, const DevAdj& X, int i) {
   const int4 topo = at(M.ntopo, (uint32_t)i);
-  const V3 lz = ald3(M, F_LZ, i);
+  const V3 lz = M.geo[i].x * ald3(M, F_Z, i);
   const float2 qb = X.q[i], qdb = X.qd[i];
   const V3 a0 = ald3(M, F_A0, i), a1 = ald3(M, F_A1, i);
-  const V3 U0a = ald3(M, F_U, i), U0l = ald3(M, F_U + 3, i), U1a = ald3(M, F_U + 6, i), U1l = ald3(M, F_U + 9, i);
+  const V3 W0a = ald3(M, F_WM, i), W0l = ald3(M, F_WM + 3, i), W1a = ald3(M, F_WM + 6, i), W1l = ald3(M, F_WM + 9, i);
   const float Di00 = aldf(M, F_DI, i), Di01 = aldf(M, F_DI + 1, i), Di11 = aldf(M, F_DI + 2, i);
   V3 pn = v3(0, 0, 0), pf = v3(0, 0, 0);
   const int cb = topo.y, ce = cb + (topo.z & 0xFFFF);
@@ -56,25 +56,23 @@ __device__ void node_lam_up(const DevModel& M, const DevAdj& X, int i) {
   const float h = M.h;
   const float b0 = h * fmaf(h, qb.x, qdb.x), b1 = h * fmaf(h, qb.y, qdb.y);  // qdd_bar
   const float u0 = b0 - dot(a0, pn), u1 = b1 - dot(a1, pn);
-  const float w0 = fmaf(Di00, u0, Di01 * u1), w1 = fmaf(Di01, u0, Di11 * u1);
-  pn = fma3(w0, U0a, fma3(w1, U1a, pn));
-  pf = fma3(w0, U0l, fma3(w1, U1l, pf));
-  asto(M, F_LU, i, u0); asto(M, F_LU + 1, i, u1);
+  // U D^-1 u = W u; the down pass needs D^-1 u
+  pn = fma3(u0, W0a, fma3(u1, W1a, pn));
+  pf = fma3(u0, W0l, fma3(u1, W1l, pf));
+  asto(M, F_LU, i, fmaf(Di00, u0, Di01 * u1)); asto(M, F_LU + 1, i, fmaf(Di01, u0, Di11 * u1));
   asto3(M, F_LPA, i, pn); asto3(M, F_LPA + 3, i, pf);
 }
 
 // ---- lambda solve, down pass: back substitution; the field is the virtual velocity nu --
 __device__ void node_lam_down(const DevModel& M, int i) {
   const int par = at(M.ntopo, (uint32_t)i).x;
-  const V3 U0a = ald3(M, F_U, i), U0l = ald3(M, F_U + 3, i), U1a = ald3(M, F_U + 6, i), U1l = ald3(M, F_U + 9, i);
-  const float lu0 = aldf(M, F_LU, i), lu1 = aldf(M, F_LU + 1, i);
-  const float Di00 = aldf(M, F_DI, i), Di01 = aldf(M, F_DI + 1, i), Di11 = aldf(M, F_DI + 2, i);
-  const V3 a0 = ald3(M, F_A0, i), a1 = ald3(M, F_A1, i), lz = ald3(M, F_LZ, i);
+  const V3 W0a = ald3(M, F_WM, i), W0l = ald3(M, F_WM + 3, i), W1a = ald3(M, F_WM + 6, i), W1l = ald3(M, F_WM + 9, i);
+  const float du0 = aldf(M, F_LU, i), du1 = aldf(M, F_LU + 1, i);
+  const V3 a0 = ald3(M, F_A0, i), a1 = ald3(M, F_A1, i), lz = M.geo[i].x * ald3(M, F_Z, i);
   V3 aa = v3(0, 0, 0), al = v3(0, 0, 0);
   if (par >= 0) { aa = ald3(M, F_LA, par); al = ald3(M, F_LA + 3, par); }
-  const float t0 = lu0 - (dot(U0a, aa) + dot(U0l, al));
-  const float t1 = lu1 - (dot(U1a, aa) + dot(U1l, al));
-  const float l0 = fmaf(Di00, t0, Di01 * t1), l1 = fmaf(Di01, t0, Di11 * t1);
+  const float l0 = du0 - (dot(W0a, aa) + dot(W0l, al));
+  const float l1 = du1 - (dot(W1a, aa) + dot(W1l, al));
   aa = fma3(l0, a0, fma3(l1, a1, aa));
   asto3(M, F_NU, i, aa); asto3(M, F_NU + 3, i, al);
   asto(M, F_LAM, i, l0); asto(M, F_LAM + 1, i, l1);
@@ -85,7 +83,7 @@ __device__ void node_lam_down(const DevModel& M, int i) {
 __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView& R0, const DevInputs& I,
                              const DevAdj& X, int i, int64_t n, int s_call) {
   const int4 topo = at(M.ntopo, (uint32_t)i);
-  const bool skip = aldf(M, F_SKIP, i) != 0.f;  // frozen env: the step is the identity
+  const bool skip = (((int)aldf(M, F_FLG, i)) & 1) != 0;  // frozen env: the step is the identity
   const float h = M.h;
   const int par = topo.x;
   // forward quantities of this node
@@ -94,7 +92,8 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   c1 = v3(aldf(M, F_SR + 1, i), aldf(M, F_SR + 4, i), aldf(M, F_SR + 7, i));
   c2 = v3(aldf(M, F_SR + 2, i), aldf(M, F_SR + 5, i), aldf(M, F_SR + 8, i));
   const V3 a0 = ald3(M, F_A0, i), a1 = c1, z = c2;
-  const V3 lz = ald3(M, F_LZ, i);
+  const float4 g4 = M.geo[i];
+  const V3 lz = g4.x * z;
   const V3 om = ald3(M, F_W, i);
   const V3 v = par >= 0 ? ald3(M, F_VT, par) : v3(0, 0, 0);
   const V3 Aa = ald3(M, F_SA, i), Al = ald3(M, F_SA + 3, i);
@@ -113,7 +112,6 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   const V3 ff = mulT(IB, Aa) + mul(IM, Al) + ald3(M, F_SPA + 3, i);
   const float2 q = R0.q(i), qd = R0.qd(i);
   const V3 u = fma3(qd.x, a0, qd.y * a1);
-  const float4 g4 = M.geo[i];
   const float l = g4.x, m = g4.y, Jt = g4.z, Iax = g4.w, dJ = Iax - Jt;
   const V3 ho = (0.5f * m * l) * z;
   const Sym3 Jo{fmaf(dJ, z.x * z.x, Jt), fmaf(dJ, z.y * z.y, Jt), fmaf(dJ, z.z * z.z, Jt), dJ * z.x * z.y, dJ * z.x * z.z,
@@ -179,7 +177,7 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   // applied force: moment arm (l/2) z
   {
     V3 F, T;
-    const bool snp = aldf(M, F_SNAP, i) != 0.f;
+    const bool snp = (((int)aldf(M, F_SNAP, i)) & 1) != 0;
     if (applied_force(M, I, i, splitmix64((uint64_t)n), s_call, m, snp, M.hkey[i], F, T)) zb = zb - (0.5f * l) * cross(F, na);
   }
   zb = fma3(0.5f * m * l, hb, zb);
@@ -313,7 +311,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_adjoint_packs(DevModel M, DevState W, const float* rec, DevInputs I, DevAdj X,
                                                       int s_call) {
   const int pk = blockIdx.x;
-  const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
+  const int lb = ldc(M.pack_lvl, pk), le = ldc(M.pack_lvl, pk + 1) - 1;
   const int64_t n = *W.step - 1;  // the forward step just taken on W
   const RecView R0{rec, M.n_seg, M.n_apple};
   for (int lv = le - 1; lv >= lb; --lv) {
@@ -365,7 +363,7 @@ __device__ void node_tip_fk(const DevModel& M, const float2* qs, int i) {
 template <int NT>
 __global__ __launch_bounds__(NT) void k_tip_fk(DevModel M, const float2* q) {
   const int pk = blockIdx.x;
-  const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
+  const int lb = ldc(M.pack_lvl, pk), le = ldc(M.pack_lvl, pk + 1) - 1;
   for (int lv = lb; lv < le; ++lv) {
     const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
     for (int i = a + (int)threadIdx.x; i < b; i += NT) node_tip_fk(M, q, i);
@@ -418,7 +416,7 @@ __device__ void node_tip_bwd(const DevModel& M, float2* gq, int i) {
 template <int NT>
 __global__ __launch_bounds__(NT) void k_tip_bwd(DevModel M, float2* gq) {
   const int pk = blockIdx.x;
-  const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
+  const int lb = ldc(M.pack_lvl, pk), le = ldc(M.pack_lvl, pk + 1) - 1;
   for (int lv = le - 1; lv >= lb; --lv) {
     const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
     for (int i = a + (int)threadIdx.x; i < b; i += NT) node_tip_bwd(M, gq, i);

@@ -494,6 +494,10 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   std::vector<NodeRec> nrec(NS);
   std::vector<int4> ntopo(NS);
   std::vector<uint64_t> hkey(NS);
+  std::vector<int32_t> anode(NS, -1);  // apple-node index, in node order
+  int32_t n_anode = 0;
+  for (int64_t i = 0; i < NS; ++i)
+    if (apple_beg[i + 1] > apple_beg[i]) anode[i] = n_anode++;
   for (int64_t i = 0; i < NS; ++i) {
     const int napp = apple_beg[i + 1] - apple_beg[i];
     if (nchild_i[i] > 0xFFFF || napp > 0xFFFF)
@@ -505,8 +509,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     nrec[i].rq = rq[i];
     nrec[i].geo = geo[i];
     nrec[i].topo = make_int4(par_i[i], child_i[i], nchild_i[i] | (napp << 16), env_i[i]);
-    nrec[i].aux = make_int4((int32_t)(uint32_t)(hkey[i] & 0xFFFFFFFFull), (int32_t)(uint32_t)(hkey[i] >> 32), apple_beg[i], bits);
-    ntopo[i] = nrec[i].topo;
+    nrec[i].aux = make_int4((int32_t)(uint32_t)(hkey[i] & 0xFFFFFFFFull), (int32_t)(uint32_t)(hkey[i] >> 32), anode[i], bits);
+    ntopo[i] = make_int4(par_i[i], child_i[i], nchild_i[i] | (napp << 16), anode[i]);
   }
   std::vector<AppleRec> arec(NA);
   for (int64_t k = 0; k < NA; ++k) {
@@ -516,7 +520,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     arec[k].par = make_float4((float)(1.0 / fdet), apar_h[k].y, apar_h[k].z, (float)(1.0 / (d->tension_factor * fdet)));
     arec[k].rest = make_float4(ahrest_h[k].x, ahrest_h[k].y, ahrest_h[k].z, (float)(d->dt / ma));
     const int node = int_of[aseg_g[a]];
-    arec[k].link = make_int4(node, apple_env[k], 0, 0);
+    arec[k].link = make_int4(node, apple_env[k], (int)(k == apple_beg[node]), anode[node]);
   }
   std::vector<int32_t> pack_apl(pack_node.size());
   for (size_t p = 0; p + 1 < pack_node.size(); ++p) pack_apl[p] = apple_beg[pack_node[p]];
@@ -561,10 +565,12 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   }
   const int scr_nf = tun.adjoint_ckpt_max > 0 ? (int)N_FIELDS_ADJ : (int)N_FIELDS;
   const size_t scr_bytes = (size_t)scr_nf * (size_t)((std::max<int64_t>(NS, 1) + 63) / 64) * 64 * 4;
-  he = hipMalloc(&M->scr, scr_bytes);
+  // per-step scratch, then the dense data of the nodes that carry apples
+  const size_t an_bytes = (size_t)std::max<int32_t>(n_anode, 1) * (K_N + E_N) * 4;
+  he = hipMalloc(&M->scr, scr_bytes + an_bytes);
   M->scr_bytes = scr_bytes;
   if (he != hipSuccess) { (void)hipFree(M->arena); delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc scratch: ") + hipGetErrorString(he)); }
-  M->bytes = (int64_t)(ar.off + scr_bytes);
+  M->bytes = (int64_t)(ar.off + scr_bytes + an_bytes);
   char* base = (char*)M->arena;
   DevModel& dm = M->dm;
   dm.n_env = B; dm.n_seg = (int32_t)NS; dm.n_apple = (int32_t)NA; dm.n_pack = M->n_pack;
@@ -583,7 +589,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.scr_nf = scr_nf;
   dm.lds_cap = n_lds_packs > 0 ? tun.lds_width : 0;
   // dynamic LDS of the step kernels: the level exchange, reused by the apple phase
-  M->lds_bytes = std::max((size_t)dm.lds_cap * 2 * N_PUB_MAX, (size_t)11 * tun.threads) * 4;
+  M->lds_bytes = std::max((size_t)dm.lds_cap * 2 * X_STRIDE, (size_t)11 * tun.threads) * 4;
   M->kp0 = (float*)(base + o_kp); M->kd0 = (float*)(base + o_kd); M->apple_rest = (float*)(base + o_ar);
   dm.queue = (int32_t*)(base + o_q);
   dm.h = (float)d->dt;
@@ -595,6 +601,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.rng_thr = (uint32_t)std::floor(d->wrench_fraction * 16777216.0);
   dm.wsig = (float)d->wrench_sigma;
   dm.scr = M->scr;
+  dm.asnap = (float*)((char*)M->scr + scr_bytes);
+  dm.aext = dm.asnap + (size_t)std::max<int32_t>(n_anode, 1) * K_N;
   int dev = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&M->n_cu, hipDeviceAttributeMultiprocessorCount, dev);

@@ -18,41 +18,51 @@ enum : int {
   F_VT = 15,        // 3: linear velocity of the tip point
   F_AVA = 18,       // 3: velocity-product (+ base) acceleration at the tip, angular
   F_AVL = 21,       // 3:   linear
-  F_SNAP = 24,      // 1: snapped flag
+  F_SNAP = 24,      // 1: snapped flag + 2 x the env's frozen flag
   N_PUB1 = 25,
-  // node-private data kept from the down pass for the up pass
+  // node-private data kept from the down pass for the up and second down passes; the
+  // own-body inertia, l z and the spring terms are formed again from static data, z and
+  // the state instead of being stored
   F_A0 = 25,        // 3: joint axis x (world)
   F_A1 = 28,        // 3: joint axis y (world)
   F_C = 31,         // 6: velocity-product acceleration c (ang, lin)
-  F_P = 37,         // 6: bias force p (ang, lin) incl. applied forces
-  F_MO = 43,        // 1: own mass (+ virtual apple masses)
-  F_HO = 44,        // 3: own first moment about the joint point
-  F_JO = 47,        // 6: own rotational inertia about the joint (xx yy zz xy xz yz)
-  F_TAU = 53,       // 2: spring/damper torque
-  F_DG = 55,        // 1: implicit diagonal h kd + h^2 kp
-  F_LZ = 56,        // 3: l * z (joint point -> tip)
-  F_SKIP = 59,      // 1: env frozen at the start of this step
+  F_P = 37,         // 6: bias force p (ang, lin) incl. applied forces and apple reactions
+  F_Z = 43,         // 3: body axis z (world)
+  F_FLG = 46,       // 1: 1 if the env is frozen at the start of the step, + 2 if the joint is broken
   // up-pass publication (27): articulated inertia and bias at the node's joint point
   F_IA = 60,        // 6: A (rotational block, sym)
   F_IB = 66,        // 9: B (coupling block, row major)
   F_IM = 75,        // 6: M (linear block, sym)
   F_PA = 81,        // 6: bias (ang, lin)
   N_PUBU = 27,
-  // node-private factor data for the second down pass
-  F_U = 87,         // 12: U = I^A S (col 0: ang 3 lin 3, col 1: ang 3 lin 3)
-  F_DI = 99,        // 3: D^-1 (00 01 11)
-  F_UU = 102,       // 2: u = tau - S^T p^A
-  // kinematics of a node that carries apples, kept for the apple phase
-  F_KR = 104,       // 9: body rotation, row major
-  F_KW = 113,       // 3: angular velocity
-  F_KV = 116,       // 3: velocity of the joint point
-  F_KAA = 119,      // 3: velocity-product (+ base) acceleration at the joint point, angular
-  F_KAL = 122,      // 3:   linear
-  F_KPJ = 125,      // 3: joint point (absolute)
+  // node-private factor data for the second down pass: qdd = D^-1 u - W^T (A_parent + c)
+  F_WM = 87,        // 12: W = U D^-1, U = I^A S (col 0: ang 3 lin 3, col 1: ang 3 lin 3)
+  F_DU = 99,        // 2: D^-1 u, u = tau - S^T p^A
+  F_DI = 101,       // 3: D^-1 (00 01 11), stored only in save mode (the adjoint's solves)
+  // node-private outputs of the down 1 and up passes, each a contiguous range of fields
+  N_OUT1 = 22,      // F_A0 .. F_FLG
+  N_OUTU = 14,      // F_WM .. F_DU + 1
   N_FIELDS = 128,
+  // Nodes that carry apples (a minority) keep their apple data in two dense arrays
+  // indexed by the node's apple-node index, so it moves in whole sectors:
+  // the kinematics down 1 keeps for the apple phase, [n_anode][K_N] floats
+  K_R = 0,          // 9: body rotation, row major
+  K_W = 9,          // 3: angular velocity
+  K_V = 12,         // 3: velocity of the joint point
+  K_AA = 15,        // 3: velocity-product (+ base) acceleration at the joint point, angular
+  K_AL = 18,        // 3:   linear
+  K_PJ = 21,        // 3: joint point (absolute)
+  K_N = 24,
+  // the apples' sums the apple phase hands to the up pass, [n_anode][E_N] floats
+  E_MO = 0,         // 1: virtual mass
+  E_HO = 1,         // 3: its first moment about the joint point
+  E_JO = 4,         // 6: its rotational inertia about the joint (xx yy zz xy xz yz)
+  E_P = 10,         // 6: reaction bias (ang, lin)
+  E_N = 16,
   // second down pass publication (6) overwrites the first six fields
   F_AT = 0,         // 6: acceleration at the tip (ang, lin)
   N_PUB_MAX = 27,
+  X_STRIDE = 28,     // LDS exchange floats per node slot (N_PUB_MAX rounded to 16 B)
   // ---- fields of the adjoint ----
   // saved by the forward step in save mode
   F_SR = 128,       // 9: body rotation, row major
@@ -62,7 +72,7 @@ enum : int {
   F_SA = 170,       // 6: total acceleration at the joint point
   F_SQDD = 176,     // 2: joint accelerations
   // adjoint passes
-  F_LU = 178,       // 2: u of the solve M lambda = qdd_bar
+  F_LU = 178,       // 2: D^-1 u of the solve M lambda = qdd_bar
   F_LPA = 180,      // 6: bias of that solve passed to the parent
   F_LA = 186,       // 6: acceleration of that solve at the tip
   F_NU = 192,       // 6: virtual velocity nu at the joint point
@@ -77,13 +87,13 @@ struct NodeRec {
   float4 rq;    // rest quaternion (w, x, y, z)
   float4 geo;   // (l, m, Jt about the joint, Ia)
   int4 topo;    // (parent, first child, children | apples << 16, env)
-  int4 aux;     // (random-wrench key low, high 32 bits, first apple, 1 / M_max as float bits)
+  int4 aux;     // (random-wrench key low, high 32 bits, apple-node index or -1, 1 / M_max as float bits)
 };
 struct AppleRec {
   float4 hang;  // hang point in the segment frame, mass
   float4 par;   // (1 / f_det, c_s, F_max, 1 / (alpha f_det))
   float4 rest;  // rest hang point (origin of a detached apple's position), h / m
-  int4 link;    // (node, env, unused, unused)
+  int4 link;    // (node, env, 1 if the first apple of its node, the node's apple-node index)
 };
 
 struct DevModel {
@@ -96,7 +106,7 @@ struct DevModel {
   const int32_t* pack_lds;   // 1: every level of the pack fits the workgroup (LDS publications)
   const int32_t* pack_apl;   // [n_pack+1] apples of pack p: pack_apl[p] .. pack_apl[p+1]-1
   const NodeRec* nrec;       // per node (internal order)
-  const int4* ntopo;         // per node: the topology word of its record (read by up and down 2)
+  const int4* ntopo;         // per node: (parent, first child, children | apples << 16, apple-node index)
   const AppleRec* arec;      // per apple (internal order)
   // per node (internal order)
   const int32_t* par;        // parent node, -1 = world
@@ -120,6 +130,8 @@ struct DevModel {
   uint32_t rng_thr;
   float wsig;
   float* scr;                // blocks of 64 nodes, each [scr_nf][64] floats (see scr_idx)
+  float* asnap;              // [n_anode][K_N] kinematics of the nodes that carry apples
+  float* aext;               // [n_anode][E_N] apple sums per node that carries apples
   int32_t* queue;            // persistent-kernel pack counter(s)
   int32_t save_adj;          // forward step also writes the fields the adjoint reads back
   int32_t scr_nf;            // fields per node: N_FIELDS, or N_FIELDS_ADJ with adjoint support
@@ -132,6 +144,16 @@ struct DevModel {
 // DRAM rows and TLB entries shared across the fields a wavefront touches.
 __device__ __forceinline__ size_t scr_idx(const DevModel& M, int f, int i) {
   return ((size_t)(i >> 6) * (size_t)M.scr_nf + (size_t)f) * 64u + (size_t)(i & 63);
+}
+
+// Static per-pack tables that no kernel writes are read through the constant address
+// space, so a uniform index becomes a scalar load.
+#ifndef ORCHARD_CONST_AS
+#define ORCHARD_CONST_AS __attribute__((address_space(4)))
+#endif
+template <class T>
+__device__ __forceinline__ T ldc(const T* p, int64_t i) {
+  return ((const ORCHARD_CONST_AS T*)p)[i];
 }
 
 // element idx of p with the byte offset formed in 32 bits (arrays stay below 4 GiB), so
@@ -176,6 +198,10 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
   return V3{fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x)};
 }
 __device__ __forceinline__ V3 fma3(float s, V3 a, V3 b) { return V3{fmaf(s, a.x, b.x), fmaf(s, a.y, b.y), fmaf(s, a.z, b.z)}; }
+
+static_assert(F_A1 == F_A0 + 3 && F_C == F_A1 + 3 && F_P == F_C + 6 && F_Z == F_P + 6 && F_FLG == F_Z + 3 &&
+              F_FLG + 1 - F_A0 == N_OUT1, "down 1 outputs are one field range");
+static_assert(F_DU == F_WM + 12 && F_DU + 2 - F_WM == N_OUTU, "up outputs are one field range");
 
 // symmetric 3x3 stored (xx yy zz xy xz yz)
 struct Sym3 { float xx, yy, zz, xy, xz, yz; };

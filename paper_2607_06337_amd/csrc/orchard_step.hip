@@ -12,8 +12,9 @@
 //
 // What a node hands to the next level (its "publication") goes through LDS when every
 // level of the pack fits the workgroup's exchange buffer, double-buffered by level
-// parity and indexed by the node's slot within its level; otherwise (very wide packs)
-// through global scratch.  For the adjoint's recompute the step also stores the values
+// parity; a node's publication is one contiguous 16-byte aligned slot (indexed by the
+// node's position within its level), so it moves with 128-bit LDS accesses.  Otherwise
+// (very wide packs) it goes through global scratch.  For the adjoint's recompute the step also stores the values
 // the reverse pass reads back.
 #include "orchard_dev.h"
 
@@ -21,11 +22,13 @@ namespace orchard {
 
 // Scratch of one pack: P points at the pack's first 64-node block and li = node - i0
 // (i0 = that block's first node), so offsets stay 32-bit; the layout is the global one.
-__device__ __forceinline__ uint32_t sidx(int nf, int f, int li) {
-  return ((uint32_t)(li >> 6) * (uint32_t)nf + (uint32_t)f) * 64u + (uint32_t)(li & 63);
+// A node's fields share one address (base + its 32-bit lane offset); field f adds the
+// constant f*64, which the loads and stores carry as an immediate offset.
+__device__ __forceinline__ uint32_t slane(int nf, int li) {
+  return (uint32_t)(li >> 6) * (uint32_t)nf * 64u + (uint32_t)(li & 63);
 }
-__device__ __forceinline__ float pld(const float* P, int nf, int f, int li) { return at(P, sidx(nf, f, li)); }
-__device__ __forceinline__ void pst(float* P, int nf, int f, int li, float v) { at(P, sidx(nf, f, li)) = v; }
+__device__ __forceinline__ float pld(const float* P, int nf, int f, int li) { return (&at(P, slane(nf, li)))[f * 64]; }
+__device__ __forceinline__ void pst(float* P, int nf, int f, int li, float v) { (&at(P, slane(nf, li)))[f * 64] = v; }
 __device__ __forceinline__ V3 pld3(const float* P, int nf, int f, int li) {
   return v3(pld(P, nf, f, li), pld(P, nf, f + 1, li), pld(P, nf, f + 2, li));
 }
@@ -45,25 +48,38 @@ struct Lvl {
   int b;       // this level's exchange buffer (level parity)
 };
 
-// publication access: field f of a publication block starting at field f0, of node j,
-// which lies on this level (own) or on the neighbouring level (nbr)
-template <bool XL>
-__device__ __forceinline__ float xget(const Lvl& L, int f0, int f, int j) {
-  if constexpr (XL) return L.X[(uint32_t)(((L.b ^ 1) * N_PUB_MAX + (f - f0)) * L.cap + (j - L.nbr))];
-  else return pld(L.P, L.nf, f, j - L.i0);
+// a whole publication: NF fields from f0 of node j on the neighbouring level (load) or of
+// node i on this level (store); on the LDS path a slot moves as 128-bit accesses (the
+// last one also covers padding of the slot, which nobody reads)
+template <bool XL, int NF>
+__device__ __forceinline__ void xload(const Lvl& L, int f0, int j, float (&v)[NF]) {
+  if constexpr (XL) {
+    const float4* s = reinterpret_cast<const float4*>(L.X + (uint32_t)(((L.b ^ 1) * L.cap + (j - L.nbr)) * X_STRIDE));
+#pragma unroll
+    for (int k = 0; k < (NF + 3) / 4; ++k) {
+      const float4 t = s[k];
+      v[4 * k] = t.x;
+      if (4 * k + 1 < NF) v[4 * k + 1] = t.y;
+      if (4 * k + 2 < NF) v[4 * k + 2] = t.z;
+      if (4 * k + 3 < NF) v[4 * k + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) v[k] = pld(L.P, L.nf, f0 + k, j - L.i0);
+  }
 }
-template <bool XL>
-__device__ __forceinline__ void xput(const Lvl& L, int f0, int f, int i, float v) {
-  if constexpr (XL) L.X[(uint32_t)((L.b * N_PUB_MAX + (f - f0)) * L.cap + (i - L.a))] = v;
-  else pst(L.P, L.nf, f, i - L.i0, v);
-}
-template <bool XL>
-__device__ __forceinline__ V3 xget3(const Lvl& L, int f0, int f, int j) {
-  return v3(xget<XL>(L, f0, f, j), xget<XL>(L, f0, f + 1, j), xget<XL>(L, f0, f + 2, j));
-}
-template <bool XL>
-__device__ __forceinline__ void xput3(const Lvl& L, int f0, int f, int i, V3 v) {
-  xput<XL>(L, f0, f, i, v.x); xput<XL>(L, f0, f + 1, i, v.y); xput<XL>(L, f0, f + 2, i, v.z);
+template <bool XL, int NF>
+__device__ __forceinline__ void xstore(const Lvl& L, int f0, int i, const float (&v)[NF]) {
+  if constexpr (XL) {
+    float4* d = reinterpret_cast<float4*>(L.X + (uint32_t)((L.b * L.cap + (i - L.a)) * X_STRIDE));
+#pragma unroll
+    for (int k = 0; k < (NF + 3) / 4; ++k)
+      d[k] = make_float4(v[4 * k], 4 * k + 1 < NF ? v[4 * k + 1] : 0.f, 4 * k + 2 < NF ? v[4 * k + 2] : 0.f,
+                         4 * k + 3 < NF ? v[4 * k + 3] : 0.f);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) pst(L.P, L.nf, f0 + k, i - L.i0, v[k]);
+  }
 }
 
 __device__ __forceinline__ bool finite3(V3 a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
@@ -73,6 +89,17 @@ __device__ __forceinline__ bool finite3(V3 a) { return isfinite(a.x) && isfinite
 // tree's root at the end of the step.  A step's frozen test reads bit 0 only, so it never
 // depends on what other nodes of the same step have done.
 enum : uint32_t { ST_FROZEN = 1u, ST_APPLE_BAD = 2u };
+
+// First moment and rotational inertia about the joint point of an axisymmetric capsule
+// of length l, mass m, transverse / axial inertia Jt / Ia about the joint (geo = l, m, Jt,
+// Ia) whose axis is z.  Down 1 and up both form them, bit for bit the same.
+__device__ __forceinline__ void own_inertia(float4 geo, V3 z, V3& ho, Sym3& Jo) {
+  const float l = geo.x, m = geo.y, Jt = geo.z, Ia = geo.w;
+  ho = (0.5f * m * l) * z;
+  const float dJ = Ia - Jt;
+  Jo = Sym3{fmaf(dJ, z.x * z.x, Jt), fmaf(dJ, z.y * z.y, Jt), fmaf(dJ, z.z * z.z, Jt), dJ * z.x * z.y, dJ * z.x * z.z,
+            dJ * z.y * z.z};
+}
 
 // ------------------------------------------------------------------------------------------
 // down pass 1
@@ -88,7 +115,7 @@ enum : uint32_t { ST_FROZEN = 1u, ST_APPLE_BAD = 2u };
 struct In1 {
   NodeRec nr;
   float2 q, qd;
-  float kp, kd;
+  float kp;
   uint8_t brk, cnt;
 };
 __device__ __forceinline__ In1 load1(const DevModel& M, const DevState& S, const DevInputs& I, int i) {
@@ -97,7 +124,6 @@ __device__ __forceinline__ In1 load1(const DevModel& M, const DevState& S, const
   r.q = at(S.q, (uint32_t)i);
   r.qd = at(S.qd, (uint32_t)i);
   r.kp = at(I.kp, (uint32_t)i);
-  r.kd = at(I.kd, (uint32_t)i);
   r.brk = at(S.seg_evt, (uint32_t)i);
   r.cnt = at(S.seg_evt, (uint32_t)(M.n_seg + i));
   return r;
@@ -105,37 +131,42 @@ __device__ __forceinline__ In1 load1(const DevModel& M, const DevState& S, const
 
 template <bool XL>
 __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L,
-                                           int i, const In1& in, int64_t n, uint64_t kstep, int s_call) {
+                                           int i, const In1& in, int64_t n, uint64_t kstep, int s_call,
+                                           float (&o)[N_OUT1]) {
   const int NS = M.n_seg, nf = M.scr_nf, li = i - L.i0;
   const NodeRec& nr = in.nr;
   const float2 q = in.q, qd = in.qd;
-  const float kp = in.kp, kd = in.kd;
+  const float kp = in.kp;
   uint8_t brk = in.brk;
   const uint8_t cnt0 = in.cnt;
-  const int par = nr.topo.x, e = nr.topo.w;
-  // the env status depends on the node record; it is issued before the arithmetic and
-  // used only by the writes at the end
-  const uint32_t stat = at(S.status, (uint32_t)e);
-  const float l = nr.geo.x, m = nr.geo.y, Jt = nr.geo.z, Ia = nr.geo.w;
-  const float h = M.h;
+  const int par = nr.topo.x;
+  const float l = nr.geo.x, m = nr.geo.y;
 
   // ---- parent publication ----
+  // The env's frozen flag (status bit 0 at the start of the step) is read by the root and
+  // handed down with the snapped flag (F_SNAP = snapped + 2 frozen), so no other node
+  // loads the status word.
   Mat3 Rp;
   V3 pj, w, vt, Aa, Al;
-  bool snp;
+  bool snp, frozen;
   if (par < 0) {
     for (int k = 0; k < 9; ++k) Rp.m[k] = (k % 4 == 0) ? 1.f : 0.f;
     pj = v3(0, 0, 0); w = pj; vt = pj; Aa = pj;
     Al = v3(-M.gx, -M.gy, -M.gz);  // gravity as a base acceleration
     snp = false;
+    frozen = (at(S.status, (uint32_t)nr.topo.w) & ST_FROZEN) != 0u;
   } else {
-    for (int k = 0; k < 9; ++k) Rp.m[k] = xget<XL>(L, F_R, F_R + k, par);
-    pj = xget3<XL>(L, F_R, F_PT, par);
-    w = xget3<XL>(L, F_R, F_W, par);
-    vt = xget3<XL>(L, F_R, F_VT, par);
-    Aa = xget3<XL>(L, F_R, F_AVA, par);
-    Al = xget3<XL>(L, F_R, F_AVL, par);
-    snp = xget<XL>(L, F_R, F_SNAP, par) != 0.f;
+    float pv[N_PUB1];
+    xload<XL>(L, F_R, par, pv);
+    for (int k = 0; k < 9; ++k) Rp.m[k] = pv[F_R + k];
+    pj = v3(pv[F_PT], pv[F_PT + 1], pv[F_PT + 2]);
+    w = v3(pv[F_W], pv[F_W + 1], pv[F_W + 2]);
+    vt = v3(pv[F_VT], pv[F_VT + 1], pv[F_VT + 2]);
+    Aa = v3(pv[F_AVA], pv[F_AVA + 1], pv[F_AVA + 2]);
+    Al = v3(pv[F_AVL], pv[F_AVL + 1], pv[F_AVL + 2]);
+    const int sf = (int)pv[F_SNAP];
+    snp = (sf & 1) != 0;
+    frozen = (sf & 2) != 0;
   }
 
   // ---- rupture test on the state at the start of the step (Eq. break) ----
@@ -183,22 +214,20 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
 
   // ---- publish for children (values at the tip point) ----
   const V3 lz = l * z;
-  xput<XL>(L, F_R, F_R + 0, i, c0.x); xput<XL>(L, F_R, F_R + 1, i, c1.x); xput<XL>(L, F_R, F_R + 2, i, c2.x);
-  xput<XL>(L, F_R, F_R + 3, i, c0.y); xput<XL>(L, F_R, F_R + 4, i, c1.y); xput<XL>(L, F_R, F_R + 5, i, c2.y);
-  xput<XL>(L, F_R, F_R + 6, i, c0.z); xput<XL>(L, F_R, F_R + 7, i, c1.z); xput<XL>(L, F_R, F_R + 8, i, c2.z);
-  xput3<XL>(L, F_R, F_PT, i, pj + lz);
-  xput3<XL>(L, F_R, F_W, i, wi);
-  xput3<XL>(L, F_R, F_VT, i, v + cross(wi, lz));
-  xput3<XL>(L, F_R, F_AVA, i, Ava);
-  xput3<XL>(L, F_R, F_AVL, i, Avl + cross(Ava, lz));
-  xput<XL>(L, F_R, F_SNAP, i, snp ? 1.f : 0.f);
+  {
+    const V3 pt = pj + lz, vtp = v + cross(wi, lz), alt = Avl + cross(Ava, lz);
+    const float ov[N_PUB1] = {c0.x, c1.x, c2.x, c0.y, c1.y, c2.y, c0.z, c1.z, c2.z,
+                              pt.x, pt.y, pt.z, wi.x, wi.y, wi.z, vtp.x, vtp.y, vtp.z,
+                              Ava.x, Ava.y, Ava.z, alt.x, alt.y, alt.z, (snp ? 1.f : 0.f) + (frozen ? 2.f : 0.f)};
+    xstore<XL>(L, F_R, i, ov);
+  }
   if (M.save_adj) {
     // the adjoint reads these from global scratch whichever way levels exchange
     float* P = L.P;
     if constexpr (XL) {
       pst3(P, nf, F_W, li, wi);
       pst3(P, nf, F_VT, li, v + cross(wi, lz));
-      pst(P, nf, F_SNAP, li, snp ? 1.f : 0.f);
+      pst(P, nf, F_SNAP, li, (snp ? 1.f : 0.f) + (frozen ? 2.f : 0.f));
     }
     pst(P, nf, F_SR + 0, li, c0.x); pst(P, nf, F_SR + 1, li, c1.x); pst(P, nf, F_SR + 2, li, c2.x);
     pst(P, nf, F_SR + 3, li, c0.y); pst(P, nf, F_SR + 4, li, c1.y); pst(P, nf, F_SR + 5, li, c2.y);
@@ -207,12 +236,9 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   }
 
   // ---- rigid body inertia about the joint point: axisymmetric capsule ----
-  const float ml2 = 0.5f * m * l;
-  const V3 ho = ml2 * z;
-  const float dJ = Ia - Jt;
-  const Sym3 Jo{fmaf(dJ, z.x * z.x, Jt), fmaf(dJ, z.y * z.y, Jt), fmaf(dJ, z.z * z.z, Jt), dJ * z.x * z.y, dJ * z.x * z.z,
-          dJ * z.y * z.z};
-  const float mo = m;
+  V3 ho;
+  Sym3 Jo;
+  own_inertia(nr.geo, z, ho, Jo);
   // bias force p = v x* (I v)
   const V3 K = mul(Jo, wi) + cross(ho, v);
   const V3 Lm = m * v - cross(ho, wi);
@@ -229,40 +255,30 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     }
   }
 
-  const bool live = (stat & ST_FROZEN) == 0u;
+  const bool live = !frozen;
   // apples are handled by the apple phase after this pass; keep what it needs
   if (nr.topo.z >> 16) {
-    float* P = L.P;
-    pst(P, nf, F_KR + 0, li, c0.x); pst(P, nf, F_KR + 1, li, c1.x); pst(P, nf, F_KR + 2, li, c2.x);
-    pst(P, nf, F_KR + 3, li, c0.y); pst(P, nf, F_KR + 4, li, c1.y); pst(P, nf, F_KR + 5, li, c2.y);
-    pst(P, nf, F_KR + 6, li, c0.z); pst(P, nf, F_KR + 7, li, c1.z); pst(P, nf, F_KR + 8, li, c2.z);
-    pst3(P, nf, F_KW, li, wi); pst3(P, nf, F_KV, li, v);
-    pst3(P, nf, F_KAA, li, Ava); pst3(P, nf, F_KAL, li, Avl);
-    pst3(P, nf, F_KPJ, li, pj);
+    static_assert(K_R == 0 && K_W == 9 && K_V == 12 && K_AA == 15 && K_AL == 18 && K_PJ == 21 && K_N == 24,
+                  "snapshot layout");
+    float4* ks = reinterpret_cast<float4*>(M.asnap + (size_t)nr.aux.z * K_N);
+    ks[0] = make_float4(c0.x, c1.x, c2.x, c0.y);
+    ks[1] = make_float4(c1.y, c2.y, c0.z, c1.z);
+    ks[2] = make_float4(c2.z, wi.x, wi.y, wi.z);
+    ks[3] = make_float4(v.x, v.y, v.z, Ava.x);
+    ks[4] = make_float4(Ava.y, Ava.z, Avl.x, Avl.y);
+    ks[5] = make_float4(Avl.z, pj.x, pj.y, pj.z);
   }
 
-  // ---- spring / damper, implicit diagonal ----
-  const float kpe = brk ? 0.f : kp, kde = brk ? 0.f : kd;
-  const float tau0 = -kpe * fmaf(h, qd.x, q.x) - kde * qd.x;
-  const float tau1 = -kpe * fmaf(h, qd.y, q.y) - kde * qd.y;
-  const float dg = fmaf(h, kde, h * h * kpe);
-
-  // ---- event and frozen-flag writes ----
+  // ---- event writes; the spring terms are formed in the up pass from the flags ----
   if (live && !brk0) {
     at(S.seg_evt, (uint32_t)(NS + i)) = (uint8_t)cnt1;
     if (brk) { at(S.seg_evt, (uint32_t)i) = 1; at(S.evt_step, (uint32_t)i) = (int32_t)n; }
   }
-  float* P = L.P;
-  pst(P, nf, F_SKIP, li, live ? 0.f : 1.f);
-  pst3(P, nf, F_A0, li, a0); pst3(P, nf, F_A1, li, a1);
-  pst3(P, nf, F_C, li, cang); pst3(P, nf, F_C + 3, li, clin);
-  pst3(P, nf, F_P, li, pang); pst3(P, nf, F_P + 3, li, plin);
-  pst(P, nf, F_MO, li, mo); pst3(P, nf, F_HO, li, ho);
-  pst(P, nf, F_JO + 0, li, Jo.xx); pst(P, nf, F_JO + 1, li, Jo.yy); pst(P, nf, F_JO + 2, li, Jo.zz);
-  pst(P, nf, F_JO + 3, li, Jo.xy); pst(P, nf, F_JO + 4, li, Jo.xz); pst(P, nf, F_JO + 5, li, Jo.yz);
-  pst(P, nf, F_TAU, li, tau0); pst(P, nf, F_TAU + 1, li, tau1);
-  pst(P, nf, F_DG, li, dg);
-  pst3(P, nf, F_LZ, li, lz);
+  // node-private outputs (fields F_A0 .. F_FLG), stored by the caller
+  const float out[N_OUT1] = {a0.x, a0.y, a0.z, a1.x, a1.y, a1.z, cang.x, cang.y, cang.z, clin.x, clin.y, clin.z,
+                             pang.x, pang.y, pang.z, plin.x, plin.y, plin.z, z.x, z.y, z.z,
+                             (live ? 0.f : 1.f) + (brk ? 2.f : 0.f)};
+  for (int k = 0; k < N_OUT1; ++k) o[k] = out[k];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -274,6 +290,13 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// a pass's node-private outputs, fields F0 .. F0 + K - 1, at a node's scratch address
+template <int F0, int K>
+__device__ __forceinline__ void put_fields(float* base, const float (&o)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) base[(F0 + k) * 64] = o[k];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -289,8 +312,8 @@ struct AppleCon { float mv; V3 d, pang, plin; };
 template <int NT>
 __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L,
                                             float* C, int pk, int64_t n, int s_call) {
-  const int A0 = M.pack_apl[pk], A1 = M.pack_apl[pk + 1];
-  const int NS = M.n_seg, nf = M.scr_nf, t = (int)threadIdx.x;
+  const int A0 = ldc(M.pack_apl, pk), A1 = ldc(M.pack_apl, pk + 1);
+  const int NS = M.n_seg, t = (int)threadIdx.x;
   const uint32_t NA = (uint32_t)M.n_apple;
   const float h = M.h;
   const V3 gv = v3(M.gx, M.gy, M.gz);
@@ -300,17 +323,24 @@ __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S
     const bool has = a < A1;
     AppleCon con{0.f, v3(0, 0, 0), v3(0, 0, 0), v3(0, 0, 0)};
     int node = -1;
+    bool first = false;  // the node's first apple
+    int an = 0;          // the node's apple-node index
     if (has) {
       const uint32_t ua = (uint32_t)a;
       const AppleRec ar = at(M.arec, ua);
       node = ar.link.x;
-      const int li = node - L.i0;
-      const float* P = L.P;
-      const bool live = pld(P, nf, F_SKIP, li) == 0.f;
+      first = ar.link.z != 0;
+      an = ar.link.w;
+      // the env's frozen flag cannot change before down 2, so the status word still holds
+      // the value down 1 saw
+      const bool live = (at(S.status, (uint32_t)ar.link.y) & ST_FROZEN) == 0u;
+      const float4* ks = reinterpret_cast<const float4*>(M.asnap + (size_t)ar.link.w * K_N);
+      const float4 k0 = ks[0], k1 = ks[1], k2 = ks[2], k3 = ks[3], k4 = ks[4], k5 = ks[5];
       Mat3 R;
-      for (int k = 0; k < 9; ++k) R.m[k] = pld(P, nf, F_KR + k, li);
-      const V3 wi = pld3(P, nf, F_KW, li), v = pld3(P, nf, F_KV, li);
-      const V3 Ava = pld3(P, nf, F_KAA, li), Avl = pld3(P, nf, F_KAL, li), pj = pld3(P, nf, F_KPJ, li);
+      R.m[0] = k0.x; R.m[1] = k0.y; R.m[2] = k0.z; R.m[3] = k0.w; R.m[4] = k1.x; R.m[5] = k1.y;
+      R.m[6] = k1.z; R.m[7] = k1.w; R.m[8] = k2.x;
+      const V3 wi = v3(k2.y, k2.z, k2.w), v = v3(k3.x, k3.y, k3.z);
+      const V3 Ava = v3(k3.w, k4.x, k4.y), Avl = v3(k4.z, k4.w, k5.x), pj = v3(k5.y, k5.z, k5.w);
       float* Pa = S.apple;
       // position state: while attached sigma = (x - x_hang) + h v from the previous
       // update, so the stretch now is s = sigma - h v_hang; once detached, x minus the
@@ -404,15 +434,17 @@ __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S
     C[7 * NT + t] = con.plin.x; C[8 * NT + t] = con.plin.y; C[9 * NT + t] = con.plin.z;
     C[10 * NT + t] = __int_as_float(node);
     lds_barrier();
-    // the thread with a node's first apple in this chunk adds the chunk's contributions
+    // the thread with a node's first apple in this chunk adds the chunk's contributions;
+    // the virtual inertia starts from zero at the node's first apple
     if (has && (t == 0 || __float_as_int(C[10 * NT + t - 1]) != node)) {
-      float* P = L.P;
-      const int li = node - L.i0;
-      float mo = pld(P, nf, F_MO, li);
-      V3 ho = pld3(P, nf, F_HO, li);
-      Sym3 Jo{pld(P, nf, F_JO + 0, li), pld(P, nf, F_JO + 1, li), pld(P, nf, F_JO + 2, li),
-              pld(P, nf, F_JO + 3, li), pld(P, nf, F_JO + 4, li), pld(P, nf, F_JO + 5, li)};
-      V3 pang = pld3(P, nf, F_P, li), plin = pld3(P, nf, F_P + 3, li);
+      static_assert(E_MO == 0 && E_HO == 1 && E_JO == 4 && E_P == 10 && E_N == 16, "apple sums layout");
+      float4* es = reinterpret_cast<float4*>(M.aext + (size_t)an * E_N);
+      float4 e0 = make_float4(0.f, 0.f, 0.f, 0.f), e1 = e0, e2 = e0, e3 = e0;
+      if (!first) { e0 = es[0]; e1 = es[1]; e2 = es[2]; e3 = es[3]; }
+      float mo = e0.x;
+      V3 ho = v3(e0.y, e0.z, e0.w);
+      Sym3 Jo{e1.x, e1.y, e1.z, e1.w, e2.x, e2.y};
+      V3 pang = v3(e2.z, e2.w, e3.x), plin = v3(e3.y, e3.z, e3.w);
       for (int k = t; k < NT && c0 + k < A1 && __float_as_int(C[10 * NT + k]) == node; ++k) {
         const float mv = C[0 * NT + k];
         const V3 d = v3(C[1 * NT + k], C[2 * NT + k], C[3 * NT + k]);
@@ -425,61 +457,95 @@ __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S
         pang = pang + v3(C[4 * NT + k], C[5 * NT + k], C[6 * NT + k]);
         plin = plin + v3(C[7 * NT + k], C[8 * NT + k], C[9 * NT + k]);
       }
-      pst(P, nf, F_MO, li, mo);
-      pst3(P, nf, F_HO, li, ho);
-      pst(P, nf, F_JO + 0, li, Jo.xx); pst(P, nf, F_JO + 1, li, Jo.yy); pst(P, nf, F_JO + 2, li, Jo.zz);
-      pst(P, nf, F_JO + 3, li, Jo.xy); pst(P, nf, F_JO + 4, li, Jo.xz); pst(P, nf, F_JO + 5, li, Jo.yz);
-      pst3(P, nf, F_P, li, pang); pst3(P, nf, F_P + 3, li, plin);
+      es[0] = make_float4(mo, ho.x, ho.y, ho.z);
+      es[1] = make_float4(Jo.xx, Jo.yy, Jo.zz, Jo.xy);
+      es[2] = make_float4(Jo.xz, Jo.yz, pang.x, pang.y);
+      es[3] = make_float4(pang.z, plin.x, plin.y, plin.z);
     }
     // node sums of this chunk are visible to the next chunk's threads; the LDS can be reused
     __syncthreads();
   }
 }
 
-// up-pass inputs: the node's own data from down 1
-struct InU {
-  int4 topo;
-  V3 r, ho, pon, pof, a0, a1, ca, cl;
-  Sym3 Jo;
-  float mo, dg, tau0, tau1;
+// up-pass inputs: the node's own data from down 1, its static record and state.  The
+// topology word is loaded a level earlier than the rest (the LDS path pipelines it), so
+// the loads of the virtual apple inertia can be limited to nodes that carry apples
+// without waiting on a load.
+// the part of a node's topology word the up pass reads
+struct TopoU {
+  int child, cnt, an;  // first child, children | apples << 16, apple-node index
 };
-__device__ __forceinline__ InU loadU(const DevModel& M, const Lvl& L, int i) {
+__device__ __forceinline__ TopoU topo_up(const DevModel& M, int i) {
+  const int* w = reinterpret_cast<const int*>(&at(M.ntopo, (uint32_t)i));
+  return TopoU{w[1], w[2], w[3]};
+}
+struct InU {
+  TopoU topo;
+  float4 geo, e0, e1, e2, e3;  // e: the apple sums of a node that carries apples
+  V3 z, pon, pof, a0, a1, ca, cl;
+  float2 q, qd;
+  float kp, kd, flg;
+};
+__device__ __forceinline__ InU loadU(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L, int i,
+                                     TopoU topo) {
   const int nf = M.scr_nf, li = i - L.i0;
   const float* P = L.P;
   InU u;
-  u.topo = at(M.ntopo, (uint32_t)i);
-  u.r = pld3(P, nf, F_LZ, li);
-  u.mo = pld(P, nf, F_MO, li);
-  u.ho = pld3(P, nf, F_HO, li);
-  u.Jo = Sym3{pld(P, nf, F_JO + 0, li), pld(P, nf, F_JO + 1, li), pld(P, nf, F_JO + 2, li),
-              pld(P, nf, F_JO + 3, li), pld(P, nf, F_JO + 4, li), pld(P, nf, F_JO + 5, li)};
+  u.topo = topo;
+  u.geo = at(M.geo, (uint32_t)i);
+  u.q = at(S.q, (uint32_t)i);
+  u.qd = at(S.qd, (uint32_t)i);
+  u.kp = at(I.kp, (uint32_t)i);
+  u.kd = at(I.kd, (uint32_t)i);
+  u.z = pld3(P, nf, F_Z, li);
+  u.flg = pld(P, nf, F_FLG, li);
   u.pon = pld3(P, nf, F_P, li);
   u.pof = pld3(P, nf, F_P + 3, li);
   u.a0 = pld3(P, nf, F_A0, li);
   u.a1 = pld3(P, nf, F_A1, li);
-  u.dg = pld(P, nf, F_DG, li);
-  u.tau0 = pld(P, nf, F_TAU, li);
-  u.tau1 = pld(P, nf, F_TAU + 1, li);
   u.ca = pld3(P, nf, F_C, li);
   u.cl = pld3(P, nf, F_C + 3, li);
+  u.e0 = u.e1 = u.e2 = u.e3 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (topo.cnt >> 16) {
+    const float4* es = reinterpret_cast<const float4*>(M.aext + (size_t)topo.an * E_N);
+    u.e0 = es[0]; u.e1 = es[1]; u.e2 = es[2]; u.e3 = es[3];
+  }
   return u;
 }
 
 template <bool XL>
-__device__ __forceinline__ void node_up(const DevModel& M, const Lvl& L, int i, const InU& in) {
+__device__ __forceinline__ void node_up(const DevModel& M, const Lvl& L, int i, const InU& in, float (&o)[N_OUTU]) {
   const int nf = M.scr_nf, li = i - L.i0;
-  const int4 topo = in.topo;
-  const V3 r = in.r, ho = in.ho, pon = in.pon, pof = in.pof, a0 = in.a0, a1 = in.a1, ca = in.ca, cl = in.cl;
-  const float mo = in.mo, dg = in.dg, tau0 = in.tau0, tau1 = in.tau1;
-  const Sym3 Jo = in.Jo;
+  const TopoU topo = in.topo;
+  const V3 a0 = in.a0, a1 = in.a1, ca = in.ca, cl = in.cl;
+  const V3 r = in.geo.x * in.z;  // l z, joint point -> tip
+  // own body plus the apples' virtual masses and reactions (zero without apples)
+  const float4 e0 = in.e0, e1 = in.e1, e2 = in.e2, e3 = in.e3;
+  V3 ho;
+  Sym3 Jo;
+  own_inertia(in.geo, in.z, ho, Jo);
+  const float mo = in.geo.y + e0.x;
+  ho = ho + v3(e0.y, e0.z, e0.w);
+  Jo.xx += e1.x; Jo.yy += e1.y; Jo.zz += e1.z; Jo.xy += e1.w; Jo.xz += e2.x; Jo.yz += e2.y;
+  const V3 pon = in.pon + v3(e2.z, e2.w, e3.x), pof = in.pof + v3(e3.y, e3.z, e3.w);
+  // spring / damper with the implicit diagonal; a broken joint has none
+  const float h = M.h;
+  const bool brk = (((int)in.flg) & 2) != 0;
+  const float kpe = brk ? 0.f : in.kp, kde = brk ? 0.f : in.kd;
+  const float2 q = in.q, qd = in.qd;
+  const float tau0 = -kpe * fmaf(h, qd.x, q.x) - kde * qd.x;
+  const float tau1 = -kpe * fmaf(h, qd.y, q.y) - kde * qd.y;
+  const float dg = fmaf(h, kde, h * h * kpe);
 
   Sym3 A{0, 0, 0, 0, 0, 0}, Mm{0, 0, 0, 0, 0, 0};
   Mat3 B;
   for (int k = 0; k < 9; ++k) B.m[k] = 0.f;
   V3 pn = v3(0, 0, 0), pf = v3(0, 0, 0);
-  const int cb = topo.y, ce = cb + (topo.z & 0xFFFF);
+  const int cb = topo.child, ce = cb + (topo.cnt & 0xFFFF);
   for (int c = cb; c < ce; ++c) {
-#define XG(f) xget<XL>(L, F_IA, (f), c)
+    float cv[N_PUBU];
+    xload<XL>(L, F_IA, c, cv);
+#define XG(f) cv[(f) - F_IA]
     A.xx += XG(F_IA + 0); A.yy += XG(F_IA + 1); A.zz += XG(F_IA + 2);
     A.xy += XG(F_IA + 3); A.xz += XG(F_IA + 4); A.yz += XG(F_IA + 5);
     for (int k = 0; k < 9; ++k) B.m[k] += XG(F_IB + k);
@@ -547,19 +613,20 @@ __device__ __forceinline__ void node_up(const DevModel& M, const Lvl& L, int i, 
   // bias passed to the parent: p^A + I^a c + W u
   pn = pn + mul(A, ca) + mul(B, cl) + fma3(uu0, W0a, uu1 * W1a);
   pf = pf + mulT(B, ca) + mul(Mm, cl) + fma3(uu0, W0l, uu1 * W1l);
-#define XP(f, v) xput<XL>(L, F_IA, (f), i, (v))
-  XP(F_IA + 0, A.xx); XP(F_IA + 1, A.yy); XP(F_IA + 2, A.zz);
-  XP(F_IA + 3, A.xy); XP(F_IA + 4, A.xz); XP(F_IA + 5, A.yz);
-  for (int k = 0; k < 9; ++k) XP(F_IB + k, B.m[k]);
-  XP(F_IM + 0, Mm.xx); XP(F_IM + 1, Mm.yy); XP(F_IM + 2, Mm.zz);
-  XP(F_IM + 3, Mm.xy); XP(F_IM + 4, Mm.xz); XP(F_IM + 5, Mm.yz);
-  XP(F_PA + 0, pn.x); XP(F_PA + 1, pn.y); XP(F_PA + 2, pn.z);
-  XP(F_PA + 3, pf.x); XP(F_PA + 4, pf.y); XP(F_PA + 5, pf.z);
-#undef XP
+  {
+    const float ov[N_PUBU] = {A.xx, A.yy, A.zz, A.xy, A.xz, A.yz,
+                              B.m[0], B.m[1], B.m[2], B.m[3], B.m[4], B.m[5], B.m[6], B.m[7], B.m[8],
+                              Mm.xx, Mm.yy, Mm.zz, Mm.xy, Mm.xz, Mm.yz,
+                              pn.x, pn.y, pn.z, pf.x, pf.y, pf.z};
+    static_assert(F_IB - F_IA == 6 && F_IM - F_IA == 15 && F_PA - F_IA == 21, "publication order");
+    xstore<XL>(L, F_IA, i, ov);
+  }
   float* Pw = L.P;
-  pst3(Pw, nf, F_U, li, U0a); pst3(Pw, nf, F_U + 3, li, U0l); pst3(Pw, nf, F_U + 6, li, U1a); pst3(Pw, nf, F_U + 9, li, U1l);
-  pst(Pw, nf, F_DI, li, Di00); pst(Pw, nf, F_DI + 1, li, Di01); pst(Pw, nf, F_DI + 2, li, Di11);
-  pst(Pw, nf, F_UU, li, uu0); pst(Pw, nf, F_UU + 1, li, uu1);
+  if (M.save_adj) { pst(Pw, nf, F_DI, li, Di00); pst(Pw, nf, F_DI + 1, li, Di01); pst(Pw, nf, F_DI + 2, li, Di11); }
+  // node-private outputs (fields F_WM .. F_DU + 1), stored by the caller
+  const float out[N_OUTU] = {W0a.x, W0a.y, W0a.z, W0l.x, W0l.y, W0l.z, W1a.x, W1a.y, W1a.z, W1l.x, W1l.y, W1l.z,
+                             fmaf(Di00, uu0, Di01 * uu1), fmaf(Di01, uu0, Di11 * uu1)};
+  for (int k = 0; k < N_OUTU; ++k) o[k] = out[k];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -567,31 +634,29 @@ __device__ __forceinline__ void node_up(const DevModel& M, const Lvl& L, int i, 
 // ------------------------------------------------------------------------------------------
 // down 2 inputs: the node's factor data from the up pass and its state
 struct In2 {
-  int4 topo;
-  float skip, uu0, uu1, Di00, Di01, Di11;
-  V3 ca, cl, U0a, U0l, U1a, U1l, a0, a1, lz;
+  int par;
+  float flg, du0, du1, l;
+  V3 ca, cl, W0a, W0l, W1a, W1l, a0, a1, z;
   float2 q, qd;
 };
 __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const Lvl& L, int i) {
   const int nf = M.scr_nf, li = i - L.i0;
   const float* P = L.P;
   In2 d;
-  d.topo = at(M.ntopo, (uint32_t)i);
-  d.skip = pld(P, nf, F_SKIP, li);
+  d.par = at(M.ntopo, (uint32_t)i).x;
+  d.l = at(M.geo, (uint32_t)i).x;
+  d.flg = pld(P, nf, F_FLG, li);
   d.ca = pld3(P, nf, F_C, li);
   d.cl = pld3(P, nf, F_C + 3, li);
-  d.U0a = pld3(P, nf, F_U, li);
-  d.U0l = pld3(P, nf, F_U + 3, li);
-  d.U1a = pld3(P, nf, F_U + 6, li);
-  d.U1l = pld3(P, nf, F_U + 9, li);
-  d.uu0 = pld(P, nf, F_UU, li);
-  d.uu1 = pld(P, nf, F_UU + 1, li);
-  d.Di00 = pld(P, nf, F_DI, li);
-  d.Di01 = pld(P, nf, F_DI + 1, li);
-  d.Di11 = pld(P, nf, F_DI + 2, li);
+  d.W0a = pld3(P, nf, F_WM, li);
+  d.W0l = pld3(P, nf, F_WM + 3, li);
+  d.W1a = pld3(P, nf, F_WM + 6, li);
+  d.W1l = pld3(P, nf, F_WM + 9, li);
+  d.du0 = pld(P, nf, F_DU, li);
+  d.du1 = pld(P, nf, F_DU + 1, li);
   d.a0 = pld3(P, nf, F_A0, li);
   d.a1 = pld3(P, nf, F_A1, li);
-  d.lz = pld3(P, nf, F_LZ, li);
+  d.z = pld3(P, nf, F_Z, li);
   d.q = at(S.q, (uint32_t)i);
   d.qd = at(S.qd, (uint32_t)i);
   return d;
@@ -600,32 +665,34 @@ __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const
 template <bool XL>
 __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S, const Lvl& L, int i, const In2& in) {
   const int nf = M.scr_nf, li = i - L.i0;
-  const int par = in.topo.x, e = in.topo.w;
-  const bool live = in.skip == 0.f;
-  const V3 ca = in.ca, cl = in.cl, U0a = in.U0a, U0l = in.U0l, U1a = in.U1a, U1l = in.U1l;
-  const float uu0 = in.uu0, uu1 = in.uu1, Di00 = in.Di00, Di01 = in.Di01, Di11 = in.Di11;
-  const V3 a0 = in.a0, a1 = in.a1, lz = in.lz;
+  const int par = in.par;
+  const bool live = (((int)in.flg) & 1) == 0;
+  const V3 ca = in.ca, cl = in.cl, W0a = in.W0a, W0l = in.W0l, W1a = in.W1a, W1l = in.W1l;
+  const V3 a0 = in.a0, a1 = in.a1, lz = in.l * in.z;
   float2 q = in.q, qd = in.qd;
   V3 Aa, Al;
   if (par < 0) { Aa = v3(0, 0, 0); Al = v3(-M.gx, -M.gy, -M.gz); }
   else {
-    Aa = xget3<XL>(L, F_AT, F_AT, par);
-    Al = xget3<XL>(L, F_AT, F_AT + 3, par);
+    float pv[6];
+    xload<XL>(L, F_AT, par, pv);
+    Aa = v3(pv[0], pv[1], pv[2]);
+    Al = v3(pv[3], pv[4], pv[5]);
   }
   Aa = Aa + ca;
   Al = Al + cl;
-  const float t0 = uu0 - (dot(U0a, Aa) + dot(U0l, Al));
-  const float t1 = uu1 - (dot(U1a, Aa) + dot(U1l, Al));
-  const float qdd0 = fmaf(Di00, t0, Di01 * t1);
-  const float qdd1 = fmaf(Di01, t0, Di11 * t1);
+  const float qdd0 = in.du0 - (dot(W0a, Aa) + dot(W0l, Al));
+  const float qdd1 = in.du1 - (dot(W1a, Aa) + dot(W1l, Al));
   Aa = fma3(qdd0, a0, fma3(qdd1, a1, Aa));
   if (M.save_adj) {
     float* Pw = L.P;
     pst3(Pw, nf, F_SA, li, Aa); pst3(Pw, nf, F_SA + 3, li, Al);
     pst(Pw, nf, F_SQDD, li, qdd0); pst(Pw, nf, F_SQDD + 1, li, qdd1);
   }
-  xput3<XL>(L, F_AT, F_AT, i, Aa);
-  xput3<XL>(L, F_AT, F_AT + 3, i, Al + cross(Aa, lz));
+  {
+    const V3 alt = Al + cross(Aa, lz);
+    const float ov[6] = {Aa.x, Aa.y, Aa.z, alt.x, alt.y, alt.z};
+    xstore<XL>(L, F_AT, i, ov);
+  }
   if (!live) return;
   const float h = M.h;
   qd.x = fmaf(h, qdd0, qd.x);
@@ -634,10 +701,14 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
   q.y = fmaf(h, qd.y, q.y);
   at(S.q, (uint32_t)i) = q;
   at(S.qd, (uint32_t)i) = qd;
-  uint32_t* st = &at(S.status, (uint32_t)e);
-  if (!(isfinite(q.x) && isfinite(q.y) && isfinite(qd.x) && isfinite(qd.y))) atomicOr(st, ST_FROZEN);
-  // the root promotes this step's apple flag once every node of the step has run down 1
-  if (par < 0 && (*st & ST_APPLE_BAD)) atomicOr(st, ST_FROZEN);
+  // a non-finite state freezes the env; the root promotes this step's apple flag once every
+  // node of the step has run down 1 (only these rare cases touch the status word)
+  const bool bad = !(isfinite(q.x) && isfinite(q.y) && isfinite(qd.x) && isfinite(qd.y));
+  if (bad || par < 0) {
+    uint32_t* st = &at(S.status, (uint32_t)at(M.env, (uint32_t)i));
+    if (bad) atomicOr(st, ST_FROZEN);
+    if (par < 0 && (*st & ST_APPLE_BAD)) atomicOr(st, ST_FROZEN);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -661,8 +732,11 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
       L.a = M.lvl_off[lv];
       const int e = M.lvl_off[lv + 1];
       L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
-      for (int i = L.a + (int)threadIdx.x; i < e; i += NT)
-        node_down1<false>(M, S, I, L, i, load1(M, S, I, i), n, kstep, call_step0 + st);
+      for (int i = L.a + (int)threadIdx.x; i < e; i += NT) {
+        float o[N_OUT1];
+        node_down1<false>(M, S, I, L, i, load1(M, S, I, i), n, kstep, call_step0 + st, o);
+        put_fields<F_A0>(&at(L.P, slane(L.nf, i - L.i0)), o);
+      }
       __syncthreads();
     }
     apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
@@ -670,7 +744,11 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
       L.a = M.lvl_off[lv];
       const int e = M.lvl_off[lv + 1];
       L.nbr = e;
-      for (int i = L.a + (int)threadIdx.x; i < e; i += NT) node_up<false>(M, L, i, loadU(M, L, i));
+      for (int i = L.a + (int)threadIdx.x; i < e; i += NT) {
+        float o[N_OUTU];
+        node_up<false>(M, L, i, loadU(M, S, I, L, i, topo_up(M, i)), o);
+        put_fields<F_WM>(&at(L.P, slane(L.nf, i - L.i0)), o);
+      }
       __syncthreads();
     }
     for (int lv = lb; lv < le; ++lv) {
@@ -708,7 +786,11 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
         In1 nxt{};
         if (hn) nxt = load1(M, S, I, in_);
-        if (has) node_down1<true>(M, S, I, L, i, cur, n, kstep, call_step0 + st);
+        if (has) {
+          float o[N_OUT1];
+          node_down1<true>(M, S, I, L, i, cur, n, kstep, call_step0 + st, o);
+          put_fields<F_A0>(&at(L.P, slane(L.nf, i - L.i0)), o);
+        }
         if (lv + 1 < le) lds_barrier();
         i = in_; has = hn; cur = nxt;
       }
@@ -716,21 +798,34 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
     __syncthreads();
     apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
     {
+      // three levels in flight: the topology word two levels ahead, the other inputs one
+      // level ahead, the arithmetic of the current level
       int i = M.lvl_off[le - 1] + t;
       bool has = i < M.lvl_off[le];
       InU cur{};
-      if (has) cur = loadU(M, L, i);
+      if (has) cur = loadU(M, S, I, L, i, topo_up(M, i));
+      int i1 = le - 1 > lb ? M.lvl_off[le - 2] + t : 0;
+      bool h1 = le - 1 > lb && i1 < M.lvl_off[le - 1];
+      TopoU tp1{0, 0, 0};
+      if (h1) tp1 = topo_up(M, i1);
       for (int lv = le - 1; lv >= lb; --lv) {
         L.a = M.lvl_off[lv];
         L.nbr = M.lvl_off[lv + 1];
         L.b = (lv - lb) & 1;
-        const int in_ = lv > lb ? M.lvl_off[lv - 1] + t : 0;
-        const bool hn = lv > lb && in_ < M.lvl_off[lv];
+        const int i2 = lv - 1 > lb ? M.lvl_off[lv - 2] + t : 0;
+        const bool h2 = lv - 1 > lb && i2 < M.lvl_off[lv - 1];
+        TopoU tp2{0, 0, 0};
+        if (h2) tp2 = topo_up(M, i2);
         InU nxt{};
-        if (hn) nxt = loadU(M, L, in_);
-        if (has) node_up<true>(M, L, i, cur);
+        if (h1) nxt = loadU(M, S, I, L, i1, tp1);
+        if (has) {
+          float o[N_OUTU];
+          node_up<true>(M, L, i, cur, o);
+          put_fields<F_WM>(&at(L.P, slane(L.nf, i - L.i0)), o);
+        }
         if (lv > lb) lds_barrier();
-        i = in_; has = hn; cur = nxt;
+        i = i1; has = h1; cur = nxt;
+        i1 = i2; h1 = h2; tp1 = tp2;
       }
     }
     __syncthreads();
@@ -759,9 +854,9 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
 template <int NT, bool XL>
 __device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, const DevInputs& I, float* X,
                                          float* Abuf, int pk, int64_t n0, int n_inner, int call_step0) {
-  const int lb = M.pack_lvl[pk], le = M.pack_lvl[pk + 1] - 1;
+  const int lb = ldc(M.pack_lvl, pk), le = ldc(M.pack_lvl, pk + 1) - 1;
   Lvl L;
-  L.i0 = M.pack_node[pk] & ~63;
+  L.i0 = ldc(M.pack_node, pk) & ~63;
   L.nf = M.scr_nf;
   L.P = M.scr + (size_t)(L.i0 >> 6) * (size_t)L.nf * 64u;
   L.X = X;
@@ -774,24 +869,28 @@ __device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, c
 template <int NT>
 __device__ __forceinline__ void run_pack_any(const DevModel& M, const DevState& S, const DevInputs& I, float* X,
                                              float* Abuf, int pk, int64_t n0, int n_inner, int call_step0) {
-  if (M.lds_cap > 0 && M.pack_lds[pk]) run_pack<NT, true>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
+  if (M.lds_cap > 0 && ldc(M.pack_lds, pk)) run_pack<NT, true>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
   else run_pack<NT, false>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
 }
 
-// one workgroup per pack; dynamic LDS: max(2 * N_PUB_MAX * lds_cap, 11 * NT) floats, the
+// one workgroup per pack; dynamic LDS: max(2 * X_STRIDE * lds_cap, 11 * NT) floats, the
 // level exchange and, between down 1 and up, the apple phase's chunk buffer
+// At least three waves per SIMD (at most 168 VGPRs): the exchange LDS of the widest
+// packs also allows three workgroups of 256 work-items per CU.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_step_packs(DevModel M, DevState S, DevInputs I, int n_inner, int call_step0) {
-  HIP_DYNAMIC_SHARED(float, xlds)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_step_packs(DevModel M, DevState S, DevInputs I, int n_inner, int call_step0) {
+  HIP_DYNAMIC_SHARED(float4, xlds4)
+  float* xlds = reinterpret_cast<float*>(xlds4);
   const int64_t n0 = *S.step;
   run_pack_any<NT>(M, S, I, xlds, xlds, (int)blockIdx.x, n0, n_inner, call_step0);
 }
 
 // persistent grid: workgroups pull packs (largest first) from a counter
 template <int NT>
-__global__ __launch_bounds__(NT) void k_step_persistent(DevModel M, DevState S, DevInputs I, int n_inner,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_step_persistent(DevModel M, DevState S, DevInputs I, int n_inner,
                                                         int call_step0, int32_t* counter) {
-  HIP_DYNAMIC_SHARED(float, xlds)
+  HIP_DYNAMIC_SHARED(float4, xlds4)
+  float* xlds = reinterpret_cast<float*>(xlds4);
   __shared__ int pk;
   const int64_t n0 = *S.step;
   for (;;) {
