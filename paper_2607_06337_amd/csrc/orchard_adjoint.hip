@@ -38,20 +38,54 @@ struct RecView {
   __device__ uint32_t apple_evt(int a) const { return __float_as_uint(w[4 * NS + 13 * NA + NS + a]); }
 };
 
+// Each pass is split, as in the forward step, into a load stage (the node's own data:
+// forward scratch of this step, adjoint state, static records) and a compute stage that
+// also reads the neighbouring level's publications; on the LDS path the load stage of the
+// next level is issued before the current level's arithmetic, and publications move
+// through the LDS exchange (otherwise through the global fields F_LPA, F_LA, F_RB).
+// Frozen envs run the arithmetic and skip only the writes that change the adjoint state or
+// the gradients; their scratch and publications are read only by nodes of the same env.
+
 // ---- lambda solve, up pass: forward substitution with the stored factor ------------------
-// Frozen envs: the loads are issued unconditionally (so they overlap) and only the writes
-// that change the adjoint state or the gradients are skipped; scratch of a frozen env is
-// read only by nodes of the same env.
-__device__ void node_lam_up(const DevModel& M, const DevAdj& X, int i) {
+struct InLU {
+  int cb, ce;
+  float l, Di00, Di01, Di11;
+  V3 z, a0, a1, W0a, W0l, W1a, W1l;
+  float2 qb, qdb;
+};
+__device__ __forceinline__ InLU load_lu(const DevModel& M, const DevAdj& X, const Lvl& L, int i) {
+  const int nf = M.scr_nf, li = i - L.i0;
+  const float* P = L.P;
   const int4 topo = at(M.ntopo, (uint32_t)i);
-  const V3 lz = M.geo[i].x * ald3(M, F_Z, i);
-  const float2 qb = X.q[i], qdb = X.qd[i];
-  const V3 a0 = ald3(M, F_A0, i), a1 = ald3(M, F_A1, i);
-  const V3 W0a = ald3(M, F_WM, i), W0l = ald3(M, F_WM + 3, i), W1a = ald3(M, F_WM + 6, i), W1l = ald3(M, F_WM + 9, i);
-  const float Di00 = aldf(M, F_DI, i), Di01 = aldf(M, F_DI + 1, i), Di11 = aldf(M, F_DI + 2, i);
+  InLU r;
+  r.cb = topo.y;
+  r.ce = topo.y + (topo.z & 0xFFFF);
+  r.l = at(M.geo, (uint32_t)i).x;
+  r.z = pld3(P, nf, F_Z, li);
+  r.qb = at(X.q, (uint32_t)i);
+  r.qdb = at(X.qd, (uint32_t)i);
+  r.a0 = pld3(P, nf, F_A0, li);
+  r.a1 = pld3(P, nf, F_A1, li);
+  r.W0a = pld3(P, nf, F_WM, li); r.W0l = pld3(P, nf, F_WM + 3, li);
+  r.W1a = pld3(P, nf, F_WM + 6, li); r.W1l = pld3(P, nf, F_WM + 9, li);
+  r.Di00 = pld(P, nf, F_DI, li); r.Di01 = pld(P, nf, F_DI + 1, li); r.Di11 = pld(P, nf, F_DI + 2, li);
+  return r;
+}
+template <bool XL>
+__device__ __forceinline__ void node_lam_up(const DevModel& M, const Lvl& L, int i, const InLU& in) {
+  const int nf = M.scr_nf, li = i - L.i0;
+  const V3 lz = in.l * in.z;
+  const float2 qb = in.qb, qdb = in.qdb;
+  const V3 a0 = in.a0, a1 = in.a1;
+  const V3 W0a = in.W0a, W0l = in.W0l, W1a = in.W1a, W1l = in.W1l;
+  const float Di00 = in.Di00, Di01 = in.Di01, Di11 = in.Di11;
   V3 pn = v3(0, 0, 0), pf = v3(0, 0, 0);
-  const int cb = topo.y, ce = cb + (topo.z & 0xFFFF);
-  for (int c = cb; c < ce; ++c) { pn = pn + ald3(M, F_LPA, c); pf = pf + ald3(M, F_LPA + 3, c); }
+  for (int c = in.cb; c < in.ce; ++c) {
+    float cv[6];
+    xload<XL>(L, F_LPA, c, cv);
+    pn = pn + v3(cv[0], cv[1], cv[2]);
+    pf = pf + v3(cv[3], cv[4], cv[5]);
+  }
   pn = pn + cross(lz, pf);
   const float h = M.h;
   const float b0 = h * fmaf(h, qb.x, qdb.x), b1 = h * fmaf(h, qb.y, qdb.y);  // qdd_bar
@@ -59,65 +93,147 @@ __device__ void node_lam_up(const DevModel& M, const DevAdj& X, int i) {
   // U D^-1 u = W u; the down pass needs D^-1 u
   pn = fma3(u0, W0a, fma3(u1, W1a, pn));
   pf = fma3(u0, W0l, fma3(u1, W1l, pf));
-  asto(M, F_LU, i, fmaf(Di00, u0, Di01 * u1)); asto(M, F_LU + 1, i, fmaf(Di01, u0, Di11 * u1));
-  asto3(M, F_LPA, i, pn); asto3(M, F_LPA + 3, i, pf);
+  pst(L.P, nf, F_LU, li, fmaf(Di00, u0, Di01 * u1)); pst(L.P, nf, F_LU + 1, li, fmaf(Di01, u0, Di11 * u1));
+  const float ov[6] = {pn.x, pn.y, pn.z, pf.x, pf.y, pf.z};
+  xstore<XL>(L, F_LPA, i, ov);
 }
 
 // ---- lambda solve, down pass: back substitution; the field is the virtual velocity nu --
-__device__ void node_lam_down(const DevModel& M, int i) {
-  const int par = at(M.ntopo, (uint32_t)i).x;
-  const V3 W0a = ald3(M, F_WM, i), W0l = ald3(M, F_WM + 3, i), W1a = ald3(M, F_WM + 6, i), W1l = ald3(M, F_WM + 9, i);
-  const float du0 = aldf(M, F_LU, i), du1 = aldf(M, F_LU + 1, i);
-  const V3 a0 = ald3(M, F_A0, i), a1 = ald3(M, F_A1, i), lz = M.geo[i].x * ald3(M, F_Z, i);
+struct InLD {
+  int par;
+  float l, du0, du1;
+  V3 z, a0, a1, W0a, W0l, W1a, W1l;
+};
+__device__ __forceinline__ InLD load_ld(const DevModel& M, const Lvl& L, int i) {
+  const int nf = M.scr_nf, li = i - L.i0;
+  const float* P = L.P;
+  InLD r;
+  r.par = at(M.par, (uint32_t)i);
+  r.l = at(M.geo, (uint32_t)i).x;
+  r.z = pld3(P, nf, F_Z, li);
+  r.W0a = pld3(P, nf, F_WM, li); r.W0l = pld3(P, nf, F_WM + 3, li);
+  r.W1a = pld3(P, nf, F_WM + 6, li); r.W1l = pld3(P, nf, F_WM + 9, li);
+  r.du0 = pld(P, nf, F_LU, li); r.du1 = pld(P, nf, F_LU + 1, li);
+  r.a0 = pld3(P, nf, F_A0, li);
+  r.a1 = pld3(P, nf, F_A1, li);
+  return r;
+}
+template <bool XL>
+__device__ __forceinline__ void node_lam_down(const DevModel& M, const Lvl& L, int i, const InLD& in) {
+  const int nf = M.scr_nf, li = i - L.i0;
+  const V3 W0a = in.W0a, W0l = in.W0l, W1a = in.W1a, W1l = in.W1l;
+  const float du0 = in.du0, du1 = in.du1;
+  const V3 a0 = in.a0, a1 = in.a1, lz = in.l * in.z;
   V3 aa = v3(0, 0, 0), al = v3(0, 0, 0);
-  if (par >= 0) { aa = ald3(M, F_LA, par); al = ald3(M, F_LA + 3, par); }
+  if (in.par >= 0) {
+    float pv[6];
+    xload<XL>(L, F_LA, in.par, pv);
+    aa = v3(pv[0], pv[1], pv[2]);
+    al = v3(pv[3], pv[4], pv[5]);
+  }
   const float l0 = du0 - (dot(W0a, aa) + dot(W0l, al));
   const float l1 = du1 - (dot(W1a, aa) + dot(W1l, al));
   aa = fma3(l0, a0, fma3(l1, a1, aa));
-  asto3(M, F_NU, i, aa); asto3(M, F_NU + 3, i, al);
-  asto(M, F_LAM, i, l0); asto(M, F_LAM + 1, i, l1);
-  asto3(M, F_LA, i, aa); asto3(M, F_LA + 3, i, al + cross(aa, lz));
+  float* P = L.P;
+  pst3(P, nf, F_NU, li, aa); pst3(P, nf, F_NU + 3, li, al);
+  pst(P, nf, F_LAM, li, l0); pst(P, nf, F_LAM + 1, li, l1);
+  const V3 at_l = al + cross(aa, lz);
+  const float ov[6] = {aa.x, aa.y, aa.z, at_l.x, at_l.y, at_l.z};
+  xstore<XL>(L, F_LA, i, ov);
 }
 
 // ---- reverse pass (leaf -> root) ---------------------------------------------------------
-__device__ void node_reverse(const DevModel& M, const DevState& W, const RecView& R0, const DevInputs& I,
-                             const DevAdj& X, int i, int64_t n, int s_call) {
-  const int4 topo = at(M.ntopo, (uint32_t)i);
-  const bool skip = (((int)aldf(M, F_FLG, i)) & 1) != 0;  // frozen env: the step is the identity
-  const float h = M.h;
-  const int par = topo.x;
-  // forward quantities of this node
-  V3 c0, c1, c2;
-  c0 = v3(aldf(M, F_SR + 0, i), aldf(M, F_SR + 3, i), aldf(M, F_SR + 6, i));
-  c1 = v3(aldf(M, F_SR + 1, i), aldf(M, F_SR + 4, i), aldf(M, F_SR + 7, i));
-  c2 = v3(aldf(M, F_SR + 2, i), aldf(M, F_SR + 5, i), aldf(M, F_SR + 8, i));
-  const V3 a0 = ald3(M, F_A0, i), a1 = c1, z = c2;
-  const float4 g4 = M.geo[i];
-  const V3 lz = g4.x * z;
-  const V3 om = ald3(M, F_W, i);
-  const V3 v = par >= 0 ? ald3(M, F_VT, par) : v3(0, 0, 0);
-  const V3 Aa = ald3(M, F_SA, i), Al = ald3(M, F_SA + 3, i);
-  const V3 Pa = ald3(M, F_SAVP, i), Pl = ald3(M, F_SAVP + 3, i);
-  const float qdd0 = aldf(M, F_SQDD, i), qdd1 = aldf(M, F_SQDD + 1, i);
-  const float l0 = aldf(M, F_LAM, i), l1 = aldf(M, F_LAM + 1, i);
-  const V3 na = ald3(M, F_NU, i), nl = ald3(M, F_NU + 3, i);
-  // transmitted force f = I^A A + p^A (before the pivot update)
-  Sym3 IA{aldf(M, F_SIA + 0, i), aldf(M, F_SIA + 1, i), aldf(M, F_SIA + 2, i), aldf(M, F_SIA + 3, i),
-          aldf(M, F_SIA + 4, i), aldf(M, F_SIA + 5, i)};
+struct InRV {
+  int par, cb, ce, a_beg, a_end;
+  uint32_t hk0, hk1;
+  float flg, snp, kp, kd, qdd0, qdd1, l0, l1;
+  uint8_t brk;
+  float4 g4;
+  Mat3 R;  // columns c0 c1 c2
+  Sym3 IA, IM;
   Mat3 IB;
-  for (int k = 0; k < 9; ++k) IB.m[k] = aldf(M, F_SIA + 6 + k, i);
-  Sym3 IM{aldf(M, F_SIA + 15, i), aldf(M, F_SIA + 16, i), aldf(M, F_SIA + 17, i), aldf(M, F_SIA + 18, i),
-          aldf(M, F_SIA + 19, i), aldf(M, F_SIA + 20, i)};
-  const V3 fn = mul(IA, Aa) + mul(IB, Al) + ald3(M, F_SPA, i);
-  const V3 ff = mulT(IB, Aa) + mul(IM, Al) + ald3(M, F_SPA + 3, i);
-  const float2 q = R0.q(i), qd = R0.qd(i);
+  V3 a0, om, v, Aa, Al, Pa, Pl, na, nl, spn, spf;
+  float2 q, qd, qbn, qdbn, gk;
+};
+__device__ __forceinline__ InRV load_rv(const DevModel& M, const DevState& W, const RecView& R0, const DevInputs& I,
+                                        const DevAdj& X, const Lvl& L, int i) {
+  const int nf = M.scr_nf, li = i - L.i0;
+  const float* P = L.P;
+  const int4 topo = at(M.ntopo, (uint32_t)i);
+  InRV r;
+  r.par = topo.x;
+  r.cb = topo.y;
+  r.ce = topo.y + (topo.z & 0xFFFF);
+  r.a_beg = at(M.apple_beg, (uint32_t)i);
+  r.a_end = at(M.apple_beg, (uint32_t)i + 1u);
+  const uint64_t hk = at(M.hkey, (uint32_t)i);
+  r.hk0 = (uint32_t)hk;
+  r.hk1 = (uint32_t)(hk >> 32);
+  r.flg = pld(P, nf, F_FLG, li);
+  r.snp = pld(P, nf, F_SNAP, li);
+  for (int k = 0; k < 9; ++k) r.R.m[k] = pld(P, nf, F_SR + k, li);
+  r.a0 = pld3(P, nf, F_A0, li);
+  r.g4 = at(M.geo, (uint32_t)i);
+  r.om = pld3(P, nf, F_W, li);
+  // the parent's tip velocity comes from this step's forward scratch, not from a
+  // publication of this pass
+  r.v = r.par >= 0 ? pld3(P, nf, F_VT, r.par - L.i0) : v3(0, 0, 0);
+  r.Aa = pld3(P, nf, F_SA, li); r.Al = pld3(P, nf, F_SA + 3, li);
+  r.Pa = pld3(P, nf, F_SAVP, li); r.Pl = pld3(P, nf, F_SAVP + 3, li);
+  r.qdd0 = pld(P, nf, F_SQDD, li); r.qdd1 = pld(P, nf, F_SQDD + 1, li);
+  r.l0 = pld(P, nf, F_LAM, li); r.l1 = pld(P, nf, F_LAM + 1, li);
+  r.na = pld3(P, nf, F_NU, li); r.nl = pld3(P, nf, F_NU + 3, li);
+  r.IA = Sym3{pld(P, nf, F_SIA + 0, li), pld(P, nf, F_SIA + 1, li), pld(P, nf, F_SIA + 2, li),
+              pld(P, nf, F_SIA + 3, li), pld(P, nf, F_SIA + 4, li), pld(P, nf, F_SIA + 5, li)};
+  for (int k = 0; k < 9; ++k) r.IB.m[k] = pld(P, nf, F_SIA + 6 + k, li);
+  r.IM = Sym3{pld(P, nf, F_SIA + 15, li), pld(P, nf, F_SIA + 16, li), pld(P, nf, F_SIA + 17, li),
+              pld(P, nf, F_SIA + 18, li), pld(P, nf, F_SIA + 19, li), pld(P, nf, F_SIA + 20, li)};
+  r.spn = pld3(P, nf, F_SPA, li);
+  r.spf = pld3(P, nf, F_SPA + 3, li);
+  r.q = R0.q(i);
+  r.qd = R0.qd(i);
+  r.brk = at(W.seg_evt, (uint32_t)i);
+  r.kp = at(I.kp, (uint32_t)i);
+  r.kd = at(I.kd, (uint32_t)i);
+  r.qbn = at(X.q, (uint32_t)i);
+  r.qdbn = at(X.qd, (uint32_t)i);
+  r.gk = make_float2(at(X.gkp, (uint32_t)i), at(X.gkd, (uint32_t)i));
+  return r;
+}
+
+template <bool XL>
+__device__ __forceinline__ void node_reverse(const DevModel& M, const DevState& W, const RecView& R0,
+                                             const DevInputs& I, const DevAdj& X, const Lvl& L, int i,
+                                             const InRV& in, int64_t n, int s_call) {
+  const bool skip = (((int)in.flg) & 1) != 0;  // frozen env: the step is the identity
+  const float h = M.h;
+  // forward quantities of this node
+  const V3 c0 = v3(in.R.m[0], in.R.m[3], in.R.m[6]);
+  const V3 c1 = v3(in.R.m[1], in.R.m[4], in.R.m[7]);
+  const V3 c2 = v3(in.R.m[2], in.R.m[5], in.R.m[8]);
+  const V3 a0 = in.a0, a1 = c1, z = c2;
+  const float4 g4 = in.g4;
+  const V3 lz = g4.x * z;
+  const V3 om = in.om;
+  const V3 v = in.v;
+  const V3 Aa = in.Aa, Al = in.Al;
+  const V3 Pa = in.Pa, Pl = in.Pl;
+  const float qdd0 = in.qdd0, qdd1 = in.qdd1;
+  const float l0 = in.l0, l1 = in.l1;
+  const V3 na = in.na, nl = in.nl;
+  // transmitted force f = I^A A + p^A (before the pivot update)
+  const Sym3 IA = in.IA, IM = in.IM;
+  const Mat3 IB = in.IB;
+  const V3 fn = mul(IA, Aa) + mul(IB, Al) + in.spn;
+  const V3 ff = mulT(IB, Aa) + mul(IM, Al) + in.spf;
+  const float2 q = in.q, qd = in.qd;
   const V3 u = fma3(qd.x, a0, qd.y * a1);
   const float l = g4.x, m = g4.y, Jt = g4.z, Iax = g4.w, dJ = Iax - Jt;
   const V3 ho = (0.5f * m * l) * z;
   const Sym3 Jo{fmaf(dJ, z.x * z.x, Jt), fmaf(dJ, z.y * z.y, Jt), fmaf(dJ, z.z * z.z, Jt), dJ * z.x * z.y, dJ * z.x * z.z,
                 dJ * z.y * z.z};
-  const uint8_t brk = W.seg_evt[i];
-  const float kp = I.kp[i], kd = I.kd[i];
+  const uint8_t brk = in.brk;
+  const float kp = in.kp, kd = in.kd;
   const float kpe = brk ? 0.f : kp, kde = brk ? 0.f : kd;
 
   // accumulators
@@ -127,16 +243,17 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   float qdb0 = 0.f, qdb1 = 0.f;
   // ---- gather the children ----
   V3 vtb = v3(0, 0, 0), Atba = v3(0, 0, 0), Atbl = v3(0, 0, 0), Avtba = v3(0, 0, 0), Avtbl = v3(0, 0, 0), Fch = v3(0, 0, 0);
-  const int cb = topo.y, ce = cb + (topo.z & 0xFFFF);
-  for (int c = cb; c < ce; ++c) {
-    tau = tau + ald3(M, F_RB + 0, c);
-    omb = omb + ald3(M, F_RB + 3, c);
-    vtb = vtb + ald3(M, F_RB + 6, c);
-    Atba = Atba + ald3(M, F_RB + 9, c);
-    Atbl = Atbl + ald3(M, F_RB + 12, c);
-    Avtba = Avtba + ald3(M, F_RB + 15, c);
-    Avtbl = Avtbl + ald3(M, F_RB + 18, c);
-    Fch = Fch + ald3(M, F_RB + 21, c);
+  for (int c = in.cb; c < in.ce; ++c) {
+    float cv[24];
+    xload<XL>(L, F_RB, c, cv);
+    tau = tau + v3(cv[0], cv[1], cv[2]);
+    omb = omb + v3(cv[3], cv[4], cv[5]);
+    vtb = vtb + v3(cv[6], cv[7], cv[8]);
+    Atba = Atba + v3(cv[9], cv[10], cv[11]);
+    Atbl = Atbl + v3(cv[12], cv[13], cv[14]);
+    Avtba = Avtba + v3(cv[15], cv[16], cv[17]);
+    Avtbl = Avtbl + v3(cv[18], cv[19], cv[20]);
+    Fch = Fch + v3(cv[21], cv[22], cv[23]);
   }
   // tip publications: At = (A_ang, A_lin + A_ang x lz), same for Avp; vt = v + om x lz
   Aba = Aba + Atba + cross(lz, Atbl);
@@ -177,8 +294,9 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   // applied force: moment arm (l/2) z
   {
     V3 F, T;
-    const bool snp = (((int)aldf(M, F_SNAP, i)) & 1) != 0;
-    if (applied_force(M, I, i, splitmix64((uint64_t)n), s_call, m, snp, M.hkey[i], F, T)) zb = zb - (0.5f * l) * cross(F, na);
+    const bool snp = (((int)in.snp) & 1) != 0;
+    const uint64_t hkey = (uint64_t)in.hk0 | ((uint64_t)in.hk1 << 32);
+    if (applied_force(M, I, i, splitmix64((uint64_t)n), s_call, m, snp, hkey, F, T)) zb = zb - (0.5f * l) * cross(F, na);
   }
   zb = fma3(0.5f * m * l, hb, zb);
 
@@ -187,7 +305,7 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   const V3 gv = v3(M.gx, M.gy, M.gz);
   const V3 dAa = Aa - Pa, dAl = Al - Pl;
   float* gF = X.gF ? X.gF + (int64_t)s_call * 3 * NA : nullptr;
-  for (int a = M.apple_beg[i]; a < M.apple_beg[i + 1]; ++a) {
+  for (int a = in.a_beg; a < in.a_end; ++a) {
     const float4 hm = M.ahang[a];
     const float4 ap = M.apar[a];
     const float ma = hm.w, cs = ap.y, fmax = ap.z;
@@ -280,8 +398,8 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   // ---- springs, dampers, implicit diagonal; parameter gradients ----
   const float h2 = h * h;
   if (!brk && !skip) {
-    X.gkp[i] -= l0 * (h2 * qdd0 + q.x + h * qd.x) + l1 * (h2 * qdd1 + q.y + h * qd.y);
-    X.gkd[i] -= l0 * (h * qdd0 + qd.x) + l1 * (h * qdd1 + qd.y);
+    at(X.gkp, (uint32_t)i) = in.gk.x - (l0 * (h2 * qdd0 + q.x + h * qd.x) + l1 * (h2 * qdd1 + q.y + h * qd.y));
+    at(X.gkd, (uint32_t)i) = in.gk.y - (l0 * (h * qdd0 + qd.x) + l1 * (h * qdd1 + qd.y));
   }
   qb0 = fmaf(kpe, l0, qb0);
   qb1 = fmaf(kpe, l1, qb1);
@@ -289,7 +407,7 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   qdb1 = fmaf(h * kpe + kde, l1, qdb1);
 
   // ---- state adjoint before the step ----
-  const float2 qbn = X.q[i], qdbn = X.qd[i];
+  const float2 qbn = in.qbn, qdbn = in.qdbn;
   const float qdp0 = fmaf(h, qbn.x, qdbn.x), qdp1 = fmaf(h, qbn.y, qdbn.y);
   if (!skip) {
     X.q[i] = make_float2(qbn.x - qb0, qbn.y - qb1);
@@ -297,38 +415,125 @@ __device__ void node_reverse(const DevModel& M, const DevState& W, const RecView
   }
 
   // ---- publish for the parent ----
-  asto3(M, F_RB + 0, i, tau_par);
-  asto3(M, F_RB + 3, i, omb);
-  asto3(M, F_RB + 6, i, vb);
-  asto3(M, F_RB + 9, i, Aba);
-  asto3(M, F_RB + 12, i, Abl);
-  asto3(M, F_RB + 15, i, Pba);
-  asto3(M, F_RB + 18, i, Pbl);
-  asto3(M, F_RB + 21, i, ff);
+  const float ov[24] = {tau_par.x, tau_par.y, tau_par.z, omb.x, omb.y, omb.z, vb.x, vb.y, vb.z,
+                        Aba.x, Aba.y, Aba.z, Abl.x, Abl.y, Abl.z, Pba.x, Pba.y, Pba.z, Pbl.x, Pbl.y, Pbl.z,
+                        ff.x, ff.y, ff.z};
+  xstore<XL>(L, F_RB, i, ov);
 }
 
+// Global exchange (levels wider than the workgroup's exchange buffer): loads then
+// arithmetic, any number of nodes per thread and level.
+template <int NT>
+__device__ __forceinline__ void adjoint_pack_global(const DevModel& M, const DevState& W, const RecView& R0,
+                                                    const DevInputs& I, const DevAdj& X, Lvl& L, int lb, int le,
+                                                    int64_t n, int s_call) {
+  const int t = (int)threadIdx.x;
+  for (int lv = le - 1; lv >= lb; --lv) {
+    L.a = M.lvl_off[lv];
+    L.nbr = M.lvl_off[lv + 1];
+    for (int i = L.a + t; i < L.nbr; i += NT) node_lam_up<false>(M, L, i, load_lu(M, X, L, i));
+    __syncthreads();
+  }
+  for (int lv = lb; lv < le; ++lv) {
+    L.a = M.lvl_off[lv];
+    L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
+    const int e = M.lvl_off[lv + 1];
+    for (int i = L.a + t; i < e; i += NT) node_lam_down<false>(M, L, i, load_ld(M, L, i));
+    __syncthreads();
+  }
+  for (int lv = le - 1; lv >= lb; --lv) {
+    L.a = M.lvl_off[lv];
+    L.nbr = M.lvl_off[lv + 1];
+    for (int i = L.a + t; i < L.nbr; i += NT)
+      node_reverse<false>(M, W, R0, I, X, L, i, load_rv(M, W, R0, I, X, L, i), n, s_call);
+    __syncthreads();
+  }
+}
+
+// LDS exchange: at most one node per thread and level; the next level's loads are issued
+// before the current level's arithmetic (they read this step's forward scratch, the
+// adjoint state and data this thread wrote in an earlier pass).
+template <int NT>
+__device__ __forceinline__ void adjoint_pack_lds(const DevModel& M, const DevState& W, const RecView& R0,
+                                                 const DevInputs& I, const DevAdj& X, Lvl& L, int lb, int le,
+                                                 int64_t n, int s_call) {
+  const int t = (int)threadIdx.x;
+  {
+    int i = M.lvl_off[le - 1] + t;
+    bool has = i < M.lvl_off[le];
+    InLU cur{};
+    if (has) cur = load_lu(M, X, L, i);
+    for (int lv = le - 1; lv >= lb; --lv) {
+      L.a = M.lvl_off[lv];
+      L.nbr = M.lvl_off[lv + 1];
+      L.b = (lv - lb) & 1;
+      const int in_ = lv > lb ? M.lvl_off[lv - 1] + t : 0;
+      const bool hn = lv > lb && in_ < M.lvl_off[lv];
+      InLU nxt{};
+      if (hn) nxt = load_lu(M, X, L, in_);
+      if (has) node_lam_up<true>(M, L, i, cur);
+      if (lv > lb) lds_barrier();
+      i = in_; has = hn; cur = nxt;
+    }
+  }
+  __syncthreads();
+  {
+    int i = M.lvl_off[lb] + t;
+    bool has = i < M.lvl_off[lb + 1];
+    InLD cur{};
+    if (has) cur = load_ld(M, L, i);
+    for (int lv = lb; lv < le; ++lv) {
+      L.a = M.lvl_off[lv];
+      L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
+      L.b = (lv - lb) & 1;
+      const int in_ = M.lvl_off[lv + 1] + t;
+      const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
+      InLD nxt{};
+      if (hn) nxt = load_ld(M, L, in_);
+      if (has) node_lam_down<true>(M, L, i, cur);
+      if (lv + 1 < le) lds_barrier();
+      i = in_; has = hn; cur = nxt;
+    }
+  }
+  __syncthreads();
+  {
+    int i = M.lvl_off[le - 1] + t;
+    bool has = i < M.lvl_off[le];
+    InRV cur{};
+    if (has) cur = load_rv(M, W, R0, I, X, L, i);
+    for (int lv = le - 1; lv >= lb; --lv) {
+      L.a = M.lvl_off[lv];
+      L.nbr = M.lvl_off[lv + 1];
+      L.b = (lv - lb) & 1;
+      const int in_ = lv > lb ? M.lvl_off[lv - 1] + t : 0;
+      const bool hn = lv > lb && in_ < M.lvl_off[lv];
+      InRV nxt{};
+      if (hn) nxt = load_rv(M, W, R0, I, X, L, in_);
+      if (has) node_reverse<true>(M, W, R0, I, X, L, i, cur, n, s_call);
+      if (lv > lb) lds_barrier();
+      i = in_; has = hn; cur = nxt;
+    }
+  }
+}
+
+// one workgroup per pack; dynamic LDS: the level exchange of the step kernels
 template <int NT>
 __global__ __launch_bounds__(NT) void k_adjoint_packs(DevModel M, DevState W, const float* rec, DevInputs I, DevAdj X,
                                                       int s_call) {
+  HIP_DYNAMIC_SHARED(float4, xlds4)
   const int pk = blockIdx.x;
   const int lb = ldc(M.pack_lvl, pk), le = ldc(M.pack_lvl, pk + 1) - 1;
   const int64_t n = *W.step - 1;  // the forward step just taken on W
   const RecView R0{rec, M.n_seg, M.n_apple};
-  for (int lv = le - 1; lv >= lb; --lv) {
-    const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
-    for (int i = a + (int)threadIdx.x; i < b; i += NT) node_lam_up(M, X, i);
-    __syncthreads();
-  }
-  for (int lv = lb; lv < le; ++lv) {
-    const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
-    for (int i = a + (int)threadIdx.x; i < b; i += NT) node_lam_down(M, i);
-    __syncthreads();
-  }
-  for (int lv = le - 1; lv >= lb; --lv) {
-    const int a = M.lvl_off[lv], b = M.lvl_off[lv + 1];
-    for (int i = a + (int)threadIdx.x; i < b; i += NT) node_reverse(M, W, R0, I, X, i, n, s_call);
-    __syncthreads();
-  }
+  Lvl L;
+  L.i0 = ldc(M.pack_node, pk) & ~63;
+  L.nf = M.scr_nf;
+  L.P = M.scr + (size_t)(L.i0 >> 6) * (size_t)L.nf * 64u;
+  L.X = reinterpret_cast<float*>(xlds4);
+  L.cap = M.lds_cap;
+  L.b = 0;
+  if (M.lds_cap > 0 && ldc(M.pack_lds, pk)) adjoint_pack_lds<NT>(M, W, R0, I, X, L, lb, le, n, s_call);
+  else adjoint_pack_global<NT>(M, W, R0, I, X, L, lb, le, n, s_call);
 }
 
 // ---- tip positions: p_b + R_b (0, 0, l_b) -----------------------------------------------

@@ -615,6 +615,12 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     default: per_cu = lds_setup(k_step_packs<512>, k_step_persistent<512>, 512, lb); break;
   }
   M->persist_blocks = std::max(1, std::min<int>(M->n_pack, std::max(1, per_cu) * std::max(1, M->n_cu)));
+  if (tun.adjoint_ckpt_max > 0 && lb > 65536) {
+    const void* ka = tun.threads == 64 ? (const void*)k_adjoint_packs<64>
+                     : tun.threads == 128 ? (const void*)k_adjoint_packs<128>
+                     : tun.threads == 256 ? (const void*)k_adjoint_packs<256> : (const void*)k_adjoint_packs<512>;
+    (void)hipFuncSetAttribute(ka, hipFuncAttributeMaxDynamicSharedMemorySize, lb);
+  }
   if (tun.adjoint_ckpt_max > 0) {
     const int64_t words = orchard_ckpt_words(M);
     M->adj_kmax = tun.adjoint_ckpt_max;
@@ -856,6 +862,7 @@ orchard_status_t orchard_step_backward(orchard_model_t m, const float* ckpt, int
   hipStream_t hs = (hipStream_t)stream;
   const int64_t words = orchard_ckpt_words(m);
   const int NT = m->tun.threads;
+  const unsigned lb = (unsigned)m->lds_bytes;  // the adjoint kernel shares the step kernels' exchange layout
   const int nseg = (n_steps + ckpt_every - 1) / ckpt_every;
   const DevState& W = m->ws;
   auto rep = [&](int j) { return j == 0 ? m->scr : (float*)((char*)m->reps + (size_t)(j - 1) * m->scr_bytes); };
@@ -880,10 +887,10 @@ orchard_status_t orchard_step_backward(orchard_model_t m, const float* ckpt, int
       const float* rec = (const float*)rec_at(j);
       const dim3 g(m->n_pack);
       switch (NT) {
-        case 64: hipLaunchKernelGGL(k_adjoint_packs<64>, g, dim3(64), 0, hs, dm, W, rec, di, X, n0 + j); break;
-        case 128: hipLaunchKernelGGL(k_adjoint_packs<128>, g, dim3(128), 0, hs, dm, W, rec, di, X, n0 + j); break;
-        case 256: hipLaunchKernelGGL(k_adjoint_packs<256>, g, dim3(256), 0, hs, dm, W, rec, di, X, n0 + j); break;
-        default: hipLaunchKernelGGL(k_adjoint_packs<512>, g, dim3(512), 0, hs, dm, W, rec, di, X, n0 + j); break;
+        case 64: hipLaunchKernelGGL(k_adjoint_packs<64>, g, dim3(64), lb, hs, dm, W, rec, di, X, n0 + j); break;
+        case 128: hipLaunchKernelGGL(k_adjoint_packs<128>, g, dim3(128), lb, hs, dm, W, rec, di, X, n0 + j); break;
+        case 256: hipLaunchKernelGGL(k_adjoint_packs<256>, g, dim3(256), lb, hs, dm, W, rec, di, X, n0 + j); break;
+        default: hipLaunchKernelGGL(k_adjoint_packs<512>, g, dim3(512), lb, hs, dm, W, rec, di, X, n0 + j); break;
       }
       HIPCHK(hipGetLastError());
     }

@@ -276,4 +276,75 @@ __device__ __forceinline__ bool applied_force(const DevModel& M, const DevInputs
   return any;
 }
 
+// ---- per-pack scratch and the level exchange, shared by the step and adjoint kernels ----
+// Scratch of one pack: P points at the pack's first 64-node block and li = node - i0
+// (i0 = that block's first node), so offsets stay 32-bit; the layout is the global one.
+// A node's fields share one address (base + its 32-bit lane offset); field f adds the
+// constant f*64, which the loads and stores carry as an immediate offset.
+__device__ __forceinline__ uint32_t slane(int nf, int li) {
+  return (uint32_t)(li >> 6) * (uint32_t)nf * 64u + (uint32_t)(li & 63);
+}
+__device__ __forceinline__ float pld(const float* P, int nf, int f, int li) { return (&at(P, slane(nf, li)))[f * 64]; }
+__device__ __forceinline__ void pst(float* P, int nf, int f, int li, float v) { (&at(P, slane(nf, li)))[f * 64] = v; }
+__device__ __forceinline__ V3 pld3(const float* P, int nf, int f, int li) {
+  return v3(pld(P, nf, f, li), pld(P, nf, f + 1, li), pld(P, nf, f + 2, li));
+}
+__device__ __forceinline__ void pst3(float* P, int nf, int f, int li, V3 v) {
+  pst(P, nf, f, li, v.x); pst(P, nf, f + 1, li, v.y); pst(P, nf, f + 2, li, v.z);
+}
+
+// Where a pass stands: the pack's scratch, its exchange buffer and the current level.
+struct Lvl {
+  float* P;    // pack scratch
+  float* X;    // LDS exchange buffer (LDS path)
+  int nf;      // scratch fields per node
+  int cap;     // exchange slots per level
+  int i0;      // first node of the pack's first scratch block
+  int a;       // first node of this level
+  int nbr;     // first node of the neighbouring level that is read (parent or child level)
+  int b;       // this level's exchange buffer (level parity)
+};
+
+// a whole publication: NF fields from f0 of node j on the neighbouring level (load) or of
+// node i on this level (store); on the LDS path a slot moves as 128-bit accesses (the
+// last one also covers padding of the slot, which nobody reads)
+template <bool XL, int NF>
+__device__ __forceinline__ void xload(const Lvl& L, int f0, int j, float (&v)[NF]) {
+  if constexpr (XL) {
+    const float4* s = reinterpret_cast<const float4*>(L.X + (uint32_t)(((L.b ^ 1) * L.cap + (j - L.nbr)) * X_STRIDE));
+#pragma unroll
+    for (int k = 0; k < (NF + 3) / 4; ++k) {
+      const float4 t = s[k];
+      v[4 * k] = t.x;
+      if (4 * k + 1 < NF) v[4 * k + 1] = t.y;
+      if (4 * k + 2 < NF) v[4 * k + 2] = t.z;
+      if (4 * k + 3 < NF) v[4 * k + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) v[k] = pld(L.P, L.nf, f0 + k, j - L.i0);
+  }
+}
+template <bool XL, int NF>
+__device__ __forceinline__ void xstore(const Lvl& L, int f0, int i, const float (&v)[NF]) {
+  if constexpr (XL) {
+    float4* d = reinterpret_cast<float4*>(L.X + (uint32_t)((L.b * L.cap + (i - L.a)) * X_STRIDE));
+#pragma unroll
+    for (int k = 0; k < (NF + 3) / 4; ++k)
+      d[k] = make_float4(v[4 * k], 4 * k + 1 < NF ? v[4 * k + 1] : 0.f, 4 * k + 2 < NF ? v[4 * k + 2] : 0.f,
+                         4 * k + 3 < NF ? v[4 * k + 3] : 0.f);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) pst(L.P, L.nf, f0 + k, i - L.i0, v[k]);
+  }
+}
+
+// Between levels the LDS path needs only the LDS exchange to be complete (node-private
+// scratch is written and read back by the same thread); pass ends are full barriers.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 }  // namespace orchard
