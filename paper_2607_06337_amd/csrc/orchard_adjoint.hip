@@ -60,7 +60,7 @@ __device__ __forceinline__ InLU load_lu(const DevModel& M, const DevAdj& X, cons
   InLU r;
   r.cb = topo.y;
   r.ce = topo.y + (topo.z & 0xFFFF);
-  r.l = at(M.geo, (uint32_t)i).x;
+  r.l = at(M.len, (uint32_t)i);
   r.z = pld3(P, nf, F_Z, li);
   r.qb = at(X.q, (uint32_t)i);
   r.qdb = at(X.qd, (uint32_t)i);
@@ -109,7 +109,7 @@ __device__ __forceinline__ InLD load_ld(const DevModel& M, const Lvl& L, int i) 
   const float* P = L.P;
   InLD r;
   r.par = at(M.par, (uint32_t)i);
-  r.l = at(M.geo, (uint32_t)i).x;
+  r.l = at(M.len, (uint32_t)i);
   r.z = pld3(P, nf, F_Z, li);
   r.W0a = pld3(P, nf, F_WM, li); r.W0l = pld3(P, nf, F_WM + 3, li);
   r.W1a = pld3(P, nf, F_WM + 6, li); r.W1l = pld3(P, nf, F_WM + 9, li);
@@ -149,10 +149,9 @@ struct InRV {
   float flg, snp, kp, kd, qdd0, qdd1, l0, l1;
   uint8_t brk;
   float4 g4;
-  Mat3 R;  // columns c0 c1 c2
   Sym3 IA, IM;
   Mat3 IB;
-  V3 a0, om, v, Aa, Al, Pa, Pl, na, nl, spn, spf;
+  V3 a0, a1, z, om, v, Aa, Al, Pa, Pl, na, nl, spn, spf;
   float2 q, qd, qbn, qdbn, gk;
 };
 __device__ __forceinline__ InRV load_rv(const DevModel& M, const DevState& W, const RecView& R0, const DevInputs& I,
@@ -171,8 +170,9 @@ __device__ __forceinline__ InRV load_rv(const DevModel& M, const DevState& W, co
   r.hk1 = (uint32_t)(hk >> 32);
   r.flg = pld(P, nf, F_FLG, li);
   r.snp = pld(P, nf, F_SNAP, li);
-  for (int k = 0; k < 9; ++k) r.R.m[k] = pld(P, nf, F_SR + k, li);
   r.a0 = pld3(P, nf, F_A0, li);
+  r.a1 = pld3(P, nf, F_A1, li);
+  r.z = pld3(P, nf, F_Z, li);
   r.g4 = at(M.geo, (uint32_t)i);
   r.om = pld3(P, nf, F_W, li);
   // the parent's tip velocity comes from this step's forward scratch, not from a
@@ -207,11 +207,9 @@ __device__ __forceinline__ void node_reverse(const DevModel& M, const DevState& 
                                              const InRV& in, int64_t n, int s_call) {
   const bool skip = (((int)in.flg) & 1) != 0;  // frozen env: the step is the identity
   const float h = M.h;
-  // forward quantities of this node
-  const V3 c0 = v3(in.R.m[0], in.R.m[3], in.R.m[6]);
-  const V3 c1 = v3(in.R.m[1], in.R.m[4], in.R.m[7]);
-  const V3 c2 = v3(in.R.m[2], in.R.m[5], in.R.m[8]);
-  const V3 a0 = in.a0, a1 = c1, z = c2;
+  // forward quantities of this node; the body frame is (a1 x z, a1, z)
+  const V3 a0 = in.a0, a1 = in.a1, z = in.z;
+  const V3 c0 = cross(a1, z), c1 = a1, c2 = z;
   const float4 g4 = in.g4;
   const V3 lz = g4.x * z;
   const V3 om = in.om;

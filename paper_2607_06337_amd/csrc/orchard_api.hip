@@ -439,6 +439,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
 
   std::vector<int32_t> par_i(NS), child_i(NS), nchild_i(NS, 0), env_i(NS), orig_i(NS);
   std::vector<float4> rq(NS), geo(NS);
+  std::vector<float> seglen(NS);
   std::vector<float> mmax_f(NS), kp_f(NS), kd_f(NS);
   std::vector<int32_t> env_of_g(NS);
   for (int e = 0; e < B; ++e)
@@ -453,6 +454,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     rq[i] = make_float4((float)(q[0] / nq), (float)(q[1] / nq), (float)(q[2] / nq), (float)(q[3] / nq));
     geo[i] = make_float4((float)d->seg_length[g], (float)mass[g], (float)Jt[g], (float)Iax[g]);
+    seglen[i] = geo[i].x;
     mmax_f[i] = (float)mmax[g];
     kp_f[i] = (float)kp[g];
     kd_f[i] = (float)kd[g];
@@ -551,7 +553,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
          o_hr = ar.put(ahrest_h.data(), NA * 16), o_pd = ar.put(pack_lds.data(), pack_lds.size() * 4),
          o_nr = ar.put(nrec.data(), NS * sizeof(NodeRec)), o_ar2 = ar.put(arec.data(), NA * sizeof(AppleRec)),
          o_hk = ar.put(hkey.data(), NS * 8), o_pa = ar.put(pack_apl.data(), pack_apl.size() * 4),
-         o_nt = ar.put(ntopo.data(), NS * 16),
+         o_nt = ar.put(ntopo.data(), NS * 16), o_len = ar.put(seglen.data(), NS * 4),
          o_q = ar.put(&zero, 4 * 16);
   hipError_t he = hipMalloc(&M->arena, ar.off + 256);
   if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
@@ -586,6 +588,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.hkey = (const uint64_t*)(base + o_hk);
   dm.pack_apl = (const int32_t*)(base + o_pa);
   dm.ntopo = (const int4*)(base + o_nt);
+  dm.len = (const float*)(base + o_len);
   dm.scr_nf = scr_nf;
   dm.lds_cap = n_lds_packs > 0 ? tun.lds_width : 0;
   // dynamic LDS of the step kernels: the level exchange, reused by the apple phase

@@ -64,8 +64,8 @@ enum : int {
   N_PUB_MAX = 27,
   X_STRIDE = 28,     // LDS exchange floats per node slot (N_PUB_MAX rounded to 16 B)
   // ---- fields of the adjoint ----
-  // saved by the forward step in save mode
-  F_SR = 128,       // 9: body rotation, row major
+  // saved by the forward step in save mode (the body frame is rebuilt from F_A1 and F_Z)
+  F_SR = 128,       // 9: body rotation, row major (scratch of the tip-position kernels only)
   F_SAVP = 137,     // 6: velocity-product (+ base) acceleration at the joint point
   F_SIA = 143,      // 21: articulated inertia before the pivot update (A 6, B 9, M 6)
   F_SPA = 164,      // 6: articulated bias before the pivot update
@@ -118,6 +118,7 @@ struct DevModel {
   const int32_t* apple_beg;  // [n_seg+1] apples of node i: apple_beg[i] .. apple_beg[i+1]-1
   const float4* rq;          // rest quaternion (w, x, y, z)
   const float4* geo;         // (l, m, Jt about the joint, Ia)
+  const float* len;          // l alone, for the passes that need only the length
   const float* mmax;         // rupture moment
   // per apple (internal order)
   const float4* ahang;       // (hang x, y, z in the segment frame, mass)

@@ -167,9 +167,6 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
       pst3(P, nf, F_VT, li, v + cross(wi, lz));
       pst(P, nf, F_SNAP, li, (snp ? 1.f : 0.f) + (frozen ? 2.f : 0.f));
     }
-    pst(P, nf, F_SR + 0, li, c0.x); pst(P, nf, F_SR + 1, li, c1.x); pst(P, nf, F_SR + 2, li, c2.x);
-    pst(P, nf, F_SR + 3, li, c0.y); pst(P, nf, F_SR + 4, li, c1.y); pst(P, nf, F_SR + 5, li, c2.y);
-    pst(P, nf, F_SR + 6, li, c0.z); pst(P, nf, F_SR + 7, li, c1.z); pst(P, nf, F_SR + 8, li, c2.z);
     pst3(P, nf, F_SAVP, li, Ava); pst3(P, nf, F_SAVP + 3, li, Avl);
   }
 
@@ -573,8 +570,8 @@ __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const
   const int nf = M.scr_nf, li = i - L.i0;
   const float* P = L.P;
   In2 d;
-  d.par = at(M.ntopo, (uint32_t)i).x;
-  d.l = at(M.geo, (uint32_t)i).x;
+  d.par = at(M.par, (uint32_t)i);
+  d.l = at(M.len, (uint32_t)i);
   d.flg = pld(P, nf, F_FLG, li);
   d.ca = pld3(P, nf, F_C, li);
   d.cl = pld3(P, nf, F_C + 3, li);
