@@ -25,10 +25,11 @@ enum : int {
   // the state instead of being stored
   F_A0 = 25,        // 3: joint axis x (world)
   F_A1 = 28,        // 3: joint axis y (world)
-  F_C = 31,         // 6: velocity-product acceleration c (ang, lin)
-  F_P = 37,         // 6: bias force p (ang, lin) incl. applied forces and apple reactions
-  F_Z = 43,         // 3: body axis z (world)
-  F_FLG = 46,       // 1: 1 if the env is frozen at the start of the step, + 2 if the joint is broken
+  F_WV = 31,        // 6: angular velocity and joint-point velocity (the velocity-product
+                    //    acceleration and the bias are formed from them again)
+  F_Z = 37,         // 3: body axis z (world)
+  F_FLG = 40,       // 1: 1 if the env is frozen at the start of the step, + 2 if the joint is
+                    //    broken, + 4 if the segment is snapped
   // up-pass publication (27): articulated inertia and bias at the node's joint point
   F_IA = 60,        // 6: A (rotational block, sym)
   F_IB = 66,        // 9: B (coupling block, row major)
@@ -40,7 +41,7 @@ enum : int {
   F_DU = 99,        // 2: D^-1 u, u = tau - S^T p^A
   F_DI = 101,       // 3: D^-1 (00 01 11), stored only in save mode (the adjoint's solves)
   // node-private outputs of the down 1 and up passes, each a contiguous range of fields
-  N_OUT1 = 22,      // F_A0 .. F_FLG
+  N_OUT1 = 16,      // F_A0 .. F_FLG
   N_OUTU = 14,      // F_WM .. F_DU + 1
   N_FIELDS = 128,
   // Nodes that carry apples (a minority) keep their apple data in two dense arrays
@@ -200,7 +201,7 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
 }
 __device__ __forceinline__ V3 fma3(float s, V3 a, V3 b) { return V3{fmaf(s, a.x, b.x), fmaf(s, a.y, b.y), fmaf(s, a.z, b.z)}; }
 
-static_assert(F_A1 == F_A0 + 3 && F_C == F_A1 + 3 && F_P == F_C + 6 && F_Z == F_P + 6 && F_FLG == F_Z + 3 &&
+static_assert(F_A1 == F_A0 + 3 && F_WV == F_A1 + 3 && F_Z == F_WV + 6 && F_FLG == F_Z + 3 &&
               F_FLG + 1 - F_A0 == N_OUT1, "down 1 outputs are one field range");
 static_assert(F_DU == F_WM + 12 && F_DU + 2 - F_WM == N_OUTU, "up outputs are one field range");
 

@@ -39,6 +39,35 @@ __device__ __forceinline__ void own_inertia(float4 geo, V3 z, V3& ho, Sym3& Jo) 
             dJ * z.y * z.z};
 }
 
+// Velocity-product acceleration (ang, lin) at the joint point of a body with angular
+// velocity wi and joint-point velocity v, whose joint turns at rates qd about a0, a1.
+__device__ __forceinline__ void vel_product(V3 a0, V3 a1, float2 qd, V3 wi, V3 v, V3& cang, V3& clin) {
+  const V3 u = fma3(qd.x, a0, qd.y * a1);
+  cang = fma3(qd.x * qd.y, cross(a0, a1), cross(wi, u));
+  clin = cross(v, u);
+}
+
+// Bias wrench (ang, lin) of a segment's own body about its joint point: v x* (I v) minus
+// the applied body force (input and counter-based random, impulse-capped, none on a
+// snapped sub-tree) acting at the segment's midpoint.  Down 1 needs none of it; the up
+// pass forms it from the stored velocities.
+__device__ __forceinline__ void body_bias(const DevModel& M, const DevInputs& I, int i, uint64_t kstep, int s_call,
+                                          float4 geo, V3 z, V3 wi, V3 v, bool snp, uint64_t hkey, V3& pang, V3& plin) {
+  const float l = geo.x, m = geo.y;
+  V3 ho;
+  Sym3 Jo;
+  own_inertia(geo, z, ho, Jo);
+  const V3 K = mul(Jo, wi) + cross(ho, v);
+  const V3 Lm = m * v - cross(ho, wi);
+  pang = cross(wi, K) + cross(v, Lm);
+  plin = cross(wi, Lm);
+  V3 F, T;
+  if (applied_force(M, I, i, kstep, s_call, m, snp, hkey, F, T)) {
+    pang = pang - (T + cross(0.5f * (l * z), F));
+    plin = plin - F;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // down pass 1
 // ------------------------------------------------------------------------------------------
@@ -78,7 +107,7 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   uint8_t brk = in.brk;
   const uint8_t cnt0 = in.cnt;
   const int par = nr.topo.x;
-  const float l = nr.geo.x, m = nr.geo.y;
+  const float l = nr.geo.x;
 
   // ---- parent publication ----
   // The env's frozen flag (status bit 0 at the start of the step) is read by the root and
@@ -143,11 +172,10 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   const V3 a0 = J0, a1 = c1, z = c2;
 
   // ---- velocities and velocity-product acceleration (at the joint point) ----
-  const V3 u = fma3(qd.x, a0, qd.y * a1);       // relative angular velocity
-  const V3 wi = w + u;
-  const V3 v = vt;                              // joint point moves with the parent
-  const V3 cang = fma3(qd.x * qd.y, cross(a0, a1), cross(wi, u));
-  const V3 clin = cross(v, u);
+  const V3 wi = w + fma3(qd.x, a0, qd.y * a1);  // plus the relative angular velocity
+  const V3 v = vt;                               // joint point moves with the parent
+  V3 cang, clin;
+  vel_product(a0, a1, qd, wi, v, cang, clin);
   const V3 Ava = Aa + cang, Avl = Al + clin;
 
   // ---- publish for children (values at the tip point) ----
@@ -170,26 +198,6 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     pst3(P, nf, F_SAVP, li, Ava); pst3(P, nf, F_SAVP + 3, li, Avl);
   }
 
-  // ---- rigid body inertia about the joint point: axisymmetric capsule ----
-  V3 ho;
-  Sym3 Jo;
-  own_inertia(nr.geo, z, ho, Jo);
-  // bias force p = v x* (I v)
-  const V3 K = mul(Jo, wi) + cross(ho, v);
-  const V3 Lm = m * v - cross(ho, wi);
-  V3 pang = cross(wi, K) + cross(v, Lm);
-  V3 plin = cross(wi, Lm);
-
-  // ---- applied body force (input and counter-based random), impulse cap, snapped mask ----
-  {
-    V3 F, T;
-    const uint64_t hkey = (uint64_t)(uint32_t)nr.aux.x | ((uint64_t)(uint32_t)nr.aux.y << 32);
-    if (applied_force(M, I, i, kstep, s_call, m, snp, hkey, F, T)) {
-      pang = pang - (T + cross(0.5f * lz, F));
-      plin = plin - F;
-    }
-  }
-
   const bool live = !frozen;
   // apples are handled by the apple phase after this pass; keep what it needs
   if (nr.topo.z >> 16) {
@@ -210,9 +218,8 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     if (brk) { at(S.seg_evt, (uint32_t)i) = 1; at(S.evt_step, (uint32_t)i) = (int32_t)n; }
   }
   // node-private outputs (fields F_A0 .. F_FLG), stored by the caller
-  const float out[N_OUT1] = {a0.x, a0.y, a0.z, a1.x, a1.y, a1.z, cang.x, cang.y, cang.z, clin.x, clin.y, clin.z,
-                             pang.x, pang.y, pang.z, plin.x, plin.y, plin.z, z.x, z.y, z.z,
-                             (live ? 0.f : 1.f) + (brk ? 2.f : 0.f)};
+  const float out[N_OUT1] = {a0.x, a0.y, a0.z, a1.x, a1.y, a1.z, wi.x, wi.y, wi.z, v.x, v.y, v.z, z.x, z.y, z.z,
+                             (live ? 0.f : 1.f) + (brk ? 2.f : 0.f) + (snp ? 4.f : 0.f)};
   for (int k = 0; k < N_OUT1; ++k) o[k] = out[k];
 }
 
@@ -402,23 +409,20 @@ __device__ __forceinline__ TopoU topo_up(const DevModel& M, int i) {
   const int* w = reinterpret_cast<const int*>(&at(M.ntopo, (uint32_t)i));
   return TopoU{w[1], w[2], w[3]};
 }
-// up-pass inputs: the node's own data from down 1, its static record and state.  The
-// topology word is loaded a level earlier than the rest (the LDS path pipelines it), so
-// the loads of the apple sums can be limited to nodes that carry apples without waiting
-// on a load.
+// up-pass inputs: the node's own data from down 1, its static record and state
 struct InU {
   TopoU topo;
-  float4 geo, e0, e1, e2, e3;  // e: the apple sums of a node that carries apples
-  V3 z, pon, pof, a0, a1, ca, cl;
+  float4 geo;
+  V3 z, a0, a1, wi, v;
   float2 q, qd;
   float kp, kd, flg;
+  uint32_t hk0, hk1;  // random-wrench key
 };
-__device__ __forceinline__ InU loadU(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L, int i,
-                                     TopoU topo) {
+__device__ __forceinline__ InU loadU(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L, int i) {
   const int nf = M.scr_nf, li = i - L.i0;
   const float* P = L.P;
   InU u;
-  u.topo = topo;
+  u.topo = topo_up(M, i);
   u.geo = at(M.geo, (uint32_t)i);
   u.q = at(S.q, (uint32_t)i);
   u.qd = at(S.qd, (uint32_t)i);
@@ -426,35 +430,45 @@ __device__ __forceinline__ InU loadU(const DevModel& M, const DevState& S, const
   u.kd = at(I.kd, (uint32_t)i);
   u.z = pld3(P, nf, F_Z, li);
   u.flg = pld(P, nf, F_FLG, li);
-  u.pon = pld3(P, nf, F_P, li);
-  u.pof = pld3(P, nf, F_P + 3, li);
   u.a0 = pld3(P, nf, F_A0, li);
   u.a1 = pld3(P, nf, F_A1, li);
-  u.ca = pld3(P, nf, F_C, li);
-  u.cl = pld3(P, nf, F_C + 3, li);
-  u.e0 = u.e1 = u.e2 = u.e3 = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (topo.cnt >> 16) {
-    const float4* es = reinterpret_cast<const float4*>(M.aext + (size_t)topo.an * E_N);
-    u.e0 = es[0]; u.e1 = es[1]; u.e2 = es[2]; u.e3 = es[3];
-  }
+  u.wi = pld3(P, nf, F_WV, li);
+  u.v = pld3(P, nf, F_WV + 3, li);
+  const uint64_t hk = at(M.hkey, (uint32_t)i);
+  u.hk0 = (uint32_t)hk;
+  u.hk1 = (uint32_t)(hk >> 32);
   return u;
 }
 
 template <bool XL>
-__device__ __forceinline__ void node_up(const DevModel& M, const Lvl& L, int i, const InU& in, float (&o)[N_OUTU]) {
+__device__ __forceinline__ void node_up(const DevModel& M, const DevInputs& I, const Lvl& L, int i, const InU& in,
+                                        uint64_t kstep, int s_call, float (&o)[N_OUTU]) {
   const int nf = M.scr_nf, li = i - L.i0;
   const TopoU topo = in.topo;
-  const V3 a0 = in.a0, a1 = in.a1, ca = in.ca, cl = in.cl;
+  const V3 a0 = in.a0, a1 = in.a1;
   const V3 r = in.geo.x * in.z;  // l z, joint point -> tip
+  // the apple sums of a node that carries apples are loaded here rather than a level
+  // ahead (they would double in the prefetch registers); their first use comes after the
+  // bias and the children's gather
+  float4 e0 = make_float4(0.f, 0.f, 0.f, 0.f), e1 = e0, e2 = e0, e3 = e0;
+  if (topo.cnt >> 16) {
+    const float4* es = reinterpret_cast<const float4*>(M.aext + (size_t)topo.an * E_N);
+    e0 = es[0]; e1 = es[1]; e2 = es[2]; e3 = es[3];
+  }
+  // velocity-product acceleration and the own body's bias, formed from the velocities
+  V3 ca, cl, pang, plin;
+  vel_product(a0, a1, in.qd, in.wi, in.v, ca, cl);
+  const bool snp = (((int)in.flg) & 4) != 0;
+  body_bias(M, I, i, kstep, s_call, in.geo, in.z, in.wi, in.v, snp, (uint64_t)in.hk0 | ((uint64_t)in.hk1 << 32), pang,
+            plin);
   // own body plus the apples' virtual masses and reactions (zero without apples)
-  const float4 e0 = in.e0, e1 = in.e1, e2 = in.e2, e3 = in.e3;
   V3 ho;
   Sym3 Jo;
   own_inertia(in.geo, in.z, ho, Jo);
   const float mo = in.geo.y + e0.x;
   ho = ho + v3(e0.y, e0.z, e0.w);
   Jo.xx += e1.x; Jo.yy += e1.y; Jo.zz += e1.z; Jo.xy += e1.w; Jo.xz += e2.x; Jo.yz += e2.y;
-  const V3 pon = in.pon + v3(e2.z, e2.w, e3.x), pof = in.pof + v3(e3.y, e3.z, e3.w);
+  const V3 pon = pang + v3(e2.z, e2.w, e3.x), pof = plin + v3(e3.y, e3.z, e3.w);
   // spring / damper with the implicit diagonal; a broken joint has none
   const float h = M.h;
   const bool brk = (((int)in.flg) & 2) != 0;
@@ -563,7 +577,7 @@ __device__ __forceinline__ void node_up(const DevModel& M, const Lvl& L, int i, 
 struct In2 {
   int par;
   float flg, du0, du1, l;
-  V3 ca, cl, W0a, W0l, W1a, W1l, a0, a1, z;
+  V3 wi, v, W0a, W0l, W1a, W1l, a0, a1, z;
   float2 q, qd;
 };
 __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const Lvl& L, int i) {
@@ -573,8 +587,8 @@ __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const
   d.par = at(M.par, (uint32_t)i);
   d.l = at(M.len, (uint32_t)i);
   d.flg = pld(P, nf, F_FLG, li);
-  d.ca = pld3(P, nf, F_C, li);
-  d.cl = pld3(P, nf, F_C + 3, li);
+  d.wi = pld3(P, nf, F_WV, li);
+  d.v = pld3(P, nf, F_WV + 3, li);
   d.W0a = pld3(P, nf, F_WM, li);
   d.W0l = pld3(P, nf, F_WM + 3, li);
   d.W1a = pld3(P, nf, F_WM + 6, li);
@@ -594,9 +608,11 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
   const int nf = M.scr_nf, li = i - L.i0;
   const int par = in.par;
   const bool live = (((int)in.flg) & 1) == 0;
-  const V3 ca = in.ca, cl = in.cl, W0a = in.W0a, W0l = in.W0l, W1a = in.W1a, W1l = in.W1l;
+  const V3 W0a = in.W0a, W0l = in.W0l, W1a = in.W1a, W1l = in.W1l;
   const V3 a0 = in.a0, a1 = in.a1, lz = in.l * in.z;
   float2 q = in.q, qd = in.qd;
+  V3 ca, cl;
+  vel_product(a0, a1, qd, in.wi, in.v, ca, cl);
   V3 Aa, Al;
   if (par < 0) { Aa = v3(0, 0, 0); Al = v3(-M.gx, -M.gy, -M.gz); }
   else {
@@ -673,7 +689,7 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
       L.nbr = e;
       for (int i = L.a + (int)threadIdx.x; i < e; i += NT) {
         float o[N_OUTU];
-        node_up<false>(M, L, i, loadU(M, S, I, L, i, topo_up(M, i)), o);
+        node_up<false>(M, I, L, i, loadU(M, S, I, L, i), kstep, call_step0 + st, o);
         put_fields<F_WM>(&at(L.P, slane(L.nf, i - L.i0)), o);
       }
       __syncthreads();
@@ -725,34 +741,25 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
     __syncthreads();
     apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
     {
-      // three levels in flight: the topology word two levels ahead, the other inputs one
-      // level ahead, the arithmetic of the current level
       int i = M.lvl_off[le - 1] + t;
       bool has = i < M.lvl_off[le];
       InU cur{};
-      if (has) cur = loadU(M, S, I, L, i, topo_up(M, i));
-      int i1 = le - 1 > lb ? M.lvl_off[le - 2] + t : 0;
-      bool h1 = le - 1 > lb && i1 < M.lvl_off[le - 1];
-      TopoU tp1{0, 0, 0};
-      if (h1) tp1 = topo_up(M, i1);
+      if (has) cur = loadU(M, S, I, L, i);
       for (int lv = le - 1; lv >= lb; --lv) {
         L.a = M.lvl_off[lv];
         L.nbr = M.lvl_off[lv + 1];
         L.b = (lv - lb) & 1;
-        const int i2 = lv - 1 > lb ? M.lvl_off[lv - 2] + t : 0;
-        const bool h2 = lv - 1 > lb && i2 < M.lvl_off[lv - 1];
-        TopoU tp2{0, 0, 0};
-        if (h2) tp2 = topo_up(M, i2);
+        const int in_ = lv > lb ? M.lvl_off[lv - 1] + t : 0;
+        const bool hn = lv > lb && in_ < M.lvl_off[lv];
         InU nxt{};
-        if (h1) nxt = loadU(M, S, I, L, i1, tp1);
+        if (hn) nxt = loadU(M, S, I, L, in_);
         if (has) {
           float o[N_OUTU];
-          node_up<true>(M, L, i, cur, o);
+          node_up<true>(M, I, L, i, cur, kstep, call_step0 + st, o);
           put_fields<F_WM>(&at(L.P, slane(L.nf, i - L.i0)), o);
         }
         if (lv > lb) lds_barrier();
-        i = i1; has = h1; cur = nxt;
-        i1 = i2; h1 = h2; tp1 = tp2;
+        i = in_; has = hn; cur = nxt;
       }
     }
     __syncthreads();
