@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 # the candidates the autotuner times for the benchmark
 BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=1, persistent=0, lds_width=240)
 AUTOTUNE_CANDIDATES = [BENCH_TUNING,
+                       dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=5),
+                       dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=10),
                        dict(threads=256, pack_fill=1.0, lds_width=256), dict(threads=256, pack_fill=1.0, lds_width=224),
                        dict(threads=256, pack_fill=1.0, lds_width=192), dict(threads=128, pack_fill=1.0, lds_width=128),
                        dict(threads=256, pack_fill=1.0, lds_width=0), dict(threads=128, pack_fill=1.0, lds_width=0)]

@@ -512,13 +512,12 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     if (nchild_i[i] > 0xFFFF || napp > 0xFFFF)
       return fail(ORCHARD_ERR_INVALID_TOPOLOGY, "a segment with more than 65535 children or apples");
     const float inv_mmax = (float)(1.0 / (double)mmax_f[i]);
-    int32_t bits;
-    std::memcpy(&bits, &inv_mmax, 4);
     hkey[i] = rng_node_key(d->rng_seed, (uint64_t)env_i[i], (uint64_t)orig_i[i]);
     nrec[i].rq = rq[i];
-    nrec[i].geo = geo[i];
-    nrec[i].topo = make_int4(par_i[i], child_i[i], nchild_i[i] | (napp << 16), env_i[i]);
-    nrec[i].aux = make_int4((int32_t)(uint32_t)(hkey[i] & 0xFFFFFFFFull), (int32_t)(uint32_t)(hkey[i] >> 32), anode[i], bits);
+    nrec[i].l = geo[i].x;
+    nrec[i].inv_mmax = inv_mmax;
+    nrec[i].par = par_i[i];
+    nrec[i].anode = anode[i];
     ntopo[i] = make_int4(par_i[i], child_i[i], nchild_i[i] | (napp << 16), anode[i]);
   }
   std::vector<AppleRec> arec(NA);

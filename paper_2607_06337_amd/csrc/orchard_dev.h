@@ -82,14 +82,16 @@ enum : int {
   N_FIELDS_ADJ = 224
 };
 
-// Static records read by the forward step: one 64-byte record per node and one per apple
-// (a few wide loads instead of one load per array).
+// Static records read by the forward step: one 32-byte record per node for the first down
+// pass and one 64-byte record per apple (a few wide loads instead of one load per array).
 struct NodeRec {
   float4 rq;    // rest quaternion (w, x, y, z)
-  float4 geo;   // (l, m, Jt about the joint, Ia)
-  int4 topo;    // (parent, first child, children | apples << 16, env)
-  int4 aux;     // (random-wrench key low, high 32 bits, apple-node index or -1, 1 / M_max as float bits)
+  float l;      // length
+  float inv_mmax;  // 1 / M_max (rupture moment)
+  int par;      // parent (-1 for a root)
+  int anode;    // apple-node index, -1 if the segment carries no apple
 };
+static_assert(sizeof(NodeRec) == 32, "the first down pass reads one 32-byte record per segment");
 struct AppleRec {
   float4 hang;  // hang point in the segment frame, mass
   float4 par;   // (1 / f_det, c_s, F_max, 1 / (alpha f_det))

@@ -106,8 +106,8 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   const float kp = in.kp;
   uint8_t brk = in.brk;
   const uint8_t cnt0 = in.cnt;
-  const int par = nr.topo.x;
-  const float l = nr.geo.x;
+  const int par = nr.par;
+  const float l = nr.l;
 
   // ---- parent publication ----
   // The env's frozen flag (status bit 0 at the start of the step) is read by the root and
@@ -121,7 +121,7 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     pj = v3(0, 0, 0); w = pj; vt = pj; Aa = pj;
     Al = v3(-M.gx, -M.gy, -M.gz);  // gravity as a base acceleration
     snp = false;
-    frozen = (at(S.status, (uint32_t)nr.topo.w) & ST_FROZEN) != 0u;
+    frozen = (at(S.status, (uint32_t)at(M.env, (uint32_t)i)) & ST_FROZEN) != 0u;
   } else {
     float pv[N_PUB1];
     xload<XL>(L, F_R, par, pv);
@@ -141,7 +141,7 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   int cnt1 = 0;
   if (!brk0) {
     const float th = sqrtf(fmaf(q.x, q.x, q.y * q.y));
-    const float mu = kp * th * __int_as_float(nr.aux.w);
+    const float mu = kp * th * nr.inv_mmax;
     cnt1 = mu > 1.f ? (int)cnt0 + 1 : 0;
     cnt1 = cnt1 > 255 ? 255 : cnt1;
     if (cnt1 >= M.n_break) brk = 1;
@@ -200,10 +200,10 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
 
   const bool live = !frozen;
   // apples are handled by the apple phase after this pass; keep what it needs
-  if (nr.topo.z >> 16) {
+  if (nr.anode >= 0) {
     static_assert(K_R == 0 && K_W == 9 && K_V == 12 && K_AA == 15 && K_AL == 18 && K_PJ == 21 && K_N == 24,
                   "snapshot layout");
-    float4* ks = reinterpret_cast<float4*>(M.asnap + (size_t)nr.aux.z * K_N);
+    float4* ks = reinterpret_cast<float4*>(M.asnap + (size_t)nr.anode * K_N);
     ks[0] = make_float4(c0.x, c1.x, c2.x, c0.y);
     ks[1] = make_float4(c1.y, c2.y, c0.z, c1.z);
     ks[2] = make_float4(c2.z, wi.x, wi.y, wi.z);
