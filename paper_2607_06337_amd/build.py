@@ -9,8 +9,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liborchard.so")
 SOURCES = ["orchard_api.hip", "orchard_step.hip", "orchard_adjoint.hip"]
-# packed FP32 instructions are kept out of every kernel (-packed-fp32-ops)
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-Wall",
+# packed FP32 instructions are kept out of every kernel (-packed-fp32-ops); a*b + c is
+# fused into an FMA only within one source expression (-ffp-contract=on), so an inline
+# function rounds the same way in every kernel and pass it is instantiated in
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-Wall", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
 

@@ -150,25 +150,20 @@ def test_checkpoint_interval_does_not_change_gradients():
         assert np.array_equal(x, y)
 
 
-def test_gradients_agree_across_mappings():
+def test_gradients_are_bitwise_identical_across_mappings():
     # the adjoint's level exchange through LDS (several workgroup sizes) or through global
-    # scratch sums in the same order; the two instantiations may contract a*b+c into FMAs
-    # differently, so gradients agree to rounding, and each LDS width bitwise with the others
+    # scratch runs the same arithmetic in the same order (FMA contraction is per source
+    # expression, so both instantiations round alike)
     batch = make_batch("grad512", env_ids=range(6))
     consts = step_constants()
     F = grad_apple_forces(batch, T)
     tip_idx, target = grad_targets(batch, _rest_tips(batch))
     ref = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=10, tuning=dict(threads=64, lds_width=0))
-    lds = []
     for tun in (dict(threads=64, lds_width=64), dict(threads=128, lds_width=96), dict(threads=256, lds_width=240)):
         res = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=10, tuning=tun)
         assert res[0] == ref[0], tun  # the forward is bit-identical across mappings
         for x, y in zip(res[1:4], ref[1:4]):
-            assert _rel(x, y) < 1e-5, (tun, _rel(x, y))
-        lds.append(res)
-    for res in lds[1:]:
-        for x, y in zip(res[1:4], lds[0][1:4]):
-            assert np.array_equal(x, y)
+            assert np.array_equal(x, y), (tun, _rel(x, y))
 
 
 def test_large_tree_adjoint_matches_fp64_central_differences():
