@@ -168,7 +168,7 @@ __device__ __forceinline__ InRV load_rv(const DevModel& M, const DevState& W, co
   const uint64_t hk = at(M.hkey, (uint32_t)i);
   r.hk0 = (uint32_t)hk;
   r.hk1 = (uint32_t)(hk >> 32);
-  r.flg = pld(P, nf, F_FLG, li);
+  r.flg = pld(P, nf, F_SFRZ, li);
   r.snp = pld(P, nf, F_SNAP, li);
   r.a0 = pld3(P, nf, F_A0, li);
   r.a1 = pld3(P, nf, F_A1, li);
@@ -205,7 +205,7 @@ template <bool XL>
 __device__ __forceinline__ void node_reverse(const DevModel& M, const DevState& W, const RecView& R0,
                                              const DevInputs& I, const DevAdj& X, const Lvl& L, int i,
                                              const InRV& in, int64_t n, int s_call) {
-  const bool skip = (((int)in.flg) & 1) != 0;  // frozen env: the step is the identity
+  const bool skip = in.flg != 0.f;  // frozen env: the step is the identity
   const float h = M.h;
   // forward quantities of this node; the body frame is (a1 x z, a1, z)
   const V3 a0 = in.a0, a1 = in.a1, z = in.z;
@@ -292,7 +292,7 @@ __device__ __forceinline__ void node_reverse(const DevModel& M, const DevState& 
   // applied force: moment arm (l/2) z
   {
     V3 F, T;
-    const bool snp = (((int)in.snp) & 1) != 0;
+    const bool snp = in.snp != 0.f;
     const uint64_t hkey = (uint64_t)in.hk0 | ((uint64_t)in.hk1 << 32);
     if (applied_force(M, I, i, splitmix64((uint64_t)n), s_call, m, snp, hkey, F, T)) zb = zb - (0.5f * l) * cross(F, na);
   }

@@ -18,7 +18,7 @@ enum : int {
   F_VT = 15,        // 3: linear velocity of the tip point
   F_AVA = 18,       // 3: velocity-product (+ base) acceleration at the tip, angular
   F_AVL = 21,       // 3:   linear
-  F_SNAP = 24,      // 1: snapped flag + 2 x the env's frozen flag
+  F_SNAP = 24,      // 1: snapped flag
   N_PUB1 = 25,
   // node-private data kept from the down pass for the up and second down passes; the
   // own-body inertia, l z and the spring terms are formed again from static data, z and
@@ -28,8 +28,7 @@ enum : int {
   F_WV = 31,        // 6: angular velocity and joint-point velocity (the velocity-product
                     //    acceleration and the bias are formed from them again)
   F_Z = 37,         // 3: body axis z (world)
-  F_FLG = 40,       // 1: 1 if the env is frozen at the start of the step, + 2 if the joint is
-                    //    broken, + 4 if the segment is snapped
+  F_FLG = 40,       // 1: flags of the step (broken, snapped, broken at the start, rupture count)
   // up-pass publication (27): articulated inertia and bias at the node's joint point
   F_IA = 60,        // 6: A (rotational block, sym)
   F_IB = 66,        // 9: B (coupling block, row major)
@@ -43,6 +42,7 @@ enum : int {
   // node-private outputs of the down 1 and up passes, each a contiguous range of fields
   N_OUT1 = 16,      // F_A0 .. F_FLG
   N_OUTU = 14,      // F_WM .. F_DU + 1
+  F_SFRZ = 104,     // 1: the env's frozen flag at the start of the step, stored in save mode
   N_FIELDS = 128,
   // Nodes that carry apples (a minority) keep their apple data in two dense arrays
   // indexed by the node's apple-node index, so it moves in whole sectors:
@@ -60,8 +60,8 @@ enum : int {
   E_JO = 4,         // 6: its rotational inertia about the joint (xx yy zz xy xz yz)
   E_P = 10,         // 6: reaction bias (ang, lin)
   E_N = 16,
-  // second down pass publication (6) overwrites the first six fields
-  F_AT = 0,         // 6: acceleration at the tip (ang, lin)
+  // second down pass publication (7) overwrites the first seven fields
+  F_AT = 0,         // 6: acceleration at the tip (ang, lin), then the env's frozen flag
   N_PUB_MAX = 27,
   X_STRIDE = 28,     // LDS exchange floats per node slot (N_PUB_MAX rounded to 16 B)
   // ---- fields of the adjoint ----

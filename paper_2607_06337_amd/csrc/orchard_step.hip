@@ -78,6 +78,20 @@ __device__ __forceinline__ void body_bias(const DevModel& M, const DevInputs& I,
 // nodes) and a compute stage, so the LDS path can issue the next level's loads before
 // the current level's arithmetic.
 
+// Node flags of a step (F_FLG), an integer below 2^11 held exactly in a float: broken
+// after the rupture test, snapped, broken at the start of the step, rupture counter.
+__device__ __forceinline__ float flg_pack(bool brk, bool snp, bool brk0, int cnt) {
+  return (float)((brk ? 1 : 0) | (snp ? 2 : 0) | (brk0 ? 4 : 0) | (cnt << 3));
+}
+struct Flags {
+  bool brk, snp, brk0;
+  int cnt;
+};
+__device__ __forceinline__ Flags flg_unpack(float f) {
+  const int v = (int)f;
+  return Flags{(v & 1) != 0, (v & 2) != 0, (v & 4) != 0, v >> 3};
+}
+
 // down 1 inputs that do not depend on other nodes
 struct In1 {
   NodeRec nr;
@@ -100,7 +114,7 @@ template <bool XL>
 __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L,
                                            int i, const In1& in, int64_t n, uint64_t kstep, int s_call,
                                            float (&o)[N_OUT1]) {
-  const int NS = M.n_seg, nf = M.scr_nf, li = i - L.i0;
+  const int nf = M.scr_nf, li = i - L.i0;
   const NodeRec& nr = in.nr;
   const float2 q = in.q, qd = in.qd;
   const float kp = in.kp;
@@ -110,18 +124,16 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   const float l = nr.l;
 
   // ---- parent publication ----
-  // The env's frozen flag (status bit 0 at the start of the step) is read by the root and
-  // handed down with the snapped flag (F_SNAP = snapped + 2 frozen), so no other node
-  // loads the status word.
+  // Down 1 writes nothing that depends on the env's frozen flag: its event writes are left
+  // to the up pass, and the frozen test of the state writes is made in down 2.
   Mat3 Rp;
   V3 pj, w, vt, Aa, Al;
-  bool snp, frozen;
+  bool snp;
   if (par < 0) {
     for (int k = 0; k < 9; ++k) Rp.m[k] = (k % 4 == 0) ? 1.f : 0.f;
     pj = v3(0, 0, 0); w = pj; vt = pj; Aa = pj;
     Al = v3(-M.gx, -M.gy, -M.gz);  // gravity as a base acceleration
     snp = false;
-    frozen = (at(S.status, (uint32_t)at(M.env, (uint32_t)i)) & ST_FROZEN) != 0u;
   } else {
     float pv[N_PUB1];
     xload<XL>(L, F_R, par, pv);
@@ -131,9 +143,7 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     vt = v3(pv[F_VT], pv[F_VT + 1], pv[F_VT + 2]);
     Aa = v3(pv[F_AVA], pv[F_AVA + 1], pv[F_AVA + 2]);
     Al = v3(pv[F_AVL], pv[F_AVL + 1], pv[F_AVL + 2]);
-    const int sf = (int)pv[F_SNAP];
-    snp = (sf & 1) != 0;
-    frozen = (sf & 2) != 0;
+    snp = pv[F_SNAP] != 0.f;
   }
 
   // ---- rupture test on the state at the start of the step (Eq. break) ----
@@ -184,7 +194,7 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     const V3 pt = pj + lz, vtp = v + cross(wi, lz), alt = Avl + cross(Ava, lz);
     const float ov[N_PUB1] = {c0.x, c1.x, c2.x, c0.y, c1.y, c2.y, c0.z, c1.z, c2.z,
                               pt.x, pt.y, pt.z, wi.x, wi.y, wi.z, vtp.x, vtp.y, vtp.z,
-                              Ava.x, Ava.y, Ava.z, alt.x, alt.y, alt.z, (snp ? 1.f : 0.f) + (frozen ? 2.f : 0.f)};
+                              Ava.x, Ava.y, Ava.z, alt.x, alt.y, alt.z, snp ? 1.f : 0.f};
     xstore<XL>(L, F_R, i, ov);
   }
   if (M.save_adj) {
@@ -193,12 +203,11 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     if constexpr (XL) {
       pst3(P, nf, F_W, li, wi);
       pst3(P, nf, F_VT, li, v + cross(wi, lz));
-      pst(P, nf, F_SNAP, li, (snp ? 1.f : 0.f) + (frozen ? 2.f : 0.f));
+      pst(P, nf, F_SNAP, li, snp ? 1.f : 0.f);
     }
     pst3(P, nf, F_SAVP, li, Ava); pst3(P, nf, F_SAVP + 3, li, Avl);
   }
 
-  const bool live = !frozen;
   // apples are handled by the apple phase after this pass; keep what it needs
   if (nr.anode >= 0) {
     static_assert(K_R == 0 && K_W == 9 && K_V == 12 && K_AA == 15 && K_AL == 18 && K_PJ == 21 && K_N == 24,
@@ -212,14 +221,10 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     ks[5] = make_float4(Avl.z, pj.x, pj.y, pj.z);
   }
 
-  // ---- event writes; the spring terms are formed in the up pass from the flags ----
-  if (live && !brk0) {
-    at(S.seg_evt, (uint32_t)(NS + i)) = (uint8_t)cnt1;
-    if (brk) { at(S.seg_evt, (uint32_t)i) = 1; at(S.evt_step, (uint32_t)i) = (int32_t)n; }
-  }
-  // node-private outputs (fields F_A0 .. F_FLG), stored by the caller
+  // node-private outputs (fields F_A0 .. F_FLG), stored by the caller; the flags carry the
+  // rupture test's result for the up pass, which forms the spring terms and writes the events
   const float out[N_OUT1] = {a0.x, a0.y, a0.z, a1.x, a1.y, a1.z, wi.x, wi.y, wi.z, v.x, v.y, v.z, z.x, z.y, z.z,
-                             (live ? 0.f : 1.f) + (brk ? 2.f : 0.f) + (snp ? 4.f : 0.f)};
+                             flg_pack(brk != 0, snp, brk0, cnt1)};
   for (int k = 0; k < N_OUT1; ++k) o[k] = out[k];
 }
 
@@ -262,8 +267,8 @@ __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S
       node = ar.link.x;
       first = ar.link.z != 0;
       an = ar.link.w;
-      // the env's frozen flag cannot change before down 2, so the status word still holds
-      // the value down 1 saw
+      // the env's frozen flag (status bit 0) changes only in down 2, so here it still holds
+      // its value at the start of the step
       const bool live = (at(S.status, (uint32_t)ar.link.y) & ST_FROZEN) == 0u;
       const float4* ks = reinterpret_cast<const float4*>(M.asnap + (size_t)ar.link.w * K_N);
       const float4 k0 = ks[0], k1 = ks[1], k2 = ks[2], k3 = ks[3], k4 = ks[4], k5 = ks[5];
@@ -417,6 +422,7 @@ struct InU {
   float2 q, qd;
   float kp, kd, flg;
   uint32_t hk0, hk1;  // random-wrench key
+  int env;
 };
 __device__ __forceinline__ InU loadU(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L, int i) {
   const int nf = M.scr_nf, li = i - L.i0;
@@ -437,14 +443,19 @@ __device__ __forceinline__ InU loadU(const DevModel& M, const DevState& S, const
   const uint64_t hk = at(M.hkey, (uint32_t)i);
   u.hk0 = (uint32_t)hk;
   u.hk1 = (uint32_t)(hk >> 32);
+  u.env = at(M.env, (uint32_t)i);
   return u;
 }
 
 template <bool XL>
-__device__ __forceinline__ void node_up(const DevModel& M, const DevInputs& I, const Lvl& L, int i, const InU& in,
-                                        uint64_t kstep, int s_call, float (&o)[N_OUTU]) {
+__device__ __forceinline__ void node_up(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L, int i,
+                                        const InU& in, int64_t n, uint64_t kstep, int s_call, float (&o)[N_OUTU]) {
   const int nf = M.scr_nf, li = i - L.i0;
   const TopoU topo = in.topo;
+  // the env's frozen flag at the start of the step (bit 0 changes only in down 2) decides the
+  // event writes at the end
+  const uint32_t stat = at(S.status, (uint32_t)in.env);
+  const Flags fl = flg_unpack(in.flg);
   const V3 a0 = in.a0, a1 = in.a1;
   const V3 r = in.geo.x * in.z;  // l z, joint point -> tip
   // the apple sums of a node that carries apples are loaded here rather than a level
@@ -458,7 +469,7 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevInputs& I, c
   // velocity-product acceleration and the own body's bias, formed from the velocities
   V3 ca, cl, pang, plin;
   vel_product(a0, a1, in.qd, in.wi, in.v, ca, cl);
-  const bool snp = (((int)in.flg) & 4) != 0;
+  const bool snp = fl.snp;
   body_bias(M, I, i, kstep, s_call, in.geo, in.z, in.wi, in.v, snp, (uint64_t)in.hk0 | ((uint64_t)in.hk1 << 32), pang,
             plin);
   // own body plus the apples' virtual masses and reactions (zero without apples)
@@ -471,7 +482,7 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevInputs& I, c
   const V3 pon = pang + v3(e2.z, e2.w, e3.x), pof = plin + v3(e3.y, e3.z, e3.w);
   // spring / damper with the implicit diagonal; a broken joint has none
   const float h = M.h;
-  const bool brk = (((int)in.flg) & 2) != 0;
+  const bool brk = fl.brk;
   const float kpe = brk ? 0.f : in.kp, kde = brk ? 0.f : in.kd;
   const float2 q = in.q, qd = in.qd;
   const float tau0 = -kpe * fmaf(h, qd.x, q.x) - kde * qd.x;
@@ -564,6 +575,11 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevInputs& I, c
   }
   float* Pw = L.P;
   if (M.save_adj) { pst(Pw, nf, F_DI, li, Di00); pst(Pw, nf, F_DI + 1, li, Di01); pst(Pw, nf, F_DI + 2, li, Di11); }
+  // rupture events of this step (the test ran in down 1)
+  if ((stat & ST_FROZEN) == 0u && !fl.brk0) {
+    at(S.seg_evt, (uint32_t)(M.n_seg + i)) = (uint8_t)fl.cnt;
+    if (fl.brk) { at(S.seg_evt, (uint32_t)i) = 1; at(S.evt_step, (uint32_t)i) = (int32_t)n; }
+  }
   // node-private outputs (fields F_WM .. F_DU + 1), stored by the caller
   const float out[N_OUTU] = {W0a.x, W0a.y, W0a.z, W0l.x, W0l.y, W0l.z, W1a.x, W1a.y, W1a.z, W1l.x, W1l.y, W1l.z,
                              fmaf(Di00, uu0, Di01 * uu1), fmaf(Di01, uu0, Di11 * uu1)};
@@ -576,7 +592,7 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevInputs& I, c
 // down 2 inputs: the node's factor data from the up pass and its state
 struct In2 {
   int par;
-  float flg, du0, du1, l;
+  float du0, du1, l;
   V3 wi, v, W0a, W0l, W1a, W1l, a0, a1, z;
   float2 q, qd;
 };
@@ -586,7 +602,6 @@ __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const
   In2 d;
   d.par = at(M.par, (uint32_t)i);
   d.l = at(M.len, (uint32_t)i);
-  d.flg = pld(P, nf, F_FLG, li);
   d.wi = pld3(P, nf, F_WV, li);
   d.v = pld3(P, nf, F_WV + 3, li);
   d.W0a = pld3(P, nf, F_WM, li);
@@ -607,19 +622,26 @@ template <bool XL>
 __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S, const Lvl& L, int i, const In2& in) {
   const int nf = M.scr_nf, li = i - L.i0;
   const int par = in.par;
-  const bool live = (((int)in.flg) & 1) == 0;
   const V3 W0a = in.W0a, W0l = in.W0l, W1a = in.W1a, W1l = in.W1l;
   const V3 a0 = in.a0, a1 = in.a1, lz = in.l * in.z;
   float2 q = in.q, qd = in.qd;
   V3 ca, cl;
   vel_product(a0, a1, qd, in.wi, in.v, ca, cl);
+  // The env's frozen flag at the start of the step is read by the root (nothing of this
+  // step has set bit 0 yet: only down 2 does) and handed down with the acceleration.
   V3 Aa, Al;
-  if (par < 0) { Aa = v3(0, 0, 0); Al = v3(-M.gx, -M.gy, -M.gz); }
-  else {
-    float pv[6];
+  bool frozen;
+  uint32_t rstat = 0;
+  if (par < 0) {
+    Aa = v3(0, 0, 0); Al = v3(-M.gx, -M.gy, -M.gz);
+    rstat = at(S.status, (uint32_t)at(M.env, (uint32_t)i));
+    frozen = (rstat & ST_FROZEN) != 0u;
+  } else {
+    float pv[7];
     xload<XL>(L, F_AT, par, pv);
     Aa = v3(pv[0], pv[1], pv[2]);
     Al = v3(pv[3], pv[4], pv[5]);
+    frozen = pv[6] != 0.f;
   }
   Aa = Aa + ca;
   Al = Al + cl;
@@ -630,13 +652,14 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
     float* Pw = L.P;
     pst3(Pw, nf, F_SA, li, Aa); pst3(Pw, nf, F_SA + 3, li, Al);
     pst(Pw, nf, F_SQDD, li, qdd0); pst(Pw, nf, F_SQDD + 1, li, qdd1);
+    pst(Pw, nf, F_SFRZ, li, frozen ? 1.f : 0.f);
   }
   {
     const V3 alt = Al + cross(Aa, lz);
-    const float ov[6] = {Aa.x, Aa.y, Aa.z, alt.x, alt.y, alt.z};
+    const float ov[7] = {Aa.x, Aa.y, Aa.z, alt.x, alt.y, alt.z, frozen ? 1.f : 0.f};
     xstore<XL>(L, F_AT, i, ov);
   }
-  if (!live) return;
+  if (frozen) return;
   const float h = M.h;
   qd.x = fmaf(h, qdd0, qd.x);
   qd.y = fmaf(h, qdd1, qd.y);
@@ -647,11 +670,7 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
   // a non-finite state freezes the env; the root promotes this step's apple flag once every
   // node of the step has run down 1 (only these rare cases touch the status word)
   const bool bad = !(isfinite(q.x) && isfinite(q.y) && isfinite(qd.x) && isfinite(qd.y));
-  if (bad || par < 0) {
-    uint32_t* st = &at(S.status, (uint32_t)at(M.env, (uint32_t)i));
-    if (bad) atomicOr(st, ST_FROZEN);
-    if (par < 0 && (*st & ST_APPLE_BAD)) atomicOr(st, ST_FROZEN);
-  }
+  if (bad || (par < 0 && (rstat & ST_APPLE_BAD))) atomicOr(&at(S.status, (uint32_t)at(M.env, (uint32_t)i)), ST_FROZEN);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -689,7 +708,7 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
       L.nbr = e;
       for (int i = L.a + (int)threadIdx.x; i < e; i += NT) {
         float o[N_OUTU];
-        node_up<false>(M, I, L, i, loadU(M, S, I, L, i), kstep, call_step0 + st, o);
+        node_up<false>(M, S, I, L, i, loadU(M, S, I, L, i), n, kstep, call_step0 + st, o);
         put_fields<F_WM>(&at(L.P, slane(L.nf, i - L.i0)), o);
       }
       __syncthreads();
@@ -755,7 +774,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         if (hn) nxt = loadU(M, S, I, L, in_);
         if (has) {
           float o[N_OUTU];
-          node_up<true>(M, I, L, i, cur, kstep, call_step0 + st, o);
+          node_up<true>(M, S, I, L, i, cur, n, kstep, call_step0 + st, o);
           put_fields<F_WM>(&at(L.P, slane(L.nf, i - L.i0)), o);
         }
         if (lv > lb) lds_barrier();
