@@ -169,7 +169,7 @@ __device__ __forceinline__ InRV load_rv(const DevModel& M, const DevState& W, co
   r.hk0 = (uint32_t)hk;
   r.hk1 = (uint32_t)(hk >> 32);
   r.flg = pld(P, nf, F_SFRZ, li);
-  r.snp = pld(P, nf, F_SNAP, li);
+  r.snp = pld(P, nf, F_SSNP, li);
   r.a0 = pld3(P, nf, F_A0, li);
   r.a1 = pld3(P, nf, F_A1, li);
   r.z = pld3(P, nf, F_Z, li);

@@ -11,24 +11,28 @@ namespace orchard {
 // publications in LDS (double-buffered by level parity); wide packs keep them in these
 // global fields.
 enum : int {
-  // down pass 1 publication (25), values at the node's tip point
-  F_R = 0,          // 9: body rotation, row major
-  F_PT = 9,         // 3: tip point (absolute; only detached apples use positions)
-  F_W = 12,         // 3: angular velocity
-  F_VT = 15,        // 3: linear velocity of the tip point
-  F_AVA = 18,       // 3: velocity-product (+ base) acceleration at the tip, angular
-  F_AVL = 21,       // 3:   linear
-  F_SNAP = 24,      // 1: snapped flag
-  N_PUB1 = 25,
+  // Publication of the two down passes (values at the node's tip point), one slot of 28
+  // floats; an LDS slot uses the same offsets.  Down 1 writes F_R .. F_SNAP, down 2
+  // F_SNAP .. F_AT + 5, a fused pass (down 2 of one step, down 1 of the next) all of it.
+  F_R = 0,          // 6: body rotation, columns 1 and 2 (column 0 is their cross product)
+  F_PT = 6,         // 3: tip point (absolute; only detached apples use positions)
+  F_W = 9,          // 3: angular velocity
+  F_VT = 12,        // 3: linear velocity of the tip point
+  F_AVA = 15,       // 3: velocity-product (+ base) acceleration at the tip, angular
+  F_AVL = 18,       // 3:   linear
+  F_SNAP = 21,      // 1: flags: snapped (down 1 part) + 2 x the env's frozen flag (down 2 part)
+  N_PUB1 = 22,
+  F_AT = 22,        // 6: acceleration at the tip (ang, lin)
+  N_PUBD = 28,
   // node-private data kept from the down pass for the up and second down passes; the
   // own-body inertia, l z and the spring terms are formed again from static data, z and
   // the state instead of being stored
-  F_A0 = 25,        // 3: joint axis x (world)
-  F_A1 = 28,        // 3: joint axis y (world)
-  F_WV = 31,        // 6: angular velocity and joint-point velocity (the velocity-product
+  F_A0 = 28,        // 3: joint axis x (world)
+  F_A1 = 31,        // 3: joint axis y (world)
+  F_WV = 34,        // 6: angular velocity and joint-point velocity (the velocity-product
                     //    acceleration and the bias are formed from them again)
-  F_Z = 37,         // 3: body axis z (world)
-  F_FLG = 40,       // 1: flags of the step (broken, snapped, broken at the start, rupture count)
+  F_Z = 40,         // 3: body axis z (world)
+  F_FLG = 43,       // 1: flags of the step (broken, snapped, broken at the start, rupture count)
   // up-pass publication (27): articulated inertia and bias at the node's joint point
   F_IA = 60,        // 6: A (rotational block, sym)
   F_IB = 66,        // 9: B (coupling block, row major)
@@ -43,6 +47,7 @@ enum : int {
   N_OUT1 = 16,      // F_A0 .. F_FLG
   N_OUTU = 14,      // F_WM .. F_DU + 1
   F_SFRZ = 104,     // 1: the env's frozen flag at the start of the step, stored in save mode
+  F_SSNP = 105,     // 1: the snapped flag, stored in save mode
   N_FIELDS = 128,
   // Nodes that carry apples (a minority) keep their apple data in two dense arrays
   // indexed by the node's apple-node index, so it moves in whole sectors:
@@ -60,10 +65,8 @@ enum : int {
   E_JO = 4,         // 6: its rotational inertia about the joint (xx yy zz xy xz yz)
   E_P = 10,         // 6: reaction bias (ang, lin)
   E_N = 16,
-  // second down pass publication (7) overwrites the first seven fields
-  F_AT = 0,         // 6: acceleration at the tip (ang, lin), then the env's frozen flag
-  N_PUB_MAX = 27,
-  X_STRIDE = 28,     // LDS exchange floats per node slot (N_PUB_MAX rounded to 16 B)
+  N_PUB_MAX = 28,
+  X_STRIDE = 28,     // LDS exchange floats per node slot (N_PUB_MAX, a multiple of 16 B)
   // ---- fields of the adjoint ----
   // saved by the forward step in save mode (the body frame is rebuilt from F_A1 and F_Z)
   F_SR = 128,       // 9: body rotation, row major (scratch of the tip-position kernels only)
@@ -206,6 +209,8 @@ __device__ __forceinline__ V3 fma3(float s, V3 a, V3 b) { return V3{fmaf(s, a.x,
 static_assert(F_A1 == F_A0 + 3 && F_WV == F_A1 + 3 && F_Z == F_WV + 6 && F_FLG == F_Z + 3 &&
               F_FLG + 1 - F_A0 == N_OUT1, "down 1 outputs are one field range");
 static_assert(F_DU == F_WM + 12 && F_DU + 2 - F_WM == N_OUTU, "up outputs are one field range");
+static_assert(F_AT == F_SNAP + 1 && N_PUB1 == F_SNAP + 1 && N_PUBD == F_AT + 6 && N_PUBD <= X_STRIDE &&
+              N_PUBD <= F_A0 && F_FLG < F_IA, "down-pass publication slot, then node-private fields");
 
 // symmetric 3x3 stored (xx yy zz xy xz yz)
 struct Sym3 { float xx, yy, zz, xy, xz, yz; };
@@ -310,33 +315,46 @@ struct Lvl {
 };
 
 // a whole publication: NF fields from f0 of node j on the neighbouring level (load) or of
-// node i on this level (store); on the LDS path a slot moves as 128-bit accesses (the
-// last one also covers padding of the slot, which nobody reads)
-template <bool XL, int NF>
+// node i on this level (store); in an LDS slot the fields start at offset OFF.  Aligned
+// publications move as 128-bit LDS accesses (the last one also covers slot padding,
+// which nobody reads).
+template <bool XL, int NF, int OFF = 0>
 __device__ __forceinline__ void xload(const Lvl& L, int f0, int j, float (&v)[NF]) {
   if constexpr (XL) {
-    const float4* s = reinterpret_cast<const float4*>(L.X + (uint32_t)(((L.b ^ 1) * L.cap + (j - L.nbr)) * X_STRIDE));
+    const float* sl = L.X + (uint32_t)(((L.b ^ 1) * L.cap + (j - L.nbr)) * X_STRIDE);
+    if constexpr (OFF % 4 == 0 && OFF + 4 * ((NF + 3) / 4) <= X_STRIDE) {
+      const float4* s = reinterpret_cast<const float4*>(sl + OFF);
 #pragma unroll
-    for (int k = 0; k < (NF + 3) / 4; ++k) {
-      const float4 t = s[k];
-      v[4 * k] = t.x;
-      if (4 * k + 1 < NF) v[4 * k + 1] = t.y;
-      if (4 * k + 2 < NF) v[4 * k + 2] = t.z;
-      if (4 * k + 3 < NF) v[4 * k + 3] = t.w;
+      for (int k = 0; k < (NF + 3) / 4; ++k) {
+        const float4 t = s[k];
+        v[4 * k] = t.x;
+        if (4 * k + 1 < NF) v[4 * k + 1] = t.y;
+        if (4 * k + 2 < NF) v[4 * k + 2] = t.z;
+        if (4 * k + 3 < NF) v[4 * k + 3] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NF; ++k) v[k] = sl[OFF + k];
     }
   } else {
 #pragma unroll
     for (int k = 0; k < NF; ++k) v[k] = pld(L.P, L.nf, f0 + k, j - L.i0);
   }
 }
-template <bool XL, int NF>
+template <bool XL, int NF, int OFF = 0>
 __device__ __forceinline__ void xstore(const Lvl& L, int f0, int i, const float (&v)[NF]) {
   if constexpr (XL) {
-    float4* d = reinterpret_cast<float4*>(L.X + (uint32_t)((L.b * L.cap + (i - L.a)) * X_STRIDE));
+    float* sl = L.X + (uint32_t)((L.b * L.cap + (i - L.a)) * X_STRIDE);
+    if constexpr (OFF % 4 == 0 && OFF + 4 * ((NF + 3) / 4) <= X_STRIDE) {
+      float4* d = reinterpret_cast<float4*>(sl + OFF);
 #pragma unroll
-    for (int k = 0; k < (NF + 3) / 4; ++k)
-      d[k] = make_float4(v[4 * k], 4 * k + 1 < NF ? v[4 * k + 1] : 0.f, 4 * k + 2 < NF ? v[4 * k + 2] : 0.f,
-                         4 * k + 3 < NF ? v[4 * k + 3] : 0.f);
+      for (int k = 0; k < (NF + 3) / 4; ++k)
+        d[k] = make_float4(v[4 * k], 4 * k + 1 < NF ? v[4 * k + 1] : 0.f, 4 * k + 2 < NF ? v[4 * k + 2] : 0.f,
+                           4 * k + 3 < NF ? v[4 * k + 3] : 0.f);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NF; ++k) sl[OFF + k] = v[k];
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < NF; ++k) pst(L.P, L.nf, f0 + k, i - L.i0, v[k]);

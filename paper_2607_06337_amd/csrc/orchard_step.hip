@@ -99,24 +99,32 @@ struct In1 {
   float kp;
   uint8_t brk, cnt;
 };
+// STATE: also the joint state (a fused pass takes it from the second down pass instead)
+template <bool STATE = true>
 __device__ __forceinline__ In1 load1(const DevModel& M, const DevState& S, const DevInputs& I, int i) {
   In1 r;
   r.nr = at(M.nrec, (uint32_t)i);
-  r.q = at(S.q, (uint32_t)i);
-  r.qd = at(S.qd, (uint32_t)i);
+  if constexpr (STATE) {
+    r.q = at(S.q, (uint32_t)i);
+    r.qd = at(S.qd, (uint32_t)i);
+  } else {
+    r.q = r.qd = make_float2(0.f, 0.f);
+  }
   r.kp = at(I.kp, (uint32_t)i);
   r.brk = at(S.seg_evt, (uint32_t)i);
   r.cnt = at(S.seg_evt, (uint32_t)(M.n_seg + i));
   return r;
 }
 
+// pv: the parent's publication (not read for a root); q, qd: the joint state at the start
+// of the step; pub: this node's publication, o: its node-private outputs (both stored by
+// the caller).
 template <bool XL>
-__device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L,
-                                           int i, const In1& in, int64_t n, uint64_t kstep, int s_call,
+__device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S, const Lvl& L, int i, const In1& in,
+                                           float2 q, float2 qd, const float (&pv)[N_PUB1], float (&pub)[N_PUB1],
                                            float (&o)[N_OUT1]) {
   const int nf = M.scr_nf, li = i - L.i0;
   const NodeRec& nr = in.nr;
-  const float2 q = in.q, qd = in.qd;
   const float kp = in.kp;
   uint8_t brk = in.brk;
   const uint8_t cnt0 = in.cnt;
@@ -135,15 +143,17 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     Al = v3(-M.gx, -M.gy, -M.gz);  // gravity as a base acceleration
     snp = false;
   } else {
-    float pv[N_PUB1];
-    xload<XL>(L, F_R, par, pv);
-    for (int k = 0; k < 9; ++k) Rp.m[k] = pv[F_R + k];
+    const V3 r1 = v3(pv[F_R], pv[F_R + 1], pv[F_R + 2]), r2 = v3(pv[F_R + 3], pv[F_R + 4], pv[F_R + 5]);
+    const V3 r0 = cross(r1, r2);
+    Rp.m[0] = r0.x; Rp.m[1] = r1.x; Rp.m[2] = r2.x;
+    Rp.m[3] = r0.y; Rp.m[4] = r1.y; Rp.m[5] = r2.y;
+    Rp.m[6] = r0.z; Rp.m[7] = r1.z; Rp.m[8] = r2.z;
     pj = v3(pv[F_PT], pv[F_PT + 1], pv[F_PT + 2]);
     w = v3(pv[F_W], pv[F_W + 1], pv[F_W + 2]);
     vt = v3(pv[F_VT], pv[F_VT + 1], pv[F_VT + 2]);
     Aa = v3(pv[F_AVA], pv[F_AVA + 1], pv[F_AVA + 2]);
     Al = v3(pv[F_AVL], pv[F_AVL + 1], pv[F_AVL + 2]);
-    snp = pv[F_SNAP] != 0.f;
+    snp = (((int)pv[F_SNAP]) & 1) != 0;
   }
 
   // ---- rupture test on the state at the start of the step (Eq. break) ----
@@ -192,10 +202,10 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   const V3 lz = l * z;
   {
     const V3 pt = pj + lz, vtp = v + cross(wi, lz), alt = Avl + cross(Ava, lz);
-    const float ov[N_PUB1] = {c0.x, c1.x, c2.x, c0.y, c1.y, c2.y, c0.z, c1.z, c2.z,
+    const float ov[N_PUB1] = {c1.x, c1.y, c1.z, c2.x, c2.y, c2.z,
                               pt.x, pt.y, pt.z, wi.x, wi.y, wi.z, vtp.x, vtp.y, vtp.z,
                               Ava.x, Ava.y, Ava.z, alt.x, alt.y, alt.z, snp ? 1.f : 0.f};
-    xstore<XL>(L, F_R, i, ov);
+    for (int k = 0; k < N_PUB1; ++k) pub[k] = ov[k];
   }
   if (M.save_adj) {
     // the adjoint reads these from global scratch whichever way levels exchange
@@ -203,8 +213,8 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
     if constexpr (XL) {
       pst3(P, nf, F_W, li, wi);
       pst3(P, nf, F_VT, li, v + cross(wi, lz));
-      pst(P, nf, F_SNAP, li, snp ? 1.f : 0.f);
     }
+    pst(P, nf, F_SSNP, li, snp ? 1.f : 0.f);
     pst3(P, nf, F_SAVP, li, Ava); pst3(P, nf, F_SAVP + 3, li, Avl);
   }
 
@@ -618,8 +628,12 @@ __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const
   return d;
 }
 
+// pv: the parent's flags and acceleration at the tip (not read for a root); pub: this
+// node's, stored by the caller; qn, qdn: the joint state after the step (unchanged in a
+// frozen env), also written to the state here.
 template <bool XL>
-__device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S, const Lvl& L, int i, const In2& in) {
+__device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S, const Lvl& L, int i, const In2& in,
+                                           const float (&pv)[7], float (&pub)[7], float2& qn, float2& qdn) {
   const int nf = M.scr_nf, li = i - L.i0;
   const int par = in.par;
   const V3 W0a = in.W0a, W0l = in.W0l, W1a = in.W1a, W1l = in.W1l;
@@ -637,11 +651,9 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
     rstat = at(S.status, (uint32_t)at(M.env, (uint32_t)i));
     frozen = (rstat & ST_FROZEN) != 0u;
   } else {
-    float pv[7];
-    xload<XL>(L, F_AT, par, pv);
-    Aa = v3(pv[0], pv[1], pv[2]);
-    Al = v3(pv[3], pv[4], pv[5]);
-    frozen = pv[6] != 0.f;
+    frozen = (((int)pv[0]) & 2) != 0;
+    Aa = v3(pv[1], pv[2], pv[3]);
+    Al = v3(pv[4], pv[5], pv[6]);
   }
   Aa = Aa + ca;
   Al = Al + cl;
@@ -656,9 +668,11 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
   }
   {
     const V3 alt = Al + cross(Aa, lz);
-    const float ov[7] = {Aa.x, Aa.y, Aa.z, alt.x, alt.y, alt.z, frozen ? 1.f : 0.f};
-    xstore<XL>(L, F_AT, i, ov);
+    const float ov[7] = {frozen ? 2.f : 0.f, Aa.x, Aa.y, Aa.z, alt.x, alt.y, alt.z};
+    for (int k = 0; k < 7; ++k) pub[k] = ov[k];
   }
+  qn = q;
+  qdn = qd;
   if (frozen) return;
   const float h = M.h;
   qd.x = fmaf(h, qdd0, qd.x);
@@ -667,6 +681,8 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
   q.y = fmaf(h, qd.y, q.y);
   at(S.q, (uint32_t)i) = q;
   at(S.qd, (uint32_t)i) = qd;
+  qn = q;
+  qdn = qd;
   // a non-finite state freezes the env; the root promotes this step's apple flag once every
   // node of the step has run down 1 (only these rare cases touch the status word)
   const bool bad = !(isfinite(q.x) && isfinite(q.y) && isfinite(qd.x) && isfinite(qd.y));
@@ -676,48 +692,93 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
 // ------------------------------------------------------------------------------------------
 // pack kernels
 // ------------------------------------------------------------------------------------------
+// One node of a down pass: the parent's publication in (nothing for a root), the node's
+// own out through the exchange, its node-private outputs to scratch.
+template <bool XL>
+__device__ __forceinline__ void pass_down1(const DevModel& M, const DevState& S, const Lvl& L, int i, const In1& in) {
+  float pv[N_PUB1], pub[N_PUB1], o[N_OUT1];
+  if (in.nr.par >= 0) xload<XL>(L, F_R, in.nr.par, pv);
+  node_down1<XL>(M, S, L, i, in, in.q, in.qd, pv, pub, o);
+  xstore<XL>(L, F_R, i, pub);
+  put_fields<F_A0>(&at(L.P, slane(L.nf, i - L.i0)), o);
+}
+template <bool XL>
+__device__ __forceinline__ void pass_down2(const DevModel& M, const DevState& S, const Lvl& L, int i, const In2& in) {
+  float pv[7], pub[7];
+  float2 qn, qdn;
+  if (in.par >= 0) xload<XL, 7, F_SNAP>(L, F_SNAP, in.par, pv);
+  node_down2<XL>(M, S, L, i, in, pv, pub, qn, qdn);
+  xstore<XL, 7, F_SNAP>(L, F_SNAP, i, pub);
+}
+// Fused pass of a multi-step launch: down 2 of one step and down 1 of the next walk the
+// tree in the same direction, so one sweep does both.  The parent's whole slot comes in
+// once; the joint state goes from one part to the other in registers; the flags float
+// carries the next step's snapped flag and this step's frozen flag.
+template <bool XL>
+__device__ __forceinline__ void pass_fused(const DevModel& M, const DevState& S, const Lvl& L, int i, const In2& in2,
+                                           const In1& in1) {
+  float pv[N_PUBD], pv1[N_PUB1], pv2[7];
+  if (in2.par >= 0) {
+    xload<XL>(L, F_R, in2.par, pv);
+    for (int k = 0; k < N_PUB1; ++k) pv1[k] = pv[k];
+    for (int k = 0; k < 7; ++k) pv2[k] = pv[F_SNAP + k];
+  }
+  float pub2[7], pub1[N_PUB1], o[N_OUT1];
+  float2 qn, qdn;
+  node_down2<XL>(M, S, L, i, in2, pv2, pub2, qn, qdn);
+  node_down1<XL>(M, S, L, i, in1, qn, qdn, pv1, pub1, o);
+  float pub[N_PUBD];
+  for (int k = 0; k < F_SNAP; ++k) pub[k] = pub1[k];
+  pub[F_SNAP] = pub1[F_SNAP] + pub2[0];
+  for (int k = 1; k < 7; ++k) pub[F_SNAP + k] = pub2[k];
+  xstore<XL>(L, F_R, i, pub);
+  put_fields<F_A0>(&at(L.P, slane(L.nf, i - L.i0)), o);
+}
+
 template <bool XL>
 __device__ __forceinline__ void level_barrier() {
   if constexpr (XL) lds_barrier();
   else __syncthreads();
 }
 
+// Steps of a launch: down 1 of the first step, then per step the apple phase, the up pass
+// and either the fused pass into the next step or, after the last, down 2.  Save mode (the
+// adjoint's recompute) runs one step per launch, so it never fuses.
+
 // Global exchange: any number of nodes per thread and level, loads then arithmetic.
 template <int NT>
 __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevState& S, const DevInputs& I, Lvl& L,
                                                 float* Abuf, int pk, int lb, int le, int64_t n0, int n_inner,
                                                 int call_step0) {
+  const int t = (int)threadIdx.x;
+  for (int lv = lb; lv < le; ++lv) {
+    L.a = M.lvl_off[lv];
+    const int e = M.lvl_off[lv + 1];
+    for (int i = L.a + t; i < e; i += NT) pass_down1<false>(M, S, L, i, load1(M, S, I, i));
+    __syncthreads();
+  }
   for (int st = 0; st < n_inner; ++st) {
     const int64_t n = n0 + st;
     const uint64_t kstep = splitmix64((uint64_t)n);
-    for (int lv = lb; lv < le; ++lv) {
-      L.a = M.lvl_off[lv];
-      const int e = M.lvl_off[lv + 1];
-      L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
-      for (int i = L.a + (int)threadIdx.x; i < e; i += NT) {
-        float o[N_OUT1];
-        node_down1<false>(M, S, I, L, i, load1(M, S, I, i), n, kstep, call_step0 + st, o);
-        put_fields<F_A0>(&at(L.P, slane(L.nf, i - L.i0)), o);
-      }
-      __syncthreads();
-    }
     apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
     for (int lv = le - 1; lv >= lb; --lv) {
       L.a = M.lvl_off[lv];
       const int e = M.lvl_off[lv + 1];
-      L.nbr = e;
-      for (int i = L.a + (int)threadIdx.x; i < e; i += NT) {
+      for (int i = L.a + t; i < e; i += NT) {
         float o[N_OUTU];
         node_up<false>(M, S, I, L, i, loadU(M, S, I, L, i), n, kstep, call_step0 + st, o);
         put_fields<F_WM>(&at(L.P, slane(L.nf, i - L.i0)), o);
       }
       __syncthreads();
     }
+    const bool fuse = st + 1 < n_inner;
     for (int lv = lb; lv < le; ++lv) {
       L.a = M.lvl_off[lv];
       const int e = M.lvl_off[lv + 1];
-      L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
-      for (int i = L.a + (int)threadIdx.x; i < e; i += NT) node_down2<false>(M, S, L, i, load2(M, S, L, i));
+      for (int i = L.a + t; i < e; i += NT) {
+        if (fuse) pass_fused<false>(M, S, L, i, load2(M, S, L, i), load1<false>(M, S, I, i));
+        else pass_down2<false>(M, S, L, i, load2(M, S, L, i));
+      }
       __syncthreads();
     }
   }
@@ -732,32 +793,28 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
                                              float* Abuf, int pk, int lb, int le, int64_t n0, int n_inner,
                                              int call_step0) {
   const int t = (int)threadIdx.x;
+  {
+    int i = M.lvl_off[lb] + t;
+    bool has = i < M.lvl_off[lb + 1];
+    In1 cur{};
+    if (has) cur = load1(M, S, I, i);
+    for (int lv = lb; lv < le; ++lv) {
+      L.a = M.lvl_off[lv];
+      L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
+      L.b = (lv - lb) & 1;
+      const int in_ = M.lvl_off[lv + 1] + t;
+      const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
+      In1 nxt{};
+      if (hn) nxt = load1(M, S, I, in_);
+      if (has) pass_down1<true>(M, S, L, i, cur);
+      if (lv + 1 < le) lds_barrier();
+      i = in_; has = hn; cur = nxt;
+    }
+  }
+  __syncthreads();
   for (int st = 0; st < n_inner; ++st) {
     const int64_t n = n0 + st;
     const uint64_t kstep = splitmix64((uint64_t)n);
-    {
-      int i = M.lvl_off[lb] + t;
-      bool has = i < M.lvl_off[lb + 1];
-      In1 cur{};
-      if (has) cur = load1(M, S, I, i);
-      for (int lv = lb; lv < le; ++lv) {
-        L.a = M.lvl_off[lv];
-        L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
-        L.b = (lv - lb) & 1;
-        const int in_ = M.lvl_off[lv + 1] + t;
-        const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
-        In1 nxt{};
-        if (hn) nxt = load1(M, S, I, in_);
-        if (has) {
-          float o[N_OUT1];
-          node_down1<true>(M, S, I, L, i, cur, n, kstep, call_step0 + st, o);
-          put_fields<F_A0>(&at(L.P, slane(L.nf, i - L.i0)), o);
-        }
-        if (lv + 1 < le) lds_barrier();
-        i = in_; has = hn; cur = nxt;
-      }
-    }
-    __syncthreads();
     apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
     {
       int i = M.lvl_off[le - 1] + t;
@@ -782,7 +839,26 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
       }
     }
     __syncthreads();
-    {
+    if (st + 1 < n_inner) {
+      int i = M.lvl_off[lb] + t;
+      bool has = i < M.lvl_off[lb + 1];
+      In2 c2{};
+      In1 c1{};
+      if (has) { c2 = load2(M, S, L, i); c1 = load1<false>(M, S, I, i); }
+      for (int lv = lb; lv < le; ++lv) {
+        L.a = M.lvl_off[lv];
+        L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
+        L.b = (lv - lb) & 1;
+        const int in_ = M.lvl_off[lv + 1] + t;
+        const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
+        In2 n2{};
+        In1 n1{};
+        if (hn) { n2 = load2(M, S, L, in_); n1 = load1<false>(M, S, I, in_); }
+        if (has) pass_fused<true>(M, S, L, i, c2, c1);
+        if (lv + 1 < le) lds_barrier();
+        i = in_; has = hn; c2 = n2; c1 = n1;
+      }
+    } else {
       int i = M.lvl_off[lb] + t;
       bool has = i < M.lvl_off[lb + 1];
       In2 cur{};
@@ -795,7 +871,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
         In2 nxt{};
         if (hn) nxt = load2(M, S, L, in_);
-        if (has) node_down2<true>(M, S, L, i, cur);
+        if (has) pass_down2<true>(M, S, L, i, cur);
         if (lv + 1 < le) lds_barrier();
         i = in_; has = hn; cur = nxt;
       }
