@@ -29,13 +29,13 @@ sys.path.insert(0, ROOT)
 
 # kernel mapping used by the full-size parity test and the adjoint ratio, and the first of
 # the candidates the autotuner times for the benchmark
-BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=1, persistent=0, lds_width=240)
-AUTOTUNE_CANDIDATES = [BENCH_TUNING,
-                       dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=5),
-                       dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=10),
-                       dict(threads=256, pack_fill=1.0, lds_width=256), dict(threads=256, pack_fill=1.0, lds_width=224),
-                       dict(threads=256, pack_fill=1.0, lds_width=192), dict(threads=128, pack_fill=1.0, lds_width=128),
-                       dict(threads=256, pack_fill=1.0, lds_width=0), dict(threads=128, pack_fill=1.0, lds_width=0)]
+BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=10, persistent=0, lds_width=240)
+# candidates of the autotuner: workgroup size, LDS width, steps per launch (a multi-step
+# launch fuses the second down pass of a step with the first of the next)
+AUTOTUNE_CANDIDATES = [BENCH_TUNING, dict(BENCH_TUNING, steps_per_launch=1),
+                       dict(BENCH_TUNING, lds_width=256), dict(BENCH_TUNING, lds_width=224),
+                       dict(BENCH_TUNING, lds_width=192), dict(BENCH_TUNING, threads=128, lds_width=128),
+                       dict(BENCH_TUNING, lds_width=0), dict(BENCH_TUNING, threads=128, lds_width=0)]
 GRAPH_STEPS = 100  # steps per captured HIP graph in the timed rollout
 # the plain per-step kernel: one 256-thread workgroup per tree, one launch per step,
 # levels exchange through global scratch
