@@ -103,7 +103,8 @@ typedef struct {
   int32_t persistent;           /* 1: persistent grid pulling packs from a queue      */
   int32_t adjoint_ckpt_max;     /* > 0: allocate recompute buffers for                */
                                 /*   orchard_step_backward with ckpt_every up to this */
-                                /*   (K scratch copies and K + 1 state records)       */
+                                /*   (two sets of K scratch copies and K + 1 state    */
+                                /*   records, a second stream and five events)        */
   int32_t lds_width;
   int32_t pack_skew;
 } orchard_tuning_t;
@@ -215,7 +216,10 @@ typedef struct {
  * [n_seg] and, if non-NULL, grad_apple_force [n_steps][n_apple][3].  Params and
  * inputs must be those of the forward call.  The quaternion and angular velocity of
  * the apples are not differentiated, nor is a detached apple's position w.r.t. the
- * tree pose at the detach step.  Stream-ordered; no allocation. */
+ * tree pose at the detach step.  Stream-ordered with respect to stream; the recompute
+ * of each checkpoint segment runs on the model's second stream, overlapping the
+ * reverse sweep of the segment after it (two sets of recompute buffers), and is joined
+ * back before the call's last work on stream.  No allocation. */
 orchard_status_t orchard_step_backward(orchard_model_t model, const float* ckpt, int32_t ckpt_every, int32_t n_steps,
                                        const orchard_params_t* params, const orchard_inputs_t* inputs,
                                        const orchard_adjoint_t* adj, float* grad_kp, float* grad_kd,

@@ -73,13 +73,16 @@ struct orchard_model_s {
   int64_t bytes = 0;
   int n_cu = 256;
   int persist_blocks = 0;
-  // adjoint support
+  // adjoint support: two sets of recompute buffers, so that the save-mode recompute of one
+  // checkpoint interval (on a second stream) overlaps the reverse sweep of the next
   int32_t adj_kmax = 0;
-  float* recs = nullptr;       // [adj_kmax + 1][ckpt words]
-  float* reps = nullptr;       // [adj_kmax - 1] scratch replicas (the main scratch is replica 0)
+  float* recs = nullptr;       // [2][adj_kmax + 1][ckpt words]
+  float* reps = nullptr;       // [2 adj_kmax - 1] scratch replicas (the main scratch is set 0's first)
   size_t scr_bytes = 0;
-  void* work = nullptr;        // work state
-  DevState ws{};
+  void* work = nullptr;        // work states of both sets
+  DevState ws{}, ws2{};
+  hipStream_t s_aux = nullptr;                   // recompute stream (default priority)
+  hipEvent_t ev_in = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -633,26 +636,37 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   if (tun.adjoint_ckpt_max > 0) {
     const int64_t words = orchard_ckpt_words(M);
     M->adj_kmax = tun.adjoint_ckpt_max;
-    const size_t rb = (size_t)(M->adj_kmax + 1) * (size_t)words * 4;
+    const size_t rb = 2 * (size_t)(M->adj_kmax + 1) * (size_t)words * 4;
     // one scratch per step of a checkpoint interval: the backward sweep runs each step's
-    // forward once, keeping what the reverse pass reads back
-    const size_t pb = (size_t)(M->adj_kmax - 1) * M->scr_bytes;
+    // forward once, keeping what the reverse pass reads back (two sets of them)
+    const size_t pb = (size_t)(2 * M->adj_kmax - 1) * M->scr_bytes;
     // work state: q, qd (float2), apple (13A), seg_evt (2S), apple_evt (4A), evt_step (S+A), status (B),
     // step; every piece starts on a 256-byte boundary
     auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t wb = 2 * r256(8 * (size_t)NS) + r256(52 * (size_t)NA) + r256(2 * (size_t)NS) + r256(4 * (size_t)NA) +
                       r256(4 * (size_t)(NS + NA)) + r256(4 * (size_t)B) + r256(8);
-    if (hipMalloc(&M->recs, rb) != hipSuccess || hipMalloc(&M->work, wb) != hipSuccess ||
+    if (hipMalloc(&M->recs, rb) != hipSuccess || hipMalloc(&M->work, 2 * wb) != hipSuccess ||
         (pb > 0 && hipMalloc(&M->reps, pb) != hipSuccess)) {
       orchard_model_destroy(M);
       return fail(ORCHARD_ERR_OUT_OF_MEMORY, "adjoint buffers");
     }
+    if (hipStreamCreateWithFlags(&M->s_aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&M->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&M->ev_rec[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&M->ev_rec[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&M->ev_adj[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&M->ev_adj[1], hipEventDisableTiming) != hipSuccess) {
+      orchard_model_destroy(M);
+      return fail(ORCHARD_ERR_HIP, "adjoint stream or events");
+    }
     char* w = (char*)M->work;
     auto take = [&](size_t b) { char* r = w; w += (b + 255) & ~size_t(255); return r; };
-    M->ws.q = (float2*)take(8 * NS); M->ws.qd = (float2*)take(8 * NS); M->ws.apple = (float*)take(52 * NA);
-    M->ws.seg_evt = (uint8_t*)take(2 * NS); M->ws.apple_evt = (uint8_t*)take(4 * NA);
-    M->ws.evt_step = (int32_t*)take(4 * (NS + NA)); M->ws.status = (uint32_t*)take(4 * B); M->ws.step = (int64_t*)take(8);
-    M->bytes += (int64_t)(rb + wb + pb);
+    for (DevState* ws : {&M->ws, &M->ws2}) {
+      ws->q = (float2*)take(8 * NS); ws->qd = (float2*)take(8 * NS); ws->apple = (float*)take(52 * NA);
+      ws->seg_evt = (uint8_t*)take(2 * NS); ws->apple_evt = (uint8_t*)take(4 * NA);
+      ws->evt_step = (int32_t*)take(4 * (NS + NA)); ws->status = (uint32_t*)take(4 * B); ws->step = (int64_t*)take(8);
+    }
+    M->bytes += (int64_t)(rb + 2 * wb + pb);
   }
   *out = M;
   return ORCHARD_OK;
@@ -663,6 +677,9 @@ void orchard_model_destroy(orchard_model_t m) {
   if (m->recs) (void)hipFree(m->recs);
   if (m->reps) (void)hipFree(m->reps);
   if (m->work) (void)hipFree(m->work);
+  for (hipEvent_t e : {m->ev_in, m->ev_rec[0], m->ev_rec[1], m->ev_adj[0], m->ev_adj[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (m->s_aux) (void)hipStreamDestroy(m->s_aux);
   if (m->arena) (void)hipFree(m->arena);
   if (m->scr) (void)hipFree(m->scr);
   delete m;
@@ -873,36 +890,72 @@ orchard_status_t orchard_step_backward(orchard_model_t m, const float* ckpt, int
   const int NT = m->tun.threads;
   const unsigned lb = (unsigned)m->lds_bytes;  // the adjoint kernel shares the step kernels' exchange layout
   const int nseg = (n_steps + ckpt_every - 1) / ckpt_every;
-  const DevState& W = m->ws;
-  auto rep = [&](int j) { return j == 0 ? m->scr : (float*)((char*)m->reps + (size_t)(j - 1) * m->scr_bytes); };
-  auto rec_at = [&](int j) { return (uint32_t*)m->recs + (int64_t)j * words; };
-  for (int sg = nseg - 1; sg >= 0; --sg) {
-    const int n0 = sg * ckpt_every, nk = std::min(ckpt_every, n_steps - n0);
-    // forward sweep: every step once, in save mode into its own scratch; records hold the
-    // state before each step and after the last
-    hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (const uint32_t*)ckpt + (int64_t)sg * words);
-    hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, rec_at(0));
+  // recompute set s (= checkpoint interval mod 2): work state, scratch copies, records
+  const int K = m->adj_kmax;
+  auto wstate = [&](int s) -> const DevState& { return s == 0 ? m->ws : m->ws2; };
+  auto rep = [&](int s, int j) {
+    const int k = s * K + j;  // copy k of the 2K; copy 0 is the main scratch
+    return k == 0 ? m->scr : (float*)((char*)m->reps + (size_t)(k - 1) * m->scr_bytes);
+  };
+  auto rec_at = [&](int s, int j) { return (uint32_t*)m->recs + ((int64_t)s * (K + 1) + j) * words; };
+  // forward sweep of interval sg: every step once, in save mode into its own scratch;
+  // records hold the state before each step and after the last
+  auto recompute = [&](int sg, hipStream_t st) -> orchard_status_t {
+    const int s = sg & 1, n0 = sg * ckpt_every, nk = std::min(ckpt_every, n_steps - n0);
+    const DevState& W = wstate(s);
+    hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, st, m->dm, W, (const uint32_t*)ckpt + (int64_t)sg * words);
+    hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, st, m->dm, W, rec_at(s, 0));
     for (int j = 0; j < nk; ++j) {
-      orchard_status_t st = launch_steps(m, W, di, 1, n0 + j, hs, true, rep(j));
-      if (st) return st;
-      hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, rec_at(j + 1));
+      orchard_status_t r = launch_steps(m, W, di, 1, n0 + j, st, true, rep(s, j));
+      if (r) return r;
+      hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, st, m->dm, W, rec_at(s, j + 1));
     }
-    // reverse sweep: W holds the state after step j (event flags, step counter)
+    HIPCHK(hipGetLastError());
+    return ORCHARD_OK;
+  };
+  // reverse sweep of interval sg: W holds the state after step j (event flags, step counter)
+  auto reverse = [&](int sg, hipStream_t st) -> orchard_status_t {
+    const int s = sg & 1, n0 = sg * ckpt_every, nk = std::min(ckpt_every, n_steps - n0);
+    const DevState& W = wstate(s);
     for (int j = nk - 1; j >= 0; --j) {
       if (j < nk - 1)
-        hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, hs, m->dm, W, (const uint32_t*)rec_at(j + 1));
+        hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, st, m->dm, W, (const uint32_t*)rec_at(s, j + 1));
       DevModel dm = m->dm;
-      dm.scr = rep(j);
-      const float* rec = (const float*)rec_at(j);
+      dm.scr = rep(s, j);
+      const float* rec = (const float*)rec_at(s, j);
       const dim3 g(m->n_pack);
       switch (NT) {
-        case 64: hipLaunchKernelGGL(k_adjoint_packs<64>, g, dim3(64), lb, hs, dm, W, rec, di, X, n0 + j); break;
-        case 128: hipLaunchKernelGGL(k_adjoint_packs<128>, g, dim3(128), lb, hs, dm, W, rec, di, X, n0 + j); break;
-        case 256: hipLaunchKernelGGL(k_adjoint_packs<256>, g, dim3(256), lb, hs, dm, W, rec, di, X, n0 + j); break;
-        default: hipLaunchKernelGGL(k_adjoint_packs<512>, g, dim3(512), lb, hs, dm, W, rec, di, X, n0 + j); break;
+        case 64: hipLaunchKernelGGL(k_adjoint_packs<64>, g, dim3(64), lb, st, dm, W, rec, di, X, n0 + j); break;
+        case 128: hipLaunchKernelGGL(k_adjoint_packs<128>, g, dim3(128), lb, st, dm, W, rec, di, X, n0 + j); break;
+        case 256: hipLaunchKernelGGL(k_adjoint_packs<256>, g, dim3(256), lb, st, dm, W, rec, di, X, n0 + j); break;
+        default: hipLaunchKernelGGL(k_adjoint_packs<512>, g, dim3(512), lb, st, dm, W, rec, di, X, n0 + j); break;
       }
       HIPCHK(hipGetLastError());
     }
+    return ORCHARD_OK;
+  };
+  if (nseg == 0) return ORCHARD_OK;
+  // The recomputes run in order on the second stream, the reverse sweeps in order on the
+  // caller's: interval sg - 1 is recomputed while interval sg is reversed.  Reverse sweep
+  // sg waits for its recompute; recompute sg - 1 reuses the buffers of interval sg + 1,
+  // so it waits for that reverse sweep.
+  hipStream_t sa = m->s_aux;
+  HIPCHK(hipEventRecord(m->ev_in, hs));
+  HIPCHK(hipStreamWaitEvent(sa, m->ev_in, 0));
+  orchard_status_t r = recompute(nseg - 1, sa);
+  if (r) return r;
+  HIPCHK(hipEventRecord(m->ev_rec[(nseg - 1) & 1], sa));
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    if (sg >= 1) {
+      if (sg + 1 <= nseg - 1) HIPCHK(hipStreamWaitEvent(sa, m->ev_adj[(sg + 1) & 1], 0));
+      r = recompute(sg - 1, sa);
+      if (r) return r;
+      HIPCHK(hipEventRecord(m->ev_rec[(sg - 1) & 1], sa));
+    }
+    HIPCHK(hipStreamWaitEvent(hs, m->ev_rec[sg & 1], 0));
+    r = reverse(sg, hs);
+    if (r) return r;
+    HIPCHK(hipEventRecord(m->ev_adj[sg & 1], hs));
   }
   return ORCHARD_OK;
 }
