@@ -784,6 +784,14 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
   }
 }
 
+// Work-item of a level's k-th node on the LDS path: the level's first 64 nodes go to wave
+// (level mod waves), so narrow levels, which fill one wave, rotate over the SIMDs instead
+// of all landing on the first wave.
+template <int NT>
+__device__ __forceinline__ int lvl_lane(int t, int lv) {
+  return (t + NT - 64 * (lv & (NT / 64 - 1))) & (NT - 1);
+}
+
 // LDS exchange: at most one node per thread and level (level width <= lds_width <=
 // threads).  Each pass is software-pipelined: the loads of this thread's node on the
 // next level are issued before the current level's arithmetic; they read only static
@@ -794,7 +802,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
                                              int call_step0) {
   const int t = (int)threadIdx.x;
   {
-    int i = M.lvl_off[lb] + t;
+    int i = M.lvl_off[lb] + lvl_lane<NT>(t, lb);
     bool has = i < M.lvl_off[lb + 1];
     In1 cur{};
     if (has) cur = load1(M, S, I, i);
@@ -802,7 +810,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
       L.a = M.lvl_off[lv];
       L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
       L.b = (lv - lb) & 1;
-      const int in_ = M.lvl_off[lv + 1] + t;
+      const int in_ = M.lvl_off[lv + 1] + lvl_lane<NT>(t, lv + 1);
       const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
       In1 nxt{};
       if (hn) nxt = load1(M, S, I, in_);
@@ -817,7 +825,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
     const uint64_t kstep = splitmix64((uint64_t)n);
     apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
     {
-      int i = M.lvl_off[le - 1] + t;
+      int i = M.lvl_off[le - 1] + lvl_lane<NT>(t, le - 1);
       bool has = i < M.lvl_off[le];
       InU cur{};
       if (has) cur = loadU(M, S, I, L, i);
@@ -825,7 +833,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         L.a = M.lvl_off[lv];
         L.nbr = M.lvl_off[lv + 1];
         L.b = (lv - lb) & 1;
-        const int in_ = lv > lb ? M.lvl_off[lv - 1] + t : 0;
+        const int in_ = lv > lb ? M.lvl_off[lv - 1] + lvl_lane<NT>(t, lv - 1) : 0;
         const bool hn = lv > lb && in_ < M.lvl_off[lv];
         InU nxt{};
         if (hn) nxt = loadU(M, S, I, L, in_);
@@ -840,7 +848,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
     }
     __syncthreads();
     if (st + 1 < n_inner) {
-      int i = M.lvl_off[lb] + t;
+      int i = M.lvl_off[lb] + lvl_lane<NT>(t, lb);
       bool has = i < M.lvl_off[lb + 1];
       In2 c2{};
       In1 c1{};
@@ -849,7 +857,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         L.a = M.lvl_off[lv];
         L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
         L.b = (lv - lb) & 1;
-        const int in_ = M.lvl_off[lv + 1] + t;
+        const int in_ = M.lvl_off[lv + 1] + lvl_lane<NT>(t, lv + 1);
         const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
         In2 n2{};
         In1 n1{};
@@ -859,7 +867,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         i = in_; has = hn; c2 = n2; c1 = n1;
       }
     } else {
-      int i = M.lvl_off[lb] + t;
+      int i = M.lvl_off[lb] + lvl_lane<NT>(t, lb);
       bool has = i < M.lvl_off[lb + 1];
       In2 cur{};
       if (has) cur = load2(M, S, L, i);
@@ -867,7 +875,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         L.a = M.lvl_off[lv];
         L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
         L.b = (lv - lb) & 1;
-        const int in_ = M.lvl_off[lv + 1] + t;
+        const int in_ = M.lvl_off[lv + 1] + lvl_lane<NT>(t, lv + 1);
         const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
         In2 nxt{};
         if (hn) nxt = load2(M, S, L, in_);
