@@ -457,7 +457,7 @@ __device__ __forceinline__ void adjoint_pack_lds(const DevModel& M, const DevSta
                                                  int64_t n, int s_call) {
   const int t = (int)threadIdx.x;
   {
-    int i = M.lvl_off[le - 1] + t;
+    int i = M.lvl_off[le - 1] + lvl_lane<NT>(t, le - 1);
     bool has = i < M.lvl_off[le];
     InLU cur{};
     if (has) cur = load_lu(M, X, L, i);
@@ -465,7 +465,7 @@ __device__ __forceinline__ void adjoint_pack_lds(const DevModel& M, const DevSta
       L.a = M.lvl_off[lv];
       L.nbr = M.lvl_off[lv + 1];
       L.b = (lv - lb) & 1;
-      const int in_ = lv > lb ? M.lvl_off[lv - 1] + t : 0;
+      const int in_ = lv > lb ? M.lvl_off[lv - 1] + lvl_lane<NT>(t, lv - 1) : 0;
       const bool hn = lv > lb && in_ < M.lvl_off[lv];
       InLU nxt{};
       if (hn) nxt = load_lu(M, X, L, in_);
@@ -476,7 +476,7 @@ __device__ __forceinline__ void adjoint_pack_lds(const DevModel& M, const DevSta
   }
   __syncthreads();
   {
-    int i = M.lvl_off[lb] + t;
+    int i = M.lvl_off[lb] + lvl_lane<NT>(t, lb);
     bool has = i < M.lvl_off[lb + 1];
     InLD cur{};
     if (has) cur = load_ld(M, L, i);
@@ -484,7 +484,7 @@ __device__ __forceinline__ void adjoint_pack_lds(const DevModel& M, const DevSta
       L.a = M.lvl_off[lv];
       L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
       L.b = (lv - lb) & 1;
-      const int in_ = M.lvl_off[lv + 1] + t;
+      const int in_ = M.lvl_off[lv + 1] + lvl_lane<NT>(t, lv + 1);
       const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
       InLD nxt{};
       if (hn) nxt = load_ld(M, L, in_);
@@ -495,7 +495,7 @@ __device__ __forceinline__ void adjoint_pack_lds(const DevModel& M, const DevSta
   }
   __syncthreads();
   {
-    int i = M.lvl_off[le - 1] + t;
+    int i = M.lvl_off[le - 1] + lvl_lane<NT>(t, le - 1);
     bool has = i < M.lvl_off[le];
     InRV cur{};
     if (has) cur = load_rv(M, W, R0, I, X, L, i);
@@ -503,7 +503,7 @@ __device__ __forceinline__ void adjoint_pack_lds(const DevModel& M, const DevSta
       L.a = M.lvl_off[lv];
       L.nbr = M.lvl_off[lv + 1];
       L.b = (lv - lb) & 1;
-      const int in_ = lv > lb ? M.lvl_off[lv - 1] + t : 0;
+      const int in_ = lv > lb ? M.lvl_off[lv - 1] + lvl_lane<NT>(t, lv - 1) : 0;
       const bool hn = lv > lb && in_ < M.lvl_off[lv];
       InRV nxt{};
       if (hn) nxt = load_rv(M, W, R0, I, X, L, in_);

@@ -302,6 +302,14 @@ __device__ __forceinline__ void pst3(float* P, int nf, int f, int li, V3 v) {
   pst(P, nf, f, li, v.x); pst(P, nf, f + 1, li, v.y); pst(P, nf, f + 2, li, v.z);
 }
 
+// Work-item of a level's k-th node on the LDS path: the level's first 64 nodes go to wave
+// (level mod waves), so narrow levels, which fill one wave, rotate over the SIMDs instead
+// of all landing on the first wave.
+template <int NT>
+__device__ __forceinline__ int lvl_lane(int t, int lv) {
+  return (t + NT - 64 * (lv & (NT / 64 - 1))) & (NT - 1);
+}
+
 // Where a pass stands: the pack's scratch, its exchange buffer and the current level.
 struct Lvl {
   float* P;    // pack scratch

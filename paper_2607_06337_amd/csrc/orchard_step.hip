@@ -784,14 +784,6 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
   }
 }
 
-// Work-item of a level's k-th node on the LDS path: the level's first 64 nodes go to wave
-// (level mod waves), so narrow levels, which fill one wave, rotate over the SIMDs instead
-// of all landing on the first wave.
-template <int NT>
-__device__ __forceinline__ int lvl_lane(int t, int lv) {
-  return (t + NT - 64 * (lv & (NT / 64 - 1))) & (NT - 1);
-}
-
 // LDS exchange: at most one node per thread and level (level width <= lds_width <=
 // threads).  Each pass is software-pipelined: the loads of this thread's node on the
 // next level are issued before the current level's arithmetic; they read only static
