@@ -216,7 +216,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (trees are independent, "
-              "a multi-GPU run would shard the envs; see the design notes)", file=sys.stderr)
+              "a multi-GPU run would give each GPU a share of the envs balanced by segment count and depth)", file=sys.stderr)
         sys.exit(2)
 
     from orchard_inputs import make_batch, step_constants

@@ -178,8 +178,9 @@ def grad_targets(batch: Batch, rest_tips: np.ndarray, n_tips: int = 16,
     return idx, tgt
 
 
-# --- constants of the step shared by all workloads (readings of the paper, see the
-# design notes): time step, gravity, tether, damping and event parameters ---------------
+# --- constants of the step shared by all workloads (the paper's values where it gives
+# them, chosen readings where it does not): time step, gravity, tether, damping and event
+# parameters ---------------------------------------------------------------------------
 STEP_CONSTANTS = dict(
     dt=1e-3,
     gravity=(0.0, 0.0, -9.81),
