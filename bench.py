@@ -200,6 +200,17 @@ def row_scale(fwd_steps: int = 200, warm: int = 10, lead: int = 900, tail: int =
                                    backward_alg_GBps=round(lb / (bw / 1e3) / 1e9, 1)))
 
 
+def _copy_probe():
+    """Three launches of one plain elementwise kernel (256 MiB read, 256 MiB written): the
+    reference that scales the HBM counters."""
+    import torch
+    x = torch.ones(64 << 20, device="cuda")
+    for _ in range(3):
+        y = x * 1.0001
+    torch.cuda.synchronize()
+    del x, y
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +222,8 @@ def main():
     ap.add_argument("--no-row-scale", action="store_true")
     ap.add_argument("--tuning", type=str, default=None,
                     help="kernel mapping as JSON (skips the autotuner), e.g. the one a profile was taken with")
+    ap.add_argument("--row-scale-only", action="store_true",
+                    help="run only the orchard-row phases and print their figures (for per-phase counters)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB read + 256 MiB write kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -218,6 +231,14 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (trees are independent, "
               "a multi-GPU run would give each GPU a share of the envs balanced by segment count and depth)", file=sys.stderr)
         sys.exit(2)
+
+    if args.row_scale_only:
+        import torch
+        torch.cuda.init()
+        if args.copy_probe:
+            _copy_probe()
+        print(json.dumps(dict(row_scale=row_scale())), flush=True)
+        return
 
     from orchard_inputs import make_batch, step_constants
     t_gen = time.perf_counter()
@@ -252,11 +273,7 @@ def main():
         print(f"# plain per-step kernel: {plain['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     if args.copy_probe:
-        x = torch.ones(64 << 20, device="cuda")
-        for _ in range(3):
-            y = x * 1.0001  # one elementwise kernel: 256 MiB read, 256 MiB written
-        torch.cuda.synchronize()
-        del x, y
+        _copy_probe()
     ms_step = ms / args.steps
     value = batch.n_env * args.steps / (ms / 1e3)
     spl = tuning["steps_per_launch"]

@@ -35,6 +35,18 @@ def test_single_tree_1000_steps():
     assert not bad
 
 
+def test_stiffness_proportional_damping():
+    # the paper's solver damping Kd = c_d Kp with c_d = 0.1 s instead of the damping-ratio
+    # reading; each side derives Kd itself.  Two trees and a chain, 500 steps
+    b = assemble([gen_tree(5, 64, 8), gen_tree(6, 150, 20), chain_tree(10, length=0.2, radius=0.02)])
+    errs, bad, n_band, m, *_ = run_parity(b, step_constants(damping_cd=0.1), 500, 50)
+    wq, wqd = _report("damping_cd", errs, bad, n_band)
+    assert wq < TOL and wqd < TOL
+    assert not bad
+    kp, kd = (t.cpu().numpy().astype(np.float64) for t in m.default_params())
+    assert np.allclose(kd, 0.1 * kp, rtol=1e-6, atol=0)
+
+
 def test_pull_workload_full_batch_sampled():
     # all 1024 trees on the GPU; pulls on 10 % of apples from step 200; 40 envs
     # (stratified by size) against the oracle over 1000 steps
