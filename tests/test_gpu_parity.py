@@ -143,6 +143,18 @@ def test_degenerate_trees():
     assert wq < TOL and wqd < TOL
 
 
+def test_deep_horizontal_chain():
+    # 300 levels of width one (a 6 m horizontal cantilever of 2 cm segments) next to a
+    # small tree: the deepest level chain a pack can have, in the benchmark mapping
+    from bench import BENCH_TUNING
+    side = (np.cos(np.pi / 4), np.sin(np.pi / 4), 0.0, 0.0)
+    b = assemble([chain_tree(300, length=0.02, radius=0.05, root_quat=side), gen_tree(2, 60, 6)])
+    errs, bad, n_band, *_ = run_parity(b, step_constants(), 200, 20, tuning=BENCH_TUNING)
+    wq, wqd = _report("chain300", errs, bad, n_band)
+    assert wq < TOL and wqd < TOL
+    assert not bad
+
+
 def test_nonfinite_env_is_flagged_and_frozen():
     from paper_2607_06337_amd import Model
     b = make_batch("uneven8192", env_ids=range(6))
