@@ -29,10 +29,10 @@ sys.path.insert(0, ROOT)
 
 # kernel mapping used by the full-size parity test and the adjoint ratio, and the first of
 # the candidates the autotuner times for the benchmark
-BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=10, persistent=0, lds_width=240)
+BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=50, persistent=0, lds_width=240)
 # candidates of the autotuner: workgroup size, LDS width, steps per launch (a multi-step
 # launch fuses the second down pass of a step with the first of the next)
-AUTOTUNE_CANDIDATES = [BENCH_TUNING, dict(BENCH_TUNING, steps_per_launch=1),
+AUTOTUNE_CANDIDATES = [BENCH_TUNING, dict(BENCH_TUNING, steps_per_launch=10), dict(BENCH_TUNING, steps_per_launch=1),
                        dict(BENCH_TUNING, lds_width=256), dict(BENCH_TUNING, lds_width=224),
                        dict(BENCH_TUNING, lds_width=192), dict(BENCH_TUNING, threads=128, lds_width=128),
                        dict(BENCH_TUNING, lds_width=0), dict(BENCH_TUNING, threads=128, lds_width=0)]
@@ -255,7 +255,7 @@ def main():
         tuning, tune_log = dict(DEFAULT_TUNING, **json.loads(args.tuning)), None
     else:
         t_tune = time.perf_counter()
-        tuning, timings = autotune(batch, consts, AUTOTUNE_CANDIDATES, n_warm=3, n_steps=20)
+        tuning, timings = autotune(batch, consts, AUTOTUNE_CANDIDATES, n_warm=3, n_steps=100)
         tune_log = [dict(c, ms_per_step=round(ms, 4)) for c, ms in timings]
         print(f"# autotune {time.perf_counter() - t_tune:.1f} s: {tuning}", file=sys.stderr, flush=True)
     tuning = {k: tuning[k] for k in ("threads", "pack_fill", "steps_per_launch", "persistent", "lds_width", "pack_skew")}

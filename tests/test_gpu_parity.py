@@ -94,6 +94,7 @@ def test_row_scale_batch_one_launch():
     dict(threads=64, pack_fill=1.0, lds_width=64), dict(threads=256, pack_fill=2.0, lds_width=256),
     dict(threads=128, pack_fill=1.0, lds_width=0), dict(threads=128, pack_fill=1.0, lds_width=48),
     dict(threads=256, pack_fill=1.0, lds_width=0, steps_per_launch=5),
+    dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=50),
     dict(threads=128, pack_fill=1.0, lds_width=128, pack_skew=1), dict(threads=64, pack_fill=2.0, lds_width=64, pack_skew=1)])
 def test_mappings_are_bitwise_identical(tuning):
     # the mapping (workgroup per tree, exchange through LDS or global scratch) changes
