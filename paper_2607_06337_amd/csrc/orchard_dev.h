@@ -31,8 +31,7 @@ enum : int {
   F_A1 = 31,        // 3: joint axis y (world)
   F_WV = 34,        // 6: angular velocity and joint-point velocity (the velocity-product
                     //    acceleration and the bias are formed from them again)
-  F_Z = 40,         // 3: body axis z (world)
-  F_FLG = 43,       // 1: flags of the step (broken, snapped, broken at the start, rupture count)
+  F_FLG = 40,       // 1: flags of the step (broken, snapped, broken at the start, rupture count)
   // up-pass publication (27): articulated inertia and bias at the node's joint point
   F_IA = 60,        // 6: A (rotational block, sym)
   F_IB = 66,        // 9: B (coupling block, row major)
@@ -44,10 +43,12 @@ enum : int {
   F_DU = 99,        // 2: D^-1 u, u = tau - S^T p^A
   F_DI = 101,       // 3: D^-1 (00 01 11), stored only in save mode (the adjoint's solves)
   // node-private outputs of the down 1 and up passes, each a contiguous range of fields
-  N_OUT1 = 16,      // F_A0 .. F_FLG
+  N_OUT1 = 13,      // F_A0 .. F_FLG
   N_OUTU = 14,      // F_WM .. F_DU + 1
   F_SFRZ = 104,     // 1: the env's frozen flag at the start of the step, stored in save mode
   F_SSNP = 105,     // 1: the snapped flag, stored in save mode
+  F_Z = 106,        // 3: body axis z (world), stored in save mode only: the step's later
+                    //    passes rebuild it from F_A0, F_A1 and theta_y
   N_FIELDS = 128,
   // Nodes that carry apples (a minority) keep their apple data in two dense arrays
   // indexed by the node's apple-node index, so it moves in whole sectors:
@@ -206,8 +207,9 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
 }
 __device__ __forceinline__ V3 fma3(float s, V3 a, V3 b) { return V3{fmaf(s, a.x, b.x), fmaf(s, a.y, b.y), fmaf(s, a.z, b.z)}; }
 
-static_assert(F_A1 == F_A0 + 3 && F_WV == F_A1 + 3 && F_Z == F_WV + 6 && F_FLG == F_Z + 3 &&
-              F_FLG + 1 - F_A0 == N_OUT1, "down 1 outputs are one field range");
+static_assert(F_A1 == F_A0 + 3 && F_WV == F_A1 + 3 && F_FLG == F_WV + 6 && F_FLG + 1 - F_A0 == N_OUT1,
+              "down 1 outputs are one field range");
+static_assert(F_Z > F_SSNP && F_Z + 3 <= N_FIELDS, "the saved body axis sits among the save-mode fields");
 static_assert(F_DU == F_WM + 12 && F_DU + 2 - F_WM == N_OUTU, "up outputs are one field range");
 static_assert(F_AT == F_SNAP + 1 && N_PUB1 == F_SNAP + 1 && N_PUBD == F_AT + 6 && N_PUBD <= X_STRIDE &&
               N_PUBD <= F_A0 && F_FLG < F_IA, "down-pass publication slot, then node-private fields");

@@ -39,6 +39,17 @@ __device__ __forceinline__ void own_inertia(float4 geo, V3 z, V3& ho, Sym3& Jo) 
             dJ * z.y * z.z};
 }
 
+// Body axis z = R e_z from the joint axes a0 = J e_x and a1 = R e_y and the angle theta_y:
+// R = [a0, a1, a0 x a1] R_y(theta_y), so z = sin(theta_y) a0 + cos(theta_y) (a0 x a1), with
+// sin and cos formed from the half angle as down 1 forms them.  The up and second down
+// passes rebuild z this way instead of loading it.
+__device__ __forceinline__ V3 body_z(V3 a0, V3 a1, float qy) {
+  float sh, ch;
+  sincosf(0.5f * qy, &sh, &ch);
+  const float sy = 2.f * sh * ch, cy = 1.f - 2.f * sh * sh;
+  return fma3(sy, a0, cy * cross(a0, a1));
+}
+
 // Velocity-product acceleration (ang, lin) at the joint point of a body with angular
 // velocity wi and joint-point velocity v, whose joint turns at rates qd about a0, a1.
 __device__ __forceinline__ void vel_product(V3 a0, V3 a1, float2 qd, V3 wi, V3 v, V3& cang, V3& clin) {
@@ -215,6 +226,7 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
       pst3(P, nf, F_VT, li, v + cross(wi, lz));
     }
     pst(P, nf, F_SSNP, li, snp ? 1.f : 0.f);
+    pst3(P, nf, F_Z, li, z);
     pst3(P, nf, F_SAVP, li, Ava); pst3(P, nf, F_SAVP + 3, li, Avl);
   }
 
@@ -233,7 +245,7 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
 
   // node-private outputs (fields F_A0 .. F_FLG), stored by the caller; the flags carry the
   // rupture test's result for the up pass, which forms the spring terms and writes the events
-  const float out[N_OUT1] = {a0.x, a0.y, a0.z, a1.x, a1.y, a1.z, wi.x, wi.y, wi.z, v.x, v.y, v.z, z.x, z.y, z.z,
+  const float out[N_OUT1] = {a0.x, a0.y, a0.z, a1.x, a1.y, a1.z, wi.x, wi.y, wi.z, v.x, v.y, v.z,
                              flg_pack(brk != 0, snp, brk0, cnt1)};
   for (int k = 0; k < N_OUT1; ++k) o[k] = out[k];
 }
@@ -428,7 +440,7 @@ __device__ __forceinline__ TopoU topo_up(const DevModel& M, int i) {
 struct InU {
   TopoU topo;
   float4 geo;
-  V3 z, a0, a1, wi, v;
+  V3 a0, a1, wi, v;
   float2 q, qd;
   float kp, kd, flg;
   uint32_t hk0, hk1;  // random-wrench key
@@ -444,7 +456,6 @@ __device__ __forceinline__ InU loadU(const DevModel& M, const DevState& S, const
   u.qd = at(S.qd, (uint32_t)i);
   u.kp = at(I.kp, (uint32_t)i);
   u.kd = at(I.kd, (uint32_t)i);
-  u.z = pld3(P, nf, F_Z, li);
   u.flg = pld(P, nf, F_FLG, li);
   u.a0 = pld3(P, nf, F_A0, li);
   u.a1 = pld3(P, nf, F_A1, li);
@@ -466,8 +477,8 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevState& S, co
   // event writes at the end
   const uint32_t stat = at(S.status, (uint32_t)in.env);
   const Flags fl = flg_unpack(in.flg);
-  const V3 a0 = in.a0, a1 = in.a1;
-  const V3 r = in.geo.x * in.z;  // l z, joint point -> tip
+  const V3 a0 = in.a0, a1 = in.a1, z = body_z(a0, a1, in.q.y);
+  const V3 r = in.geo.x * z;  // l z, joint point -> tip
   // the apple sums of a node that carries apples are loaded here rather than a level
   // ahead (they would double in the prefetch registers); their first use comes after the
   // bias and the children's gather
@@ -480,12 +491,12 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevState& S, co
   V3 ca, cl, pang, plin;
   vel_product(a0, a1, in.qd, in.wi, in.v, ca, cl);
   const bool snp = fl.snp;
-  body_bias(M, I, i, kstep, s_call, in.geo, in.z, in.wi, in.v, snp, (uint64_t)in.hk0 | ((uint64_t)in.hk1 << 32), pang,
+  body_bias(M, I, i, kstep, s_call, in.geo, z, in.wi, in.v, snp, (uint64_t)in.hk0 | ((uint64_t)in.hk1 << 32), pang,
             plin);
   // own body plus the apples' virtual masses and reactions (zero without apples)
   V3 ho;
   Sym3 Jo;
-  own_inertia(in.geo, in.z, ho, Jo);
+  own_inertia(in.geo, z, ho, Jo);
   const float mo = in.geo.y + e0.x;
   ho = ho + v3(e0.y, e0.z, e0.w);
   Jo.xx += e1.x; Jo.yy += e1.y; Jo.zz += e1.z; Jo.xy += e1.w; Jo.xz += e2.x; Jo.yz += e2.y;
@@ -603,7 +614,7 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevState& S, co
 struct In2 {
   int par;
   float du0, du1, l;
-  V3 wi, v, W0a, W0l, W1a, W1l, a0, a1, z;
+  V3 wi, v, W0a, W0l, W1a, W1l, a0, a1;
   float2 q, qd;
 };
 __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const Lvl& L, int i) {
@@ -622,7 +633,6 @@ __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const
   d.du1 = pld(P, nf, F_DU + 1, li);
   d.a0 = pld3(P, nf, F_A0, li);
   d.a1 = pld3(P, nf, F_A1, li);
-  d.z = pld3(P, nf, F_Z, li);
   d.q = at(S.q, (uint32_t)i);
   d.qd = at(S.qd, (uint32_t)i);
   return d;
@@ -637,7 +647,7 @@ __device__ __forceinline__ void node_down2(const DevModel& M, const DevState& S,
   const int nf = M.scr_nf, li = i - L.i0;
   const int par = in.par;
   const V3 W0a = in.W0a, W0l = in.W0l, W1a = in.W1a, W1l = in.W1l;
-  const V3 a0 = in.a0, a1 = in.a1, lz = in.l * in.z;
+  const V3 a0 = in.a0, a1 = in.a1, lz = in.l * body_z(a0, a1, in.q.y);
   float2 q = in.q, qd = in.qd;
   V3 ca, cl;
   vel_product(a0, a1, qd, in.wi, in.v, ca, cl);
