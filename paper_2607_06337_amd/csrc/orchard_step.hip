@@ -617,12 +617,20 @@ struct In2 {
   V3 wi, v, W0a, W0l, W1a, W1l, a0, a1;
   float2 q, qd;
 };
+// TOPO: also the parent and the length (a fused pass takes them from the first down pass's
+// record instead)
+template <bool TOPO = true>
 __device__ __forceinline__ In2 load2(const DevModel& M, const DevState& S, const Lvl& L, int i) {
   const int nf = M.scr_nf, li = i - L.i0;
   const float* P = L.P;
   In2 d;
-  d.par = at(M.par, (uint32_t)i);
-  d.l = at(M.len, (uint32_t)i);
+  if constexpr (TOPO) {
+    d.par = at(M.par, (uint32_t)i);
+    d.l = at(M.len, (uint32_t)i);
+  } else {
+    d.par = -1;
+    d.l = 0.f;
+  }
   d.wi = pld3(P, nf, F_WV, li);
   d.v = pld3(P, nf, F_WV + 3, li);
   d.W0a = pld3(P, nf, F_WM, li);
@@ -725,8 +733,11 @@ __device__ __forceinline__ void pass_down2(const DevModel& M, const DevState& S,
 // once; the joint state goes from one part to the other in registers; the flags float
 // carries the next step's snapped flag and this step's frozen flag.
 template <bool XL>
-__device__ __forceinline__ void pass_fused(const DevModel& M, const DevState& S, const Lvl& L, int i, const In2& in2,
+__device__ __forceinline__ void pass_fused(const DevModel& M, const DevState& S, const Lvl& L, int i, const In2& in2_,
                                            const In1& in1) {
+  In2 in2 = in2_;
+  in2.par = in1.nr.par;
+  in2.l = in1.nr.l;
   float pv[N_PUBD], pv1[N_PUB1], pv2[7];
   if (in2.par >= 0) {
     xload<XL>(L, F_R, in2.par, pv);
@@ -786,7 +797,7 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
       L.a = M.lvl_off[lv];
       const int e = M.lvl_off[lv + 1];
       for (int i = L.a + t; i < e; i += NT) {
-        if (fuse) pass_fused<false>(M, S, L, i, load2(M, S, L, i), load1<false>(M, S, I, i));
+        if (fuse) pass_fused<false>(M, S, L, i, load2<false>(M, S, L, i), load1<false>(M, S, I, i));
         else pass_down2<false>(M, S, L, i, load2(M, S, L, i));
       }
       __syncthreads();
@@ -854,7 +865,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
       bool has = i < M.lvl_off[lb + 1];
       In2 c2{};
       In1 c1{};
-      if (has) { c2 = load2(M, S, L, i); c1 = load1<false>(M, S, I, i); }
+      if (has) { c2 = load2<false>(M, S, L, i); c1 = load1<false>(M, S, I, i); }
       for (int lv = lb; lv < le; ++lv) {
         L.a = M.lvl_off[lv];
         L.nbr = lv > lb ? M.lvl_off[lv - 1] : L.a;
@@ -863,7 +874,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         const bool hn = lv + 1 < le && in_ < M.lvl_off[lv + 2];
         In2 n2{};
         In1 n1{};
-        if (hn) { n2 = load2(M, S, L, in_); n1 = load1<false>(M, S, I, in_); }
+        if (hn) { n2 = load2<false>(M, S, L, in_); n1 = load1<false>(M, S, I, in_); }
         if (has) pass_fused<true>(M, S, L, i, c2, c1);
         if (lv + 1 < le) lds_barrier();
         i = in_; has = hn; c2 = n2; c1 = n1;
