@@ -19,6 +19,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -52,10 +53,18 @@ def algorithmic_bytes(batch) -> int:
     return SEG_BYTES * batch.n_seg + APPLE_BYTES * batch.n_apple
 
 
+def code_without_comments(text: str) -> str:
+    """C++ source with comments and trailing blanks removed: two sources that differ only in
+    their comments compile to the same kernel."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("paper_2607_06337_amd/csrc/orchard_step.hip", "paper_2607_06337_amd/csrc/orchard_dev.h"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        h.update(code_without_comments(open(os.path.join(ROOT, f)).read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -304,9 +304,9 @@ __device__ __forceinline__ void pst3(float* P, int nf, int f, int li, V3 v) {
   pst(P, nf, f, li, v.x); pst(P, nf, f + 1, li, v.y); pst(P, nf, f + 2, li, v.z);
 }
 
-// Work-item of a level's k-th node on the LDS path: the level's first 64 nodes go to wave
-// (level mod waves), so narrow levels, which fill one wave, rotate over the SIMDs instead
-// of all landing on the first wave.
+// Level-local node index that work-item t takes on the LDS path: the level's first 64
+// nodes go to wave (level mod waves), so narrow levels, which fill one wave, rotate over
+// the SIMDs instead of all landing on the first wave.
 template <int NT>
 __device__ __forceinline__ int lvl_lane(int t, int lv) {
   return (t + NT - 64 * (lv & (NT / 64 - 1))) & (NT - 1);
