@@ -71,3 +71,21 @@ def test_autotune_and_graph_reject_bad_arguments():
     assert L.orchard_graph_launch(None, None) == 1
     assert L.orchard_graph_create(None, None, None, None, 5, None) == 1
     L.orchard_graph_destroy(None)
+
+
+def test_create_rejects_empty_and_null_descriptions():
+    # an empty batch and a missing descriptor are argument errors, reported before any
+    # device work
+    from paper_2607_06337_amd import load_library
+    from paper_2607_06337_amd.orchard import _desc
+    L = load_library()
+    keep = []
+    d = _desc(assemble([gen_tree(1, 20, 3)]), step_constants(), keep)
+    out = C.c_void_p()
+    d.n_env = 0
+    assert L.orchard_model_create(C.byref(d), None, C.byref(out)) == 1
+    assert not out.value
+    assert L.orchard_model_create(None, None, C.byref(out)) == 1
+    d.n_env = 1
+    assert L.orchard_model_create(C.byref(d), None, None) == 1
+    assert L.orchard_last_error()
