@@ -160,7 +160,7 @@ __device__ __forceinline__ InRV load_rv(const DevModel& M, const DevState& W, co
   const float* P = L.P;
   const int4 topo = at(M.ntopo, (uint32_t)i);
   InRV r;
-  r.par = topo.x;
+  r.par = at(M.par, (uint32_t)i);
   r.cb = topo.y;
   r.ce = topo.y + (topo.z & 0xFFFF);
   r.a_beg = at(M.apple_beg, (uint32_t)i);

@@ -521,7 +521,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     nrec[i].inv_mmax = inv_mmax;
     nrec[i].par = par_i[i];
     nrec[i].anode = anode[i];
-    ntopo[i] = make_int4(par_i[i], child_i[i], nchild_i[i] | (napp << 16), anode[i]);
+    ntopo[i] = make_int4(env_i[i], child_i[i], nchild_i[i] | (napp << 16), anode[i]);
   }
   std::vector<AppleRec> arec(NA);
   for (int64_t k = 0; k < NA; ++k) {

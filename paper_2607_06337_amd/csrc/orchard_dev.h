@@ -113,7 +113,7 @@ struct DevModel {
   const int32_t* pack_lds;   // 1: every level of the pack fits the workgroup (LDS publications)
   const int32_t* pack_apl;   // [n_pack+1] apples of pack p: pack_apl[p] .. pack_apl[p+1]-1
   const NodeRec* nrec;       // per node (internal order)
-  const int4* ntopo;         // per node: (parent, first child, children | apples << 16, apple-node index)
+  const int4* ntopo;         // per node: (env, first child, children | apples << 16, apple-node index)
   const AppleRec* arec;      // per apple (internal order)
   // per node (internal order)
   const int32_t* par;        // parent node, -1 = world

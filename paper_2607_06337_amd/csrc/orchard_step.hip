@@ -430,11 +430,11 @@ __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S
 // ------------------------------------------------------------------------------------------
 // the part of a node's topology word the up pass reads
 struct TopoU {
-  int child, cnt, an;  // first child, children | apples << 16, apple-node index
+  int env, child, cnt, an;  // env, first child, children | apples << 16, apple-node index
 };
 __device__ __forceinline__ TopoU topo_up(const DevModel& M, int i) {
-  const int* w = reinterpret_cast<const int*>(&at(M.ntopo, (uint32_t)i));
-  return TopoU{w[1], w[2], w[3]};
+  const int4 w = at(M.ntopo, (uint32_t)i);
+  return TopoU{w.x, w.y, w.z, w.w};
 }
 // up-pass inputs: the node's own data from down 1, its static record and state
 struct InU {
@@ -444,7 +444,6 @@ struct InU {
   float2 q, qd;
   float kp, kd, flg;
   uint32_t hk0, hk1;  // random-wrench key
-  int env;
 };
 __device__ __forceinline__ InU loadU(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L, int i) {
   const int nf = M.scr_nf, li = i - L.i0;
@@ -464,7 +463,6 @@ __device__ __forceinline__ InU loadU(const DevModel& M, const DevState& S, const
   const uint64_t hk = at(M.hkey, (uint32_t)i);
   u.hk0 = (uint32_t)hk;
   u.hk1 = (uint32_t)(hk >> 32);
-  u.env = at(M.env, (uint32_t)i);
   return u;
 }
 
@@ -475,7 +473,7 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevState& S, co
   const TopoU topo = in.topo;
   // the env's frozen flag at the start of the step (bit 0 changes only in down 2) decides the
   // event writes at the end
-  const uint32_t stat = at(S.status, (uint32_t)in.env);
+  const uint32_t stat = at(S.status, (uint32_t)in.topo.env);
   const Flags fl = flg_unpack(in.flg);
   const V3 a0 = in.a0, a1 = in.a1, z = body_z(a0, a1, in.q.y);
   const V3 r = in.geo.x * z;  // l z, joint point -> tip
