@@ -63,3 +63,29 @@ def test_autotune_returns_the_fastest_candidate(tmp_path):
     best2, timings2 = autotune(b, c, cands, n_warm=2, n_steps=5, cache=cache)
     assert best2 == best and [t[1] for t in timings2] == ms
     assert len(json.load(open(cache))) == 1
+
+
+@pytest.mark.parametrize("tuning", [dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=50),
+                                    dict(threads=128, pack_fill=1.0, lds_width=0),
+                                    dict(threads=64, pack_fill=2.0, lds_width=64, pack_skew=1)])
+def test_internal_order_is_a_parent_first_permutation(tuning):
+    # the passes rely on the internal order: every segment and apple exactly once, each
+    # segment after its parent, and the reported depth the deepest tree's
+    from paper_2607_06337_amd import Model
+    b = make_batch("uneven8192", env_ids=range(200))
+    m = Model(b, step_constants("uneven8192"), tuning)
+    assert np.array_equal(np.sort(m.seg_map), np.arange(b.n_seg))
+    assert np.array_equal(np.sort(m.apple_map), np.arange(b.n_apple))
+    inv = np.empty(b.n_seg, np.int64)
+    inv[m.seg_map] = np.arange(b.n_seg)
+    env = np.repeat(np.arange(b.n_env), np.diff(b.seg_offset))
+    par = b.seg_parent.astype(np.int64)
+    has = par >= 0
+    g = np.flatnonzero(has)
+    assert np.all(inv[b.seg_offset[env[g]] + par[g]] < inv[g])
+    depth = np.zeros(b.n_seg, np.int64)
+    for k in range(b.n_seg):
+        if par[k] >= 0:
+            depth[k] = depth[b.seg_offset[env[k]] + par[k]] + 1
+    assert m.max_depth == depth.max() + 1
+    assert 1 <= m.n_pack <= b.n_env
