@@ -227,7 +227,10 @@ orchard_status_t orchard_step_backward(orchard_model_t model, const float* ckpt,
 
 /* Tip positions p_b + R_b (0, 0, l_b) (world frame, tree base at the origin) of the
  * segments node[k] (internal indices, device int32 [n_tips]) at joint angles q
- * (device [n_seg][2]) into out (device float [n_tips][3]).  Stream-ordered. */
+ * (device [n_seg][2]) into out (device float [n_tips][3]).  Stream-ordered.
+ * Precondition: the model was created with adjoint support (tuning.adjoint_ckpt_max
+ * >= 1), whose scratch holds the tip kernels' fields; otherwise ORCHARD_ERR_INVALID_ARG
+ * is returned before any device work.  The same holds for orchard_tips_backward. */
 orchard_status_t orchard_tips(orchard_model_t model, const float* q, int32_t n_tips, const int32_t* node, float* out,
                               orchard_stream_t stream);
 

@@ -782,10 +782,12 @@ void oracle_record_free(void* r) { delete static_cast<std::vector<StepRecord>*>(
 // Loss L = sum_k |tip_k(q_T) - target_k|^2 after n_steps from the given state (flags
 // zero at start).  If rec_in is non-null the switches are replayed from it; if rec_out
 // is non-null they are recorded there.  F: [n_steps][A][3] apple forces or null.
+// w_state (nullable, [4S + 6A]): adds the linear term w_state . S_T of the final state
+// (q, qd, apple position state, apple velocity) to the loss.
 double oracle_loss(void* m, int env, int64_t step0, int n_steps, const double* q0, const double* qd0,
                    const double* ax0, const double* av0, const double* kp, const double* kd, const double* F,
-                   int n_tips, const int32_t* tip_seg, const double* target, void* rec_in, void* rec_out,
-                   double* q_final) {
+                   int n_tips, const int32_t* tip_seg, const double* target, const double* w_state, void* rec_in,
+                   void* rec_out, double* q_final) {
   Model* M = static_cast<Model*>(m);
   const Tree& t = M->trees[env];
   EnvRun r{t, M->g, env, step0, n_steps};
@@ -794,7 +796,10 @@ double oracle_loss(void* m, int env, int64_t step0, int n_steps, const double* q
                  static_cast<std::vector<StepRecord>*>(rec_in));
   const std::vector<double>& last = states.back();
   if (q_final) std::copy(last.begin(), last.begin() + 4 * t.S, q_final);
-  return loss_of(t, last.data(), n_tips, tip_seg, target);
+  double L = loss_of(t, last.data(), n_tips, tip_seg, target);
+  if (w_state)
+    for (size_t k = 0; k < last.size(); ++k) L += w_state[k] * last[k];
+  return L;
 }
 
 // Gradient of the loss above with the forward's switches frozen.  Outputs (accumulated
@@ -802,8 +807,8 @@ double oracle_loss(void* m, int env, int64_t step0, int n_steps, const double* q
 // g_state0 [4S + 6A] = (q, qd, apple position state, apple velocity) (nullable).
 double oracle_adjoint(void* m, int env, int64_t step0, int n_steps, const double* q0, const double* qd0,
                       const double* ax0, const double* av0, const double* kp, const double* kd, const double* F,
-                      int n_tips, const int32_t* tip_seg, const double* target, double* g_kp, double* g_kd,
-                      double* g_F, double* g_state0) {
+                      int n_tips, const int32_t* tip_seg, const double* target, const double* w_state, double* g_kp,
+                      double* g_kd, double* g_F, double* g_state0) {
   Model* M = static_cast<Model*>(m);
   const Tree& t = M->trees[env];
   const int S = t.S, A = t.A, NX = 4 * S + 6 * A;
@@ -830,6 +835,8 @@ double oracle_adjoint(void* m, int env, int64_t step0, int n_steps, const double
     tp.reverse();
     for (int k = 0; k < 2 * S; ++k) xbar[k] = tp.adj[q[k].i];
     tp.clear();
+    if (w_state)
+      for (int k = 0; k < NX; ++k) { xbar[k] += w_state[k]; L += w_state[k] * states.back()[k]; }
   }
   for (int s = n_steps - 1; s >= 0; --s) {
     const std::vector<double>& x = states[s];
@@ -862,6 +869,126 @@ double oracle_adjoint(void* m, int env, int64_t step0, int n_steps, const double
   tape() = nullptr;
   if (g_state0) for (int k = 0; k < NX; ++k) g_state0[k] += xbar[k];
   return L;
+}
+
+}  // extern "C"
+
+// ======================================================================================
+// Access points for the pins: the in-step normal draws, the pivots of the L^T D L
+// factorisation, and the dot-product test of one step's tangent-linear and reverse modes
+// ======================================================================================
+#include "dual.hpp"
+
+namespace orc {
+
+// Entry-flag views for a single step of one tree (counters start at zero).
+struct OneStepEvents {
+  std::vector<uint8_t> broken, cnt, det, cntp, cntt, path;
+  std::vector<int32_t> bstep, dstep;
+  uint32_t status = 0;
+  OneStepEvents(const Tree& t, const uint8_t* broken0, const uint8_t* det0)
+      : broken(t.S, 0), cnt(t.S, 0), det(t.A, 0), cntp(t.A, 0), cntt(t.A, 0), path(t.A, 0), bstep(t.S, -1), dstep(t.A, -1) {
+    if (broken0) std::copy(broken0, broken0 + t.S, broken.begin());
+    if (det0) std::copy(det0, det0 + t.A, det.begin());
+  }
+  EventRefs refs() { return EventRefs{broken.data(), cnt.data(), det.data(), cntp.data(), cntt.data(), path.data(), bstep.data(), dstep.data(), &status}; }
+};
+
+}  // namespace orc
+
+extern "C" {
+
+// Three standard normals of the in-step random force of (env, step, segment).
+void oracle_rng_normals(uint64_t seed, int env, int64_t step, int seg, double* z) {
+  rng_normals(seed, env, step, seg, z);
+}
+
+// Pivots D (per DoF, [2S]) of the leaf-first L^T D L factorisation of H(q) + diag(dg).
+void oracle_ltdl_pivots(void* m, int env, const double* q, const double* dg, double* D) {
+  Model* M = static_cast<Model*>(m);
+  const Tree& t = M->trees[env];
+  Kin<double> K;
+  fk(t, q, K);
+  std::vector<double> H;
+  crba(t, K, H);
+  for (int k = 0; k < 2 * t.S; ++k) hent(t, H, k, k) += dg[k];
+  ltdl_factor(t, H);
+  for (int k = 0; k < 2 * t.S; ++k) D[k] = hent(t, H, k, k);
+}
+
+// Dot-product test of one step of tree env at step index n and state x = (q, qd, apple
+// position state, apple velocity) [4S + 6A], with parameters kp, kd [S] and apple forces
+// F [A][3] (nullable).  The switches the step takes from the entry flags broken0 [S] and
+// det0 [A] (nullable: none) are recorded once and frozen in both modes.  Directions
+// vx [4S + 6A], vkp, vkd [S], vF [A][3]; output weights w [4S + 6A].
+// out[0] = <J v, w> (tangent-linear), out[1] = <v, J^T w> (reverse mode); out[2..5] = the
+// numbers of broken joints, detached apples, clamped reactions and capped body forces the
+// step used.
+void oracle_step_dot(void* m, int env, int64_t n, const double* x, const double* kp, const double* kd, const double* F,
+                     const uint8_t* broken0, const uint8_t* det0, const double* vx, const double* vkp,
+                     const double* vkd, const double* vF, const double* w, double* out) {
+  Model* M = static_cast<Model*>(m);
+  const Tree& t = M->trees[env];
+  const int S = t.S, A = t.A, N2 = 2 * S, N3 = 3 * A;
+  Switches sw;
+  {
+    OneStepEvents E(t, broken0, det0);
+    EventRefs ev = E.refs();
+    std::vector<double> aq(4 * A, 0.0), aw(N3, 0.0), qo(N2), qdo(N2), axo(N3), avo(N3), aqo(4 * A), awo(N3);
+    for (int a = 0; a < A; ++a) aq[4 * a] = 1.0;
+    step_tree<double>(t, M->g, env, n, x, x + N2, x + 2 * N2, x + 2 * N2 + N3, aq.data(), aw.data(), kp, kd, nullptr,
+                      F, qo.data(), qdo.data(), axo.data(), avo.data(), aqo.data(), awo.data(), &ev, nullptr, &sw,
+                      nullptr);
+  }
+  const int NX = 2 * N2 + 2 * N3;
+  auto count = [](const std::vector<uint8_t>& f) { double c = 0; for (uint8_t x : f) c += x ? 1 : 0; return c; };
+  out[2] = count(sw.broken); out[3] = count(sw.detached); out[4] = count(sw.clamped); out[5] = count(sw.capped);
+  // tangent-linear
+  {
+    OneStepEvents E(t, broken0, det0);
+    EventRefs ev = E.refs();
+    std::vector<DU> xs(NX), kps(S), kds(S), Fs(F ? N3 : 0), aq(4 * A, DU(0.0)), aw(N3, DU(0.0));
+    for (int k = 0; k < NX; ++k) xs[k] = DU(x[k], vx[k]);
+    for (int i = 0; i < S; ++i) { kps[i] = DU(kp[i], vkp[i]); kds[i] = DU(kd[i], vkd[i]); }
+    for (int k = 0; k < (int)Fs.size(); ++k) Fs[k] = DU(F[k], vF ? vF[k] : 0.0);
+    for (int a = 0; a < A; ++a) aq[4 * a] = DU(1.0);
+    std::vector<DU> qo(N2), qdo(N2), axo(N3), avo(N3), aqo(4 * A), awo(N3);
+    step_tree<DU>(t, M->g, env, n, xs.data(), xs.data() + N2, xs.data() + 2 * N2, xs.data() + 2 * N2 + N3, aq.data(),
+                  aw.data(), kps.data(), kds.data(), nullptr, F ? Fs.data() : nullptr, qo.data(), qdo.data(),
+                  axo.data(), avo.data(), aqo.data(), awo.data(), &ev, nullptr, nullptr, &sw);
+    double s = 0.0;
+    for (int k = 0; k < N2; ++k) s += w[k] * qo[k].d + w[N2 + k] * qdo[k].d;
+    for (int k = 0; k < N3; ++k) s += w[2 * N2 + k] * axo[k].d + w[2 * N2 + N3 + k] * avo[k].d;
+    out[0] = s;
+  }
+  // reverse mode
+  {
+    OneStepEvents E(t, broken0, det0);
+    EventRefs ev = E.refs();
+    Tape tp;
+    tape() = &tp;
+    std::vector<AD> xs(NX), kps(S), kds(S), Fs(F ? N3 : 0), aq(4 * A, AD(0.0)), aw(N3, AD(0.0));
+    for (int k = 0; k < NX; ++k) xs[k] = AD::var(x[k]);
+    for (int i = 0; i < S; ++i) { kps[i] = AD::var(kp[i]); kds[i] = AD::var(kd[i]); }
+    for (int k = 0; k < (int)Fs.size(); ++k) Fs[k] = AD::var(F[k]);
+    for (int a = 0; a < A; ++a) aq[4 * a] = AD(1.0);
+    std::vector<AD> qo(N2), qdo(N2), axo(N3), avo(N3), aqo(4 * A), awo(N3);
+    step_tree<AD>(t, M->g, env, n, xs.data(), xs.data() + N2, xs.data() + 2 * N2, xs.data() + 2 * N2 + N3, aq.data(),
+                  aw.data(), kps.data(), kds.data(), nullptr, F ? Fs.data() : nullptr, qo.data(), qdo.data(),
+                  axo.data(), avo.data(), aqo.data(), awo.data(), &ev, nullptr, nullptr, &sw);
+    tp.adj.assign(tp.nodes.size(), 0.0);
+    auto seed = [&](const AD& o, double g) { if (o.i >= 0) tp.adj[o.i] += g; };
+    for (int k = 0; k < N2; ++k) { seed(qo[k], w[k]); seed(qdo[k], w[N2 + k]); }
+    for (int k = 0; k < N3; ++k) { seed(axo[k], w[2 * N2 + k]); seed(avo[k], w[2 * N2 + N3 + k]); }
+    tp.reverse();
+    auto get = [&](const AD& v) { return v.i >= 0 ? tp.adj[v.i] : 0.0; };
+    double s = 0.0;
+    for (int k = 0; k < NX; ++k) s += vx[k] * get(xs[k]);
+    for (int i = 0; i < S; ++i) s += vkp[i] * get(kps[i]) + vkd[i] * get(kds[i]);
+    for (int k = 0; k < (int)Fs.size(); ++k) s += (vF ? vF[k] : 0.0) * get(Fs[k]);
+    tape() = nullptr;
+    out[1] = s;
+  }
 }
 
 }  // extern "C"

@@ -16,7 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SRC = [os.path.join(HERE, f) for f in ("oracle.cpp", "oracle_math.hpp", "tape.hpp", "adjoint.cpp")]
+SRC = [os.path.join(HERE, f) for f in ("oracle.cpp", "oracle_math.hpp", "tape.hpp", "dual.hpp", "adjoint.cpp")]
 
 
 def build(force: bool = True) -> str:
@@ -85,6 +85,9 @@ def lib():
         L.oracle_rng_u24.argtypes = [C.c_uint64] * 5
         L.oracle_splitmix64.restype = C.c_uint64
         L.oracle_splitmix64.argtypes = [C.c_uint64]
+        L.oracle_rng_normals.argtypes = [C.c_uint64, C.c_int, C.c_int64, C.c_int, _P]
+        L.oracle_ltdl_pivots.argtypes = [C.c_void_p, C.c_int, _P, _P, _P]
+        L.oracle_step_dot.argtypes = [C.c_void_p, C.c_int, C.c_int64] + [_P] * 12
         _lib = L
     return _lib
 
@@ -208,6 +211,29 @@ class Oracle:
         lib().oracle_ltdl_solve(self.h, env, _ptr(q), _ptr(diag), _ptr(b), _ptr(x))
         return x
 
+    def ltdl_pivots(self, env, q, diag):
+        """Pivots D [2S] of the leaf-first L^T D L factorisation of H(q) + diag."""
+        S = self._S(env)
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64).reshape(2 * S)
+        q, diag = f(q), f(diag)
+        D = np.zeros(2 * S)
+        lib().oracle_ltdl_pivots(self.h, env, _ptr(q), _ptr(diag), _ptr(D))
+        return D
+
+    def step_dot(self, env, n, x, kp, kd, F, vx, vkp, vkd, vF, w, broken0=None, det0=None):
+        """Dot-product test of one step (switches frozen): (<J v, w>, <v, J^T w>).
+        The numbers of switches the step used are left in ``last_switch_counts``.
+
+        x, vx, w: [4S + 6A] (q, qd, apple position state, apple velocity); kp, kd, vkp,
+        vkd: [S]; F, vF: [A, 3] or None; broken0 [S], det0 [A]: entry flags or None."""
+        f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+        u8 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
+        args = [f(x), f(kp), f(kd), f(F), u8(broken0), u8(det0), f(vx), f(vkp), f(vkd), f(vF), f(w)]
+        out = np.zeros(6)
+        lib().oracle_step_dot(self.h, env, int(n), *[_ptr(a) for a in args], _ptr(out))
+        self.last_switch_counts = dict(broken=int(out[2]), detached=int(out[3]), clamped=int(out[4]), capped=int(out[5]))
+        return float(out[0]), float(out[1])
+
     # ---- state and rollout ----------------------------------------------------------------
     def empty_state(self) -> State:
         S, A, B = self.batch.n_seg, self.batch.n_apple, self.batch.n_env
@@ -275,6 +301,13 @@ def splitmix64(x: int) -> int:
     return int(lib().oracle_splitmix64(x))
 
 
+def rng_normals(seed, env, step, seg) -> np.ndarray:
+    """The three standard normals of the in-step random force of (env, step, segment)."""
+    z = np.zeros(3)
+    lib().oracle_rng_normals(seed, env, step, seg, _ptr(z))
+    return z
+
+
 # ---- adjoint (FP64, taped step, switches frozen) ------------------------------------------
 def _setup_adjoint(L):
     if getattr(L, "_adj_ready", False):
@@ -282,10 +315,10 @@ def _setup_adjoint(L):
     L.oracle_record_new.restype = C.c_void_p
     L.oracle_record_free.argtypes = [C.c_void_p]
     L.oracle_loss.restype = C.c_double
-    L.oracle_loss.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int] + [_P] * 7 + [C.c_int, _P, _P, C.c_void_p,
+    L.oracle_loss.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int] + [_P] * 7 + [C.c_int, _P, _P, _P, C.c_void_p,
                                                                                    C.c_void_p, _P]
     L.oracle_adjoint.restype = C.c_double
-    L.oracle_adjoint.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int] + [_P] * 7 + [C.c_int, _P, _P] + [_P] * 4
+    L.oracle_adjoint.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int] + [_P] * 7 + [C.c_int, _P, _P, _P] + [_P] * 4
     L._adj_ready = True
 
 
@@ -326,27 +359,43 @@ def env_state0(o, st, env):
     return dict(q=st.q[s0:s1], qd=st.qd[s0:s1], ax=st.ax[a0:a1], av=st.av[a0:a1])
 
 
-def loss(o, env, x0, kp, kd, F, n_steps, tips, target, step0=0, record_in=None, record_out=None, return_q=False):
+def _w_state(w_state, S, A):
+    if w_state is None:
+        return None
+    if isinstance(w_state, dict):
+        z = lambda k, n: np.zeros(n) if w_state.get(k) is None else np.asarray(w_state[k], np.float64).reshape(-1)
+        w_state = np.concatenate([z("q", 2 * S), z("qd", 2 * S), z("ax", 3 * A), z("av", 3 * A)])
+    w = np.ascontiguousarray(w_state, dtype=np.float64)
+    assert w.size == 4 * S + 6 * A
+    return w
+
+
+def loss(o, env, x0, kp, kd, F, n_steps, tips, target, step0=0, record_in=None, record_out=None, return_q=False,
+         w_state=None):
+    """Tip loss after n_steps, plus w_state . S_T if given (dict of q, qd, ax, av weights)."""
     L = lib()
     _setup_adjoint(L)
     S, A, q0, qd0, ax0, av0, kp, kd, F, tips, target = _adj_args(o, env, x0, kp, kd, F, tips, target)
+    ws = _w_state(w_state, S, A)
     qf = np.zeros(4 * S) if return_q else None
     v = L.oracle_loss(o.h, env, step0, n_steps, _ptr(q0), _ptr(qd0), _ptr(ax0), _ptr(av0), _ptr(kp), _ptr(kd), _ptr(F),
-                      len(tips), _ptr(tips), _ptr(target), record_in.h if record_in else None,
+                      len(tips), _ptr(tips), _ptr(target), _ptr(ws), record_in.h if record_in else None,
                       record_out.h if record_out else None, _ptr(qf))
     return (v, qf) if return_q else v
 
 
-def adjoint(o, env, x0, kp, kd, F, n_steps, tips, target, step0=0):
+def adjoint(o, env, x0, kp, kd, F, n_steps, tips, target, step0=0, w_state=None):
     """Returns (L, dL/dkp, dL/dkd, dL/dF [n_steps, A, 3] or None, dL/dx0 dict)."""
     L = lib()
     _setup_adjoint(L)
     S, A, q0, qd0, ax0, av0, kp, kd, F, tips, target = _adj_args(o, env, x0, kp, kd, F, tips, target)
+    ws = _w_state(w_state, S, A)
     gkp, gkd = np.zeros(S), np.zeros(S)
     gF = np.zeros((n_steps, A, 3)) if F is not None else None
     gx = np.zeros(4 * S + 6 * A)
     v = L.oracle_adjoint(o.h, env, step0, n_steps, _ptr(q0), _ptr(qd0), _ptr(ax0), _ptr(av0), _ptr(kp), _ptr(kd),
-                         _ptr(F), len(tips), _ptr(tips), _ptr(target), _ptr(gkp), _ptr(gkd), _ptr(gF), _ptr(gx))
+                         _ptr(F), len(tips), _ptr(tips), _ptr(target), _ptr(ws), _ptr(gkp), _ptr(gkd), _ptr(gF),
+                         _ptr(gx))
     g0 = dict(q=gx[:2 * S].reshape(S, 2), qd=gx[2 * S:4 * S].reshape(S, 2), ax=gx[4 * S:4 * S + 3 * A].reshape(A, 3),
               av=gx[4 * S + 3 * A:].reshape(A, 3))
     return v, gkp, gkd, gF, g0

@@ -975,6 +975,8 @@ static orchard_status_t tip_fk(orchard_model_t m, const float* q, hipStream_t hs
 orchard_status_t orchard_tips(orchard_model_t m, const float* q, int32_t n_tips, const int32_t* node, float* out,
                               orchard_stream_t stream) {
   if (!m || !q || (n_tips > 0 && (!node || !out)) || n_tips < 0) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  // the tip kernels keep their fields among the adjoint's scratch fields
+  if (m->dm.scr_nf < N_FIELDS_ADJ) return fail(ORCHARD_ERR_INVALID_ARG, "model created without adjoint support (tuning.adjoint_ckpt_max)");
   hipStream_t hs = (hipStream_t)stream;
   orchard_status_t st = tip_fk(m, q, hs);
   if (st) return st;
@@ -986,6 +988,7 @@ orchard_status_t orchard_tips(orchard_model_t m, const float* q, int32_t n_tips,
 orchard_status_t orchard_tips_backward(orchard_model_t m, const float* q, int32_t n_tips, const int32_t* node,
                                        const float* grad_out, float* grad_q, orchard_stream_t stream) {
   if (!m || !q || !grad_q || n_tips < 0 || (n_tips > 0 && (!node || !grad_out))) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
+  if (m->dm.scr_nf < N_FIELDS_ADJ) return fail(ORCHARD_ERR_INVALID_ARG, "model created without adjoint support (tuning.adjoint_ckpt_max)");
   hipStream_t hs = (hipStream_t)stream;
   orchard_status_t st = tip_fk(m, q, hs);
   if (st) return st;

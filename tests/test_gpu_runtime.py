@@ -89,3 +89,21 @@ def test_internal_order_is_a_parent_first_permutation(tuning):
             depth[k] = depth[b.seg_offset[env[k]] + par[k]] + 1
     assert m.max_depth == depth.max() + 1
     assert 1 <= m.n_pack <= b.n_env
+
+
+def test_tips_need_a_model_with_adjoint_support():
+    # the tip kernels keep their fields among the adjoint's scratch fields: on a model
+    # created without adjoint support both entry points refuse before any device work
+    from paper_2607_06337_amd import Model, OrchardError
+    b = make_batch("grad512", env_ids=range(2))
+    m = Model(b, step_constants())
+    st = m.rest_state()
+    node = torch.zeros(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(OrchardError) as ei:
+        m.tips(st.q, node)
+    assert ei.value.code == 1
+    gq = torch.zeros_like(st.q)
+    with pytest.raises(OrchardError) as ei:
+        m.tips_backward(st.q, node, torch.ones(4, 3, device="cuda"), gq)
+    assert ei.value.code == 1
+    assert torch.count_nonzero(gq) == 0
