@@ -43,6 +43,8 @@ GRAPH_STEPS = 100  # steps per captured HIP graph in the timed rollout
 PLAIN_TUNING = dict(threads=256, pack_fill=0.0, steps_per_launch=1, persistent=0, lds_width=0)
 
 HBM_PEAK_GBS = 8000.0
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4   # wave64 VALU instructions per second, whole chip
+FP32_PEAK = 78.6e12                  # FP32 vector FLOP/s without packed math
 SEG_BYTES, APPLE_BYTES = 84, 146   # algorithmic bytes per segment-step / apple-step
 WORKLOAD = "uneven8192"
 
@@ -68,69 +70,109 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kernel: str, tuning: dict):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel,
-    or None if there is none for the current kernel source and mapping."""
+def profiled_counters(kernel: str, tuning: dict):
+    """Counter figures of the committed rocprofv3 summaries of this kernel (HBM bytes per
+    launch, VALU instructions and FP32 operations per step), merged over the summaries
+    taken on the current kernel source and mapping; None if there is none."""
     cur = kernel_source_hash()
+    out = {}
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(f):
             if line.startswith("machine-readable: "):
                 rec = json.loads(line[len("machine-readable: "):])
                 if rec.get("kernel") == kernel and rec.get("src_hash") == cur and rec.get("tuning") == tuning:
-                    return rec["hbm_bytes_per_launch"]
-    return None
+                    out.update(rec)
+    return out or None
 
 
 def time_gpu(model, n_steps, warmup, graph_steps=0):
     """Time n_steps after warmup eager steps.  With graph_steps > 0 the rollout is a HIP
-    graph of graph_steps steps replayed (capture and one replay happen before the timed
-    region; a remainder runs eagerly inside it)."""
+    graph of min(graph_steps, n_steps) steps replayed (capture and one replay happen
+    before the timed region; a remainder runs eagerly inside it).  Returns (ms, wall s,
+    non-finite envs, state, description of what was timed, kernel launches timed)."""
     import torch
     st = model.rest_state()
     kp, kd = model.default_params()
     model.step(st, kp, kd, warmup)
     g = None
-    if graph_steps > 0 and n_steps >= graph_steps:
-        g = model.graph(st, kp, kd, graph_steps)
+    gs = min(graph_steps, n_steps)
+    if gs > 0:
+        g = model.graph(st, kp, kd, gs)
         g.launch()  # the first replay is not timed
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    spl = max(1, int(model.tuning["steps_per_launch"]))
+    launches = lambda k: -(-k // spl)
     t0 = time.perf_counter()
     ev0.record(stream)
     if g is not None:
-        for _ in range(n_steps // graph_steps):
+        reps, rem = n_steps // gs, n_steps % gs
+        for _ in range(reps):
             g.launch(stream)
-        if n_steps % graph_steps:
-            model.step(st, kp, kd, n_steps % graph_steps)
+        if rem:
+            model.step(st, kp, kd, rem)
+        what = f"HIP graph of {gs} steps replayed {reps} times" + (f" + {rem} eager steps" if rem else "")
+        n_launch = reps * launches(gs) + launches(rem)
     else:
         model.step(st, kp, kd, n_steps)
+        what = f"one eager call of {n_steps} steps"
+        n_launch = launches(n_steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
     status = model.status(st)
-    return ms, wall, int((status != 0).sum()), st
+    what += f" ({n_launch} launches of up to {spl} steps)"
+    return ms, wall, int((status != 0).sum()), st, what, n_launch
 
 
-def cpu_baseline(batch, consts, n_envs=64, n_steps=1500):
-    """FP64 oracle on a stratified sample of the same workload."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(batch, consts, n_envs=512, n_steps=200, n_envs_1=64, n_steps_1=100):
+    """FP64 oracle on size-stratified samples of the same workload: all cores of the
+    process's CPU share (at most 16, the share of one GPU on the box) on n_envs trees x
+    n_steps steps, and one core on n_envs_1 trees x n_steps_1 steps."""
     from oracle.oracle import Oracle
     from orchard_inputs import assemble
-    sizes = np.diff(batch.seg_offset)
-    order = np.argsort(sizes, kind="stable")
-    pick = sorted(int(order[i]) for i in np.unique(np.linspace(0, len(order) - 1, n_envs).round().astype(int)))
-    sub = assemble([batch.tree(e) for e in pick])
-    o = Oracle(sub, consts)
-    st = o.rest_state()
-    threads = min(16, os.cpu_count() or 1, len(pick))
-    t0 = time.perf_counter()
-    o.rollout(st, n_steps, threads=threads)
-    dt = time.perf_counter() - t0
-    return dict(value=len(pick) * n_steps / dt, unit="env-steps/s", cores=threads, kind="oracle",
-                sample=f"{len(pick)} size-stratified trees of the workload ({int(sizes[pick].sum())} segments) x "
-                       f"{n_steps} steps, FP64, {dt:.1f} s")
+
+    def sample(n):
+        sizes = np.diff(batch.seg_offset)
+        order = np.argsort(sizes, kind="stable")
+        pick = sorted(int(order[i]) for i in np.unique(np.linspace(0, len(order) - 1, n).round().astype(int)))
+        return pick, int(sizes[pick].sum())
+
+    def run(n, steps, threads):
+        pick, segs = sample(n)
+        o = Oracle(assemble([batch.tree(e) for e in pick]), consts)
+        st = o.rest_state()
+        t0 = time.perf_counter()
+        o.rollout(st, steps, threads=threads)
+        dt = time.perf_counter() - t0
+        return len(pick) * steps / dt, dt, len(pick), segs
+
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    threads = max(1, min(16, avail))
+    v_all, dt_all, n_all, seg_all = run(n_envs, n_steps, threads)
+    v_one, dt_one, n_one, seg_one = run(n_envs_1, n_steps_1, 1)
+    return dict(value=v_all, unit="env-steps/s", cores=threads, kind="oracle",
+                sample=f"{n_all} size-stratified trees of the workload ({seg_all} segments) x {n_steps} steps, FP64, "
+                       f"{dt_all:.1f} s on {threads} threads",
+                single_core=dict(value=v_one, sample=f"{n_one} size-stratified trees ({seg_one} segments) x "
+                                                     f"{n_steps_1} steps, {dt_one:.1f} s on 1 thread"),
+                nproc=os.cpu_count(), affinity=avail, cpu_model=_cpu_model())
 
 
 def adjoint_ratio(reps: int = 3):
@@ -178,7 +220,7 @@ def row_scale(fwd_steps: int = 200, warm: int = 10, lead: int = 900, tail: int =
     batch = make_batch("row64x16k")
     consts = step_constants()
     m = Model(batch, consts, BENCH_TUNING)
-    ms, _, n_bad, _ = time_gpu(m, fwd_steps, warm, GRAPH_STEPS)
+    ms, _, n_bad, _, _, _ = time_gpu(m, fwd_steps, warm, GRAPH_STEPS)
     fwd = dict(ms_per_step=round(ms / fwd_steps, 4), env_steps_per_s=round(batch.n_env * fwd_steps / (ms / 1e3), 1),
                alg_GBps=round(algorithmic_bytes(batch) * fwd_steps / (ms / 1e3) / 1e9, 1), nonfinite_envs=n_bad)
     del m
@@ -269,13 +311,13 @@ def main():
         print(f"# autotune {time.perf_counter() - t_tune:.1f} s: {tuning}", file=sys.stderr, flush=True)
     tuning = {k: tuning[k] for k in ("threads", "pack_fill", "steps_per_launch", "persistent", "lds_width", "pack_skew")}
     model = Model(batch, consts, tuning)
-    ms, wall, n_bad, _ = time_gpu(model, args.steps, args.warmup, GRAPH_STEPS)
+    ms, wall, n_bad, _, what, n_launch = time_gpu(model, args.steps, args.warmup, GRAPH_STEPS)
     print(f"# optimized: {args.steps} steps in {ms:.1f} ms ({wall:.2f} s wall), packs={model.n_pack}", file=sys.stderr,
           flush=True)
     plain = None
     if not args.no_plain:
         pm = Model(batch, consts, PLAIN_TUNING)
-        pms, _, _, _ = time_gpu(pm, max(1, args.steps // 4), args.warmup)
+        pms, _, _, _, _, _ = time_gpu(pm, max(1, args.steps // 4), args.warmup)
         plain = dict(value=batch.n_env * max(1, args.steps // 4) / (pms / 1e3), ms_per_step=pms / max(1, args.steps // 4),
                      tuning=PLAIN_TUNING)
         del pm
@@ -285,15 +327,31 @@ def main():
         _copy_probe()
     ms_step = ms / args.steps
     value = batch.n_env * args.steps / (ms / 1e3)
-    spl = tuning["steps_per_launch"]
-    per_launch_bytes = algorithmic_bytes(batch) * spl
-    launch_ms = ms_step * spl
+    # the step kernel's launches in the timed region: average duration and the algorithmic
+    # bytes of the steps one launch runs
+    steps_per_launch = args.steps / n_launch
+    per_launch_bytes = algorithmic_bytes(batch) * steps_per_launch
+    launch_ms = ms / n_launch
     achieved = per_launch_bytes / (launch_ms / 1e3) / 1e9
-    traffic = profiled_traffic("k_step_packs", tuning)
+    prof = profiled_counters("k_step_packs", tuning)
+    # measured HBM bytes per step of the profiled launches, times the steps of these launches
+    traffic = None
+    if prof and prof.get("hbm_bytes_per_launch"):
+        traffic = int(prof["hbm_bytes_per_launch"] / prof["tuning"]["steps_per_launch"] * steps_per_launch)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="k_step_packs", bytes_per_launch=per_launch_bytes,
-                launch_us=round(launch_ms * 1e3, 2))
+                kernel="k_step_packs", bytes_per_launch=int(per_launch_bytes),
+                launch_us=round(launch_ms * 1e3, 2), launches_timed=n_launch)
+    if prof and prof.get("valu_insts_per_step"):
+        # issue-rate ceiling of the vector ALUs: 1024 SIMDs, one wave64 VALU instruction
+        # per 4 cycles at 2.4 GHz; FP32 lane operations (FMA = 2) against 78.6 TFLOP/s
+        vi = prof["valu_insts_per_step"]
+        roof["valu"] = dict(insts_per_step=vi, frac=round(vi / (ms_step / 1e3) / VALU_ISSUE_PEAK, 4),
+                            peak_insts_per_s=VALU_ISSUE_PEAK)
+        if prof.get("fp32_flops_per_step"):
+            fl = prof["fp32_flops_per_step"]
+            roof["valu"].update(fp32_flops_per_step=fl, fp32_frac=round(fl / (ms_step / 1e3) / FP32_PEAK, 4),
+                                fp32_peak_flops=FP32_PEAK)
     adj = None
     if not args.no_adjoint:
         adj = adjoint_ratio()
@@ -313,7 +371,7 @@ def main():
                config=dict(workload=f"{WORKLOAD}: 8192 seeded L-system trees, log-uniform 50-1500 segments, "
                                     f"10-120 apples, in-step random body forces 5% N(0,5N), dt 1 ms",
                            n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=tuning,
-                           rollout=f"HIP graph of {GRAPH_STEPS} steps, replayed", autotune=tune_log),
+                           rollout=what, autotune=tune_log),
                adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
                roofline=roof, cpu_baseline=cpu, row_scale=rows)
     print(json.dumps(out), flush=True)

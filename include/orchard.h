@@ -215,8 +215,9 @@ typedef struct {
  * On return adj holds dL/dS_0 (in place).  Accumulates (+=) into grad_kp, grad_kd
  * [n_seg] and, if non-NULL, grad_apple_force [n_steps][n_apple][3].  Params and
  * inputs must be those of the forward call.  The quaternion and angular velocity of
- * the apples are not differentiated, nor is a detached apple's position w.r.t. the
- * tree pose at the detach step.  Stream-ordered with respect to stream; the recompute
+ * the apples are not differentiated (no torque acts on an apple); a fruit that
+ * detaches inside the window carries the dependence of its launch point (hang point
+ * plus stretch) on the tree pose into the tree's gradient.  Stream-ordered with respect to stream; the recompute
  * of each checkpoint segment runs on the model's second stream, overlapping the
  * reverse sweep of the segment after it (two sets of recompute buffers), and is joined
  * back before the call's last work on stream.  No allocation. */

@@ -241,8 +241,9 @@ __device__ __forceinline__ void node_reverse(const DevModel& M, const DevState& 
   float qdb0 = 0.f, qdb1 = 0.f;
   // ---- gather the children ----
   V3 vtb = v3(0, 0, 0), Atba = v3(0, 0, 0), Atbl = v3(0, 0, 0), Avtba = v3(0, 0, 0), Avtbl = v3(0, 0, 0), Fch = v3(0, 0, 0);
+  V3 pch = v3(0, 0, 0);  // position adjoint of the children's joint points (= this tip)
   for (int c = in.cb; c < in.ce; ++c) {
-    float cv[24];
+    float cv[27];
     xload<XL>(L, F_RB, c, cv);
     tau = tau + v3(cv[0], cv[1], cv[2]);
     omb = omb + v3(cv[3], cv[4], cv[5]);
@@ -252,7 +253,11 @@ __device__ __forceinline__ void node_reverse(const DevModel& M, const DevState& 
     Avtba = Avtba + v3(cv[15], cv[16], cv[17]);
     Avtbl = Avtbl + v3(cv[18], cv[19], cv[20]);
     Fch = Fch + v3(cv[21], cv[22], cv[23]);
+    pch = pch + v3(cv[24], cv[25], cv[26]);
   }
+  // joint-point positions: children sit at p + lz, this joint point at the parent's tip
+  lzb = lzb + pch;
+  V3 pb = pch;
   // tip publications: At = (A_ang, A_lin + A_ang x lz), same for Avp; vt = v + om x lz
   Aba = Aba + Atba + cross(lz, Atbl);
   Abl = Abl + Atbl;
@@ -349,12 +354,17 @@ __device__ __forceinline__ void node_reverse(const DevModel& M, const DevState& 
       sigb = sd - gs;                           // s = sigma - h vh
       vhb = (-2.f * h * M.ks) * feb + h * sd;   // d(lambda^T r)/dvh minus the direct part
     } else {
-      // ballistic: x' = x + h v', v' = v + (h/m)(m g + F); the hang point's motion at
-      // the detach step is not propagated into the tree
+      // ballistic: x' = x + h v', v' = v + (h/m)(m g + F).  At the detach step the fruit
+      // leaves from the hang point plus its stretch, x = p + d + sigma - h vh: the
+      // position adjoint reaches the joint point, the hang offset and the hang velocity
       vab = vtot;
       Fb = (h / ma) * vtot;
       sigb = xb;
-      if (!det0) vhb = h * xb;
+      if (!det0) {
+        vhb = h * xb;
+        db = db - xb;
+        pb = pb - xb;
+      }
     }
     vb = vb + vhb;
     omb = omb + cross(d, vhb);
@@ -413,9 +423,9 @@ __device__ __forceinline__ void node_reverse(const DevModel& M, const DevState& 
   }
 
   // ---- publish for the parent ----
-  const float ov[24] = {tau_par.x, tau_par.y, tau_par.z, omb.x, omb.y, omb.z, vb.x, vb.y, vb.z,
+  const float ov[27] = {tau_par.x, tau_par.y, tau_par.z, omb.x, omb.y, omb.z, vb.x, vb.y, vb.z,
                         Aba.x, Aba.y, Aba.z, Abl.x, Abl.y, Abl.z, Pba.x, Pba.y, Pba.z, Pbl.x, Pbl.y, Pbl.z,
-                        ff.x, ff.y, ff.z};
+                        ff.x, ff.y, ff.z, pb.x, pb.y, pb.z};
   xstore<XL>(L, F_RB, i, ov);
 }
 

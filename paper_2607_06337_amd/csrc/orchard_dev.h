@@ -82,8 +82,9 @@ enum : int {
   F_LA = 186,       // 6: acceleration of that solve at the tip
   F_NU = 192,       // 6: virtual velocity nu at the joint point
   F_LAM = 198,      // 2: lambda
-  F_RB = 200,       // 24: reverse-pass publication: tau_bar 3, omega_bar 3, vt_bar 3, At_bar 6, Avt_bar 6, f_lin 3
-  N_FIELDS_ADJ = 224
+  F_RB = 200,       // 27: reverse-pass publication: tau_bar 3, omega_bar 3, vt_bar 3, At_bar 6, Avt_bar 6, f_lin 3,
+                    //     joint-point position adjoint of the sub-tree 3
+  N_FIELDS_ADJ = 228
 };
 
 // Static records read by the forward step: one 32-byte record per node for the first down

@@ -3,7 +3,9 @@ same seeded inputs and compare them element by element.
 
 Tolerances (joint state): per env and per class, the largest deviation over all
 compared steps and DoF divided by max(largest oracle magnitude in that env, floor),
-floors 1e-3 rad (angles) and 1e-2 rad/s (rates); bar 1e-4.  Events: every (env,
+floors 1e-3 rad (angles) and 1e-2 rad/s (rates); bar 1e-4.  Fruit state (position
+state and velocity) is compared the same way, with floors 1e-3 m and 1e-2 m/s and bar
+APPLE_TOL.  Events: every (env,
 joint) and (env, apple) whose oracle ratio |mu - 1| (or |pi - 1|, |tau - 1|) stayed
 at least EPS away from 1 over the compared steps must have the identical event (kind
 and step) or none on both sides; ids that came within EPS ("in band") are excluded,
@@ -17,7 +19,9 @@ import numpy as np
 from oracle.oracle import Band, Oracle
 
 TOL = 1e-4
+APPLE_TOL = 1e-4
 FLOOR_Q, FLOOR_QD = 1e-3, 1e-2
+FLOOR_AX, FLOOR_AV = 1e-3, 1e-2
 EPS = 1e-3
 
 
@@ -38,39 +42,49 @@ def oracle_events(batch, st, envs):
     return ev
 
 
+def _rel(g, o, floor):
+    if g.size == 0:
+        return 0.0
+    return float(np.max(np.abs(g - o)) / max(np.max(np.abs(o)), floor))
+
+
 class Recorder:
-    """Collects GPU and oracle joint states at the compared steps."""
+    """Collects GPU and oracle joint and fruit states at the compared steps (fruit:
+    position state and velocity, descriptor order [A_tot, 3])."""
 
     def __init__(self, batch, envs):
         self.batch = batch
         self.envs = list(envs)
         self.steps = []
-        self.gq, self.gqd, self.oq, self.oqd = [], [], [], []
+        self.g = {k: [] for k in ("q", "qd", "ax", "av")}
+        self.o = {k: [] for k in ("q", "qd", "ax", "av")}
 
-    def add(self, step, gq_desc, gqd_desc, ost):
+    def add(self, step, gq_desc, gqd_desc, ost, gax_desc=None, gav_desc=None):
         self.steps.append(step)
-        self.gq.append(gq_desc.copy())
-        self.gqd.append(gqd_desc.copy())
-        self.oq.append(ost.q.copy())
-        self.oqd.append(ost.qd.copy())
+        for k, v in (("q", gq_desc), ("qd", gqd_desc), ("ax", gax_desc), ("av", gav_desc)):
+            self.g[k].append(None if v is None else v.copy())
+            self.o[k].append(getattr(ost, k).copy())
 
     def errors(self, cut=None):
-        """Per env: (rel q, rel qd, n compared steps)."""
+        """Per env: (rel q, rel qd, n compared steps, rel fruit position, rel fruit velocity)."""
         out = {}
         steps = np.array(self.steps)
+        have_apples = all(x is not None for x in self.g["ax"])
         for e in self.envs:
             s0, s1 = self.batch.seg_offset[e], self.batch.seg_offset[e + 1]
+            a0, a1 = self.batch.apple_offset[e], self.batch.apple_offset[e + 1]
             use = np.ones(len(steps), bool) if cut is None or cut.get(e) is None else steps <= cut[e]
             if not use.any():
-                out[e] = (0.0, 0.0, 0)
+                out[e] = (0.0, 0.0, 0, 0.0, 0.0)
                 continue
-            gq = np.stack([x[s0:s1] for x in self.gq])[use]
-            oq = np.stack([x[s0:s1] for x in self.oq])[use]
-            gqd = np.stack([x[s0:s1] for x in self.gqd])[use]
-            oqd = np.stack([x[s0:s1] for x in self.oqd])[use]
-            rq = np.max(np.abs(gq - oq)) / max(np.max(np.abs(oq)), FLOOR_Q)
-            rqd = np.max(np.abs(gqd - oqd)) / max(np.max(np.abs(oqd)), FLOOR_QD)
-            out[e] = (float(rq), float(rqd), int(use.sum()))
+            st = lambda d, k, lo, hi: np.stack([x[lo:hi] for x in d[k]])[use]
+            rq = _rel(st(self.g, "q", s0, s1), st(self.o, "q", s0, s1), FLOOR_Q)
+            rqd = _rel(st(self.g, "qd", s0, s1), st(self.o, "qd", s0, s1), FLOOR_QD)
+            rax = rav = 0.0
+            if have_apples and a1 > a0:
+                rax = _rel(st(self.g, "ax", a0, a1), st(self.o, "ax", a0, a1), FLOOR_AX)
+                rav = _rel(st(self.g, "av", a0, a1), st(self.o, "av", a0, a1), FLOOR_AV)
+            out[e] = (rq, rqd, int(use.sum()), rax, rav)
         return out
 
 
@@ -123,6 +137,7 @@ def run_parity(batch, consts, n_steps, every, *, envs=None, tuning=None, aforce_
     if wrench_desc is not None:
         w_int = torch.tensor(m.seg_from_desc(np.asarray(wrench_desc, np.float32)), device="cuda").contiguous()
     rec = Recorder(batch, envs)
+    rest_desc = m.apple_to_desc(m.apple_hang_rest, axis=0)
     marks = sorted(set(list(range(every, n_steps + 1, every)) + ([aforce_from] if 0 < aforce_from < n_steps else [])))
     done = 0
     for mk in marks:
@@ -135,7 +150,12 @@ def run_parity(batch, consts, n_steps, every, *, envs=None, tuning=None, aforce_
         torch.cuda.synchronize()
         gq = m.seg_to_desc(st.q.cpu().numpy().astype(np.float64))
         gqd = m.seg_to_desc(st.qd.cpu().numpy().astype(np.float64))
-        rec.add(done, gq, gqd, ost)
+        ga = m.apple_to_desc(st.apple[0:6].cpu().numpy().astype(np.float64), axis=1)
+        # a detached fruit's position state is kept relative to its rest hang point on the
+        # GPU, absolute in the oracle
+        det = m.apple_to_desc(st.apple_evt[0].cpu().numpy(), axis=0) != 0
+        gax = ga[0:3].T + np.where(det[:, None], rest_desc, 0.0)
+        rec.add(done, gq, gqd, ost, gax, ga[3:6].T)
     gev = gpu_events_desc(m, st)
     gev = {k: v for k, v in gev.items() if k[0] in set(envs)}
     oev = oracle_events(batch, ost, envs)

@@ -13,7 +13,7 @@ def test_comments_do_not_change_the_kernel_hash():
 
 def test_profile_lookup_matches_tuning_exactly():
     t = dict(bench.BENCH_TUNING, pack_skew=0)
-    found = bench.profiled_traffic("k_step_packs", t)
-    other = bench.profiled_traffic("k_step_packs", dict(t, lds_width=t["lds_width"] - 16))
+    found = bench.profiled_counters("k_step_packs", t)
+    other = bench.profiled_counters("k_step_packs", dict(t, lds_width=t["lds_width"] - 16))
     assert other is None
-    assert found is None or found > 0
+    assert found is None or found["hbm_bytes_per_launch"] > 0

@@ -190,3 +190,79 @@ def test_large_tree_adjoint_matches_fp64_central_differences():
         an = gkp @ dkp + gkd @ dkd + np.sum(gF * dF)
         print(f"large tree: fd {fd:.6e} adjoint {an:.6e}", flush=True)
         assert abs(fd - an) <= TOL * max(abs(an), 1e-12), (fd, an)
+
+
+def test_adjoint_through_every_switch():
+    # one differentiated window that contains every discrete switch of the step: a joint
+    # that breaks at window step 4, a fruit pulled off at window step 4, a fruit whose spur
+    # reaction is clamped until its stem tension tears it off, and capped in-step random
+    # body forces.  The loss adds the pulled fruit's final position and velocity to the tip
+    # loss, so the launch point of the detached fruit is differentiated too.  The GPU
+    # rollout starts from the oracle's state at the window's start (FP32) and is checked
+    # against the FP64 oracle adjoint (itself checked against replayed central differences
+    # on the CPU) and against FP64 central differences directly
+    from paper_2607_06337_amd import Model, rollout, tips
+    from tests.test_oracle_adjoint import switch_window
+    o, d, t, x0, F, tip_idx, target, Tw, pre, jb, w = switch_window()
+    batch = o.batch
+    m = Model(batch, o.consts, dict(threads=64, pack_fill=1.0, adjoint_ckpt_max=10))
+    st = m.rest_state()
+    kp0, kd0 = m.default_params()
+    # the window starts at step `pre` with the oracle's continuous state and clear counters
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a, np.float32), device="cuda")
+    st.q.copy_(dev(m.seg_from_desc(x0["q"])))
+    st.qd.copy_(dev(m.seg_from_desc(x0["qd"])))
+    st.apple[0:3].copy_(dev(m.apple_from_desc(x0["ax"].T, axis=1)))
+    st.apple[3:6].copy_(dev(m.apple_from_desc(x0["av"].T, axis=1)))
+    st.step.fill_(pre)
+    kp = kp0.clone().requires_grad_(True)
+    kd = kd0.clone().requires_grad_(True)
+    Fi = dev(m.apple_from_desc(F, axis=1)).requires_grad_(True)
+    q0 = st.q.clone().requires_grad_(True)
+    qd0 = st.qd.clone().requires_grad_(True)
+    ax0 = st.apple[0:3].clone().requires_grad_(True)
+    av0 = st.apple[3:6].clone().requires_grad_(True)
+    inv = np.empty(m.n_seg, np.int64)
+    inv[m.seg_map] = np.arange(m.n_seg)
+    node = torch.tensor(inv[tip_idx].astype(np.int32), device="cuda")
+    q, qd, ax, av = rollout(m, st, kp, kd, Tw, 10, aforce=Fi, q0=q0, qd0=qd0, ax0=ax0, av0=av0)
+    wax, wav = dev(m.apple_from_desc(w["ax"].T, axis=1)), dev(m.apple_from_desc(w["av"].T, axis=1))
+    L = ((tips(m, q, node) - dev(target)) ** 2).sum() + (wax * ax).sum() + (wav * av).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    # the window's events on the GPU: the break, the pull detach and the tension detach
+    ev = {(k, i): s for (e, k, i, s) in m.events(st)}
+    assert ev.get((1, jb)) == pre + 4, ev
+    assert ev.get((2, 0)) == pre + 4, ev
+    assert (3, 1) in ev and pre + 20 <= ev[(3, 1)] < pre + Tw, ev
+    # a detached fruit's position state is relative to its rest hang point
+    det = m.apple_to_desc(st.apple_evt[0].cpu().numpy(), axis=0) != 0
+    rest = m.apple_to_desc(m.apple_hang_rest, axis=0)
+    Lg = float(L.item()) + float(np.sum(w["ax"][det] * rest[det]))
+    Lo, gkp_o, gkd_o, gF_o, g0_o = adjoint(o, 0, x0, d["kp"], d["kd"], F, Tw, tip_idx, target, step0=pre, w_state=w)
+    print(f"switch window: L gpu {Lg:.8e} oracle {Lo:.8e}", flush=True)
+    assert abs(Lg - Lo) <= 1e-4 * abs(Lo)
+    to_np = lambda x: x.grad.cpu().numpy().astype(np.float64)
+    g = dict(kp=m.seg_to_desc(to_np(kp)), kd=m.seg_to_desc(to_np(kd)), F=m.apple_to_desc(to_np(Fi), axis=1),
+             q=m.seg_to_desc(to_np(q0)), qd=m.seg_to_desc(to_np(qd0)),
+             ax=m.apple_to_desc(to_np(ax0), axis=1).T, av=m.apple_to_desc(to_np(av0), axis=1).T)
+    ref = dict(kp=gkp_o, kd=gkd_o, F=gF_o, **g0_o)
+    for k in ref:
+        r = _rel(g[k], ref[k])
+        print(f"  d/d{k}: rel err {r:.2e}", flush=True)
+        assert r < TOL, (k, r)
+    # the broken joint's gains act only before the break: a non-zero, matching gradient
+    assert gkp_o[jb] != 0.0 and abs(g["kp"][jb] - gkp_o[jb]) <= TOL * np.abs(gkp_o).max()
+    # FP64 central differences with the GPU's event schedule replayed, along random directions
+    rec = Record()
+    loss(o, 0, x0, d["kp"], d["kd"], F, Tw, tip_idx, target, step0=pre, record_out=rec, w_state=w)
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        dkp, dkd, dF = rng.normal(size=t.n_seg) * d["kp"], rng.normal(size=t.n_seg) * d["kd"], rng.normal(size=F.shape)
+        e = 1e-5
+        fl = lambda s: loss(o, 0, x0, d["kp"] + s * dkp, d["kd"] + s * dkd, F + s * dF, Tw, tip_idx, target, step0=pre,
+                            record_in=rec, w_state=w)
+        fd = (fl(e) - fl(-e)) / (2 * e)
+        an = g["kp"] @ dkp + g["kd"] @ dkd + np.sum(g["F"] * dF)
+        print(f"  direction: fd {fd:.6e} gpu {an:.6e}", flush=True)
+        assert abs(fd - an) <= TOL * max(abs(an), 1e-12), (fd, an)
