@@ -22,6 +22,7 @@ plain seeded arrays; random numbers drawn *inside* the step (body wrenches of
 from __future__ import annotations
 
 import math
+import multiprocessing
 import os
 from concurrent.futures import ProcessPoolExecutor
 from dataclasses import dataclass
@@ -67,10 +68,13 @@ def make_trees(name: str, env_ids=None, workers: int | None = None) -> list[Tree
         env_ids = range(n_trees(name))
     jobs = [_sizes(name, int(e)) for e in env_ids]
     if workers is None:
-        workers = min(16, os.cpu_count() or 1)
+        workers = min(8, os.cpu_count() or 1)
     if len(jobs) < 64 or workers <= 1:
         return [_gen_one(j) for j in jobs]
-    with ProcessPoolExecutor(max_workers=workers) as ex:
+    # workers come from a fork server (a fresh interpreter), never forked from a caller
+    # that may already hold a GPU context
+    ctx = multiprocessing.get_context("forkserver")
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
         return list(ex.map(_gen_one, jobs, chunksize=max(1, len(jobs) // (8 * workers))))
 
 
