@@ -194,6 +194,28 @@ orchard_status_t orchard_step(orchard_model_t model, const orchard_state_t* stat
                               const orchard_inputs_t* inputs, int32_t n_steps, float* ckpt, int32_t ckpt_every,
                               orchard_stream_t stream);
 
+/* Bytes of the library's fixed step scratch (one array per GPU, held until the process
+ * ends). */
+#define ORCHARD_STATIC_SCRATCH_BYTES ((uint64_t)64 << 20)
+
+/* orchard_step for callers that cannot allocate device memory at step time (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * identical arguments, kernels and results, but the step's scratch (the per-node
+ * scratch blocks, the dense apple-node arrays and the persistent queue counter) lives
+ * in the library's fixed device array of ORCHARD_STATIC_SCRATCH_BYTES instead of the
+ * model's own scratch.  Calls no hipMalloc, hipFree or allocating routine.  A model
+ * whose step scratch (reported by the error message) exceeds the array is rejected
+ * with ORCHARD_ERR_CAPACITY before any device work; about 120 K segments fit a model
+ * without adjoint support.  The model's device must be current.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (two streams, two
+ * threads) race and must be serialised by the caller.  The queue counter is cleared by
+ * a kernel at the start of each call; nothing else in the array has to start at any
+ * value (every field a step reads was written earlier in the same step). */
+orchard_status_t orchard_step_static_scratch(orchard_model_t model, const orchard_state_t* state,
+                                             const orchard_params_t* params, const orchard_inputs_t* inputs,
+                                             int32_t n_steps, float* ckpt, int32_t ckpt_every,
+                                             orchard_stream_t stream);
+
 /* Adjoint state (caller-owned device arrays, internal order): dL/dq, dL/dqd
  * [n_seg][2] and dL/d(apple position state), dL/d(apple velocity) [3][n_apple]. */
 typedef struct {

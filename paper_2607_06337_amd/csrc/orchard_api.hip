@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -66,6 +67,9 @@ struct orchard_model_s {
   std::vector<double> apple_hang_rest;                // [n_apple][3] rest hang points
   void* arena = nullptr;
   float* scr = nullptr;
+  size_t an_bytes = 0;                                // dense apple-node arrays after the scratch blocks
+  int32_t n_anode = 0;
+  int device = 0;                                     // the device the model lives on
   size_t lds_bytes = 0;                               // dynamic LDS of the step kernels
   float* kp0 = nullptr;
   float* kd0 = nullptr;
@@ -580,6 +584,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   const size_t an_bytes = (size_t)std::max<int32_t>(n_anode, 1) * (K_N + E_N) * 4;
   he = hipMalloc(&M->scr, scr_bytes + an_bytes);
   M->scr_bytes = scr_bytes;
+  M->an_bytes = an_bytes;
+  M->n_anode = n_anode;
   if (he != hipSuccess) { (void)hipFree(M->arena); delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc scratch: ") + hipGetErrorString(he)); }
   M->bytes = (int64_t)(ar.off + scr_bytes + an_bytes);
   char* base = (char*)M->arena;
@@ -617,6 +623,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.aext = dm.asnap + (size_t)std::max<int32_t>(n_anode, 1) * K_N;
   int dev = 0;
   (void)hipGetDevice(&dev);
+  M->device = dev;
   (void)hipDeviceGetAttribute(&M->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   int per_cu = 1;
   const int lb = (int)M->lds_bytes;
@@ -738,12 +745,12 @@ int64_t orchard_ckpt_words(orchard_model_t m) {
   return 4LL * m->n_seg + 13LL * m->n_apple + m->n_seg + m->n_apple + m->n_seg + m->n_apple + m->n_env + 2;
 }
 
-static orchard_status_t launch_steps(orchard_model_t m, const DevState& ds, const DevInputs& di, int k, int s_call,
-                                     hipStream_t stream, bool save = false, float* scr = nullptr) {
+static orchard_status_t launch_steps(orchard_model_t m, const DevModel& dm0, const DevState& ds, const DevInputs& di,
+                                     int k, int s_call, hipStream_t stream, bool save = false, float* scr = nullptr) {
   const int NT = m->tun.threads;
   const unsigned lb = (unsigned)m->lds_bytes;
   if (save) {
-    DevModel dm = m->dm;
+    DevModel dm = dm0;
     dm.save_adj = 1;
     if (scr) dm.scr = scr;
     const dim3 g(m->n_pack);
@@ -756,30 +763,29 @@ static orchard_status_t launch_steps(orchard_model_t m, const DevState& ds, cons
   } else if (m->tun.persistent) {
     const dim3 g(m->persist_blocks);
     switch (NT) {
-      case 64: hipLaunchKernelGGL(k_step_persistent<64>, g, dim3(64), lb, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
-      case 128: hipLaunchKernelGGL(k_step_persistent<128>, g, dim3(128), lb, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
-      case 256: hipLaunchKernelGGL(k_step_persistent<256>, g, dim3(256), lb, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
-      default: hipLaunchKernelGGL(k_step_persistent<512>, g, dim3(512), lb, stream, m->dm, ds, di, k, s_call, m->dm.queue); break;
+      case 64: hipLaunchKernelGGL(k_step_persistent<64>, g, dim3(64), lb, stream, dm0, ds, di, k, s_call, dm0.queue); break;
+      case 128: hipLaunchKernelGGL(k_step_persistent<128>, g, dim3(128), lb, stream, dm0, ds, di, k, s_call, dm0.queue); break;
+      case 256: hipLaunchKernelGGL(k_step_persistent<256>, g, dim3(256), lb, stream, dm0, ds, di, k, s_call, dm0.queue); break;
+      default: hipLaunchKernelGGL(k_step_persistent<512>, g, dim3(512), lb, stream, dm0, ds, di, k, s_call, dm0.queue); break;
     }
   } else {
     const dim3 g(m->n_pack);
     switch (NT) {
-      case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, stream, m->dm, ds, di, k, s_call); break;
-      case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), lb, stream, m->dm, ds, di, k, s_call); break;
-      case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lb, stream, m->dm, ds, di, k, s_call); break;
-      default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), lb, stream, m->dm, ds, di, k, s_call); break;
+      case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, stream, dm0, ds, di, k, s_call); break;
+      case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), lb, stream, dm0, ds, di, k, s_call); break;
+      case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lb, stream, dm0, ds, di, k, s_call); break;
+      default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), lb, stream, dm0, ds, di, k, s_call); break;
     }
   }
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, stream, ds.step, (m->tun.persistent && !save) ? m->dm.queue : nullptr, k);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, stream, ds.step, (m->tun.persistent && !save) ? dm0.queue : nullptr, k);
   HIPCHK(hipGetLastError());
   return ORCHARD_OK;
 }
 
-orchard_status_t orchard_step(orchard_model_t m, const orchard_state_t* s, const orchard_params_t* params,
-                              const orchard_inputs_t* inputs, int32_t n_steps, float* ckpt, int32_t ckpt_every,
-                              orchard_stream_t stream) {
-  if (!m || !params || !params->kp || !params->kd) return fail(ORCHARD_ERR_INVALID_ARG, "null model or params");
+static orchard_status_t step_with(orchard_model_t m, const DevModel& dm, const orchard_state_t* s,
+                                  const orchard_params_t* params, const orchard_inputs_t* inputs, int32_t n_steps,
+                                  float* ckpt, int32_t ckpt_every, orchard_stream_t stream) {
   if (n_steps < 0) return fail(ORCHARD_ERR_INVALID_ARG, "n_steps < 0");
   if (ckpt && ckpt_every < 1) return fail(ORCHARD_ERR_INVALID_ARG, "ckpt_every must be >= 1");
   DevState ds;
@@ -805,11 +811,76 @@ orchard_status_t orchard_step(orchard_model_t m, const orchard_state_t* s, const
       }
       k = std::min(k, ckpt_every - s0 % ckpt_every);
     }
-    st = launch_steps(m, ds, di, k, s0, hs);
+    st = launch_steps(m, dm, ds, di, k, s0, hs);
     if (st) return st;
     s0 += k;
   }
   return ORCHARD_OK;
+}
+
+orchard_status_t orchard_step(orchard_model_t m, const orchard_state_t* s, const orchard_params_t* params,
+                              const orchard_inputs_t* inputs, int32_t n_steps, float* ckpt, int32_t ckpt_every,
+                              orchard_stream_t stream) {
+  if (!m || !params || !params->kp || !params->kd) return fail(ORCHARD_ERR_INVALID_ARG, "null model or params");
+  return step_with(m, m->dm, s, params, inputs, n_steps, ckpt, ckpt_every, stream);
+}
+
+// ---- the step on a fixed scratch array, for callers that cannot allocate ----------------
+// One array per GPU the library runs on, held until the process ends.  In host code its
+// name is only a stand-in for the symbol: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is ever passed on.
+static __device__ __align__(256) float scratch[ORCHARD_STATIC_SCRATCH_BYTES / 4];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this device's scratch array (resolved on the first call per device).
+static orchard_status_t scratch_address(int dev, float** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ORCHARD_ERR_INVALID_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != dev) return fail(ORCHARD_ERR_INVALID_ARG, "the model's device is not the current device");
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return ORCHARD_OK;
+}
+
+__global__ void k_zero_i32(int32_t* p, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0;
+}
+
+orchard_status_t orchard_step_static_scratch(orchard_model_t m, const orchard_state_t* s,
+                                             const orchard_params_t* params, const orchard_inputs_t* inputs,
+                                             int32_t n_steps, float* ckpt, int32_t ckpt_every,
+                                             orchard_stream_t stream) {
+  if (!m || !params || !params->kp || !params->kd) return fail(ORCHARD_ERR_INVALID_ARG, "null model or params");
+  // layout in the array: the persistent queue counter (256 bytes), the per-node scratch
+  // blocks, then the dense apple-node arrays, each as the model's own scratch lays them out
+  const size_t need = 256 + m->scr_bytes + m->an_bytes;
+  if (need > ORCHARD_STATIC_SCRATCH_BYTES)
+    return fail(ORCHARD_ERR_CAPACITY, "model needs " + std::to_string(need) + " bytes of step scratch; the static "
+                                      "scratch holds " + std::to_string((size_t)ORCHARD_STATIC_SCRATCH_BYTES));
+  float* base = nullptr;
+  orchard_status_t st = scratch_address(m->device, &base);
+  if (st) return st;
+  DevModel dm = m->dm;
+  dm.queue = reinterpret_cast<int32_t*>(base);
+  dm.scr = base + 64;
+  dm.asnap = reinterpret_cast<float*>(reinterpret_cast<char*>(dm.scr) + m->scr_bytes);
+  dm.aext = dm.asnap + (size_t)std::max<int32_t>(m->n_anode, 1) * K_N;
+  // the queue counter must start at zero (a kernel, not a memset, so the call can be captured)
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, (hipStream_t)stream, dm.queue, 1);
+  HIPCHK(hipGetLastError());
+  return step_with(m, dm, s, params, inputs, n_steps, ckpt, ckpt_every, stream);
 }
 
 // load a checkpoint record written by orchard_step into the state
@@ -906,7 +977,7 @@ orchard_status_t orchard_step_backward(orchard_model_t m, const float* ckpt, int
     hipLaunchKernelGGL(k_ckpt_load, dim3(grid_for(words)), dim3(256), 0, st, m->dm, W, (const uint32_t*)ckpt + (int64_t)sg * words);
     hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, st, m->dm, W, rec_at(s, 0));
     for (int j = 0; j < nk; ++j) {
-      orchard_status_t r = launch_steps(m, W, di, 1, n0 + j, st, true, rep(s, j));
+      orchard_status_t r = launch_steps(m, m->dm, W, di, 1, n0 + j, st, true, rep(s, j));
       if (r) return r;
       hipLaunchKernelGGL(k_ckpt_save, dim3(grid_for(words)), dim3(256), 0, st, m->dm, W, rec_at(s, j + 1));
     }

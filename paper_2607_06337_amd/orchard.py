@@ -73,7 +73,8 @@ class Event(C.Structure):
 # every exported entry point of include/orchard.h
 EXPORTS = ("orchard_model_create", "orchard_model_destroy", "orchard_model_layout", "orchard_model_maps",
            "orchard_model_apple_rest",
-           "orchard_default_params", "orchard_state_rest", "orchard_step", "orchard_ckpt_words",
+           "orchard_default_params", "orchard_state_rest", "orchard_step", "orchard_step_static_scratch",
+           "orchard_ckpt_words",
            "orchard_ckpt_load", "orchard_events", "orchard_status", "orchard_last_error", "orchard_step_backward",
            "orchard_tips", "orchard_tips_backward", "orchard_graph_create", "orchard_graph_launch",
            "orchard_graph_destroy", "orchard_autotune")
@@ -114,6 +115,8 @@ def load_library(path: str = LIB_PATH):
     L.orchard_step.argtypes = [_P, C.POINTER(CState), C.POINTER(CParams), C.POINTER(CInputs), C.c_int32, _P,
                                C.c_int32, _P]
     L.orchard_step.restype = st
+    L.orchard_step_static_scratch.argtypes = L.orchard_step.argtypes
+    L.orchard_step_static_scratch.restype = st
     L.orchard_ckpt_words.argtypes = [_P]
     L.orchard_ckpt_words.restype = C.c_int64
     L.orchard_ckpt_load.argtypes = [_P, C.POINTER(CState), _P, _P]
@@ -348,9 +351,12 @@ class Model:
 
     # ---- stepping -------------------------------------------------------------------------
     def step(self, state: State, kp, kd, n_steps: int, wrench=None, wrench_stride: int | None = None,
-             aforce=None, aforce_stride: int | None = None, ckpt=None, ckpt_every: int = 0, stream=None):
+             aforce=None, aforce_stride: int | None = None, ckpt=None, ckpt_every: int = 0, stream=None,
+             static_scratch: bool = False):
         """Advance all envs by n_steps.  wrench: float32 [n_seg, 6] (constant) or
-        [T, n_seg, 6]; aforce: [n_apple, 3] or [T, n_apple, 3] (internal order)."""
+        [T, n_seg, 6]; aforce: [n_apple, 3] or [T, n_apple, 3] (internal order).
+        static_scratch: run on the library's fixed scratch array (orchard_step_static_scratch)
+        instead of the model's own scratch."""
         assert kp.dtype == kd.dtype and kp.numel() == self.n_seg and kd.numel() == self.n_seg
         assert kp.is_contiguous() and kd.is_contiguous()
         inp = CInputs()
@@ -369,8 +375,9 @@ class Model:
             assert ckpt.is_contiguous() and ckpt.numel() >= need and ckpt.element_size() == 4
         cs = state.c()
         pr = CParams(_tptr(kp), _tptr(kd))
-        _check(load_library().orchard_step(self.h, C.byref(cs), C.byref(pr), C.byref(inp), int(n_steps),
-                                           _tptr(ckpt), int(ckpt_every), _stream(stream)))
+        fn = load_library().orchard_step_static_scratch if static_scratch else load_library().orchard_step
+        _check(fn(self.h, C.byref(cs), C.byref(pr), C.byref(inp), int(n_steps), _tptr(ckpt), int(ckpt_every),
+                  _stream(stream)))
         return state
 
     def graph(self, state: State, kp, kd, n_steps: int, wrench=None, aforce=None) -> Graph:
