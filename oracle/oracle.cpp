@@ -53,6 +53,21 @@ struct Globals {
   int32_t n_break, n_pull, n_tension, pad;
   uint64_t rng_seed;
   double wrench_fraction, wrench_sigma;
+  // variants (Sec. "Compliant branch dynamics", Sec. "Fruit"): per-level exponential
+  // stiffness Kp = k0 gamma^depth when stiffness_k0 > 0; fruit with 3 (translational)
+  // or 6 degrees of freedom
+  double stiffness_k0, stiffness_gamma;
+  int32_t fruit_dof, pad1;
+  // extras (Sec. "Compliant branch dynamics", Sec. "Branch breaking", Sec. "Numerical
+  // Stability"), all off at 0: velocity-proportional drag F = -c_v m v, tau = -c_w I w,
+  // scaled by drag_snapped on a snapped sub-tree; Coulomb friction at a broken joint of
+  // friction_base x (its limb's largest weight moment), growing linearly to
+  // friction_growth times that over friction_ramp_time, acting as a damper below
+  // friction_speed; power fade of applied force along the body's velocity from
+  // fade_speed to twice it; speed brake -brake_rate m (|v| - v_cap) above v_cap
+  double drag_lin, drag_ang, drag_snapped;
+  double friction_base, friction_growth, friction_ramp_time, friction_speed;
+  double fade_speed, brake_rate;
 };
 
 struct Tree {
@@ -61,6 +76,7 @@ struct Tree {
   std::vector<int> parent;
   std::vector<M3<double>> Q;
   std::vector<double> len, rad, mass, It, Ia, kp0, kd0, mmax;
+  std::vector<double> wmom;  // largest weight moment of each joint's limb: |g| sum m_b |c_b - p_j| at rest
   // DoF tree (2 per segment): dof 2i = x axis, 2i+1 = y axis
   std::vector<int> dpar, ddepth, roff;
   int nnz = 0;
@@ -224,6 +240,13 @@ static bool build_tree(Tree& t, const Globals& g, int S, int A, const int* paren
     t.kp0[i] = M_PI / 4.0 * E[i] * r * r * r * r / l;   // Eq. beam
     t.mmax[i] = mor[i] * M_PI * r * r * r / 4.0;        // Eq. break
   }
+  if (g.stiffness_k0 > 0) {  // per-level exponential model: each level down scales Kp by gamma
+    std::vector<int> depth(S, 0);
+    for (int i = 0; i < S; ++i) {
+      depth[i] = parent[i] < 0 ? 0 : depth[parent[i]] + 1;
+      t.kp0[i] = g.stiffness_k0 * std::pow(g.stiffness_gamma, depth[i]);
+    }
+  }
   // DoF tree
   t.dpar.resize(2 * S); t.ddepth.resize(2 * S); t.roff.resize(2 * S + 1);
   for (int i = 0; i < S; ++i) {
@@ -250,6 +273,12 @@ static bool build_tree(Tree& t, const Globals& g, int S, int A, const int* paren
       double J = 0.5 * (H[t.roff[2 * i]] + H[t.roff[2 * i + 1]]);
       t.kd0[i] = 2.0 * g.damping_zeta * std::sqrt(t.kp0[i] * J);
     }
+    // weight moment scale of each joint's limb (the friction reading): every body of
+    // the sub-tree at the distance of its centre of mass from the joint point
+    const double gn = std::sqrt(g.gravity[0] * g.gravity[0] + g.gravity[1] * g.gravity[1] + g.gravity[2] * g.gravity[2]);
+    t.wmom.assign(S, 0.0);
+    for (int b = 0; b < S; ++b)
+      for (int j = b; j >= 0; j = parent[j]) t.wmom[j] += gn * t.mass[b] * norm(K.I[b].c - K.p[j]);
   }
   t.aseg.assign(aseg, aseg + A);
   t.ahang.resize(A); t.am.assign(am, am + A); t.aR.assign(aR, aR + A); t.afdet.assign(afdet, afdet + A);
@@ -376,7 +405,18 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
   std::vector<SV<T>> fext(S);
   const bool use_rng = g.wrench_fraction > 0.0;
   const uint32_t sel_thr = (uint32_t)std::floor(g.wrench_fraction * 16777216.0);
+  const bool drag = g.drag_lin > 0 || g.drag_ang > 0;
+  const bool rails = g.fade_speed > 0 || g.brake_rate > 0;
   for (int i = 0; i < S; ++i) {
+    // the body's centre-of-mass velocity and angular velocity at the start of the step
+    const SV<T>& vb = vel[2 * i + 1];
+    const V3<T> vc = vb.l + cross(vb.a, K.I[i].c);
+    if (drag) {  // velocity-proportional drag, reduced (not removed) on a snapped sub-tree
+      const double f = snapped[i] ? g.drag_snapped : 1.0;
+      const V3<T> Fd = (-f * g.drag_lin * t.mass[i]) * vc;
+      const V3<T> Td = (-f * g.drag_ang) * (K.I[i].Ic * vb.a);
+      fext[i] = fext[i] + SV<T>{Td + cross(K.I[i].c, Fd), Fd};
+    }
     if (snapped[i]) continue;  // applied forces disabled on a snapped sub-tree
     double F[3] = {0, 0, 0}, Tq[3] = {0, 0, 0};
     bool any = false;
@@ -388,12 +428,28 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
       any = true;
     }
     if (!any) continue;
-    // impulse cap: one step of the force may not raise the body speed above v_cap
-    double nF = std::sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
-    double cap = t.mass[i] * g.v_cap / h;
-    bool cp = replay ? replay->capped[i] : (nF > cap);
-    if (cp) { for (int c = 0; c < 3; ++c) F[c] *= cap / nF; capped[i] = 1; }
     V3<T> Fv = V3<T>(T(F[0]), T(F[1]), T(F[2]));
+    if (rails) {
+      const T sp = norm(vc);
+      if (val(sp) > 0) {
+        const V3<T> u = (T(1) / sp) * vc;
+        // power fade: the part of the force along the velocity, when it pushes the body
+        // on, falls linearly from full at fade_speed to nothing at twice that speed
+        const T fu = dot(Fv, u);
+        if (g.fade_speed > 0 && val(fu) > 0 && val(sp) > g.fade_speed) {
+          T phi = T(1) - (sp - g.fade_speed) / g.fade_speed;
+          if (val(phi) < 0) phi = T(0);
+          Fv = Fv - ((T(1) - phi) * fu) * u;
+        }
+        // soft speed brake above the speed limit
+        if (g.brake_rate > 0 && val(sp) > g.v_cap) Fv = Fv - (g.brake_rate * t.mass[i] * (sp - g.v_cap)) * u;
+      }
+    }
+    // impulse cap: one step of the force may not raise the body speed above v_cap
+    const T nF = norm(Fv);
+    const double cap = t.mass[i] * g.v_cap / h;
+    bool cp = replay ? replay->capped[i] : (val(nF) > cap);
+    if (cp) { Fv = (T(cap) / nF) * Fv; capped[i] = 1; }
     V3<T> Tv = V3<T>(T(Tq[0]), T(Tq[1]), T(Tq[2]));
     fext[i] = fext[i] + SV<T>{Tv + cross(K.I[i].c, Fv), Fv};
   }
@@ -426,6 +482,17 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
   for (int i = 0; i < S; ++i) {
     T kpe = broken[i] ? T(0) : kp[i];
     T kde = broken[i] ? T(0) : kd[i];
+    if (broken[i] && g.friction_base > 0 && ev && ev->break_step[i] >= 0) {
+      // Coulomb friction of the torn fibres, ramped from friction_base to
+      // friction_growth x friction_base of the limb's weight moment over the ramp time,
+      // as a linearly implicit damper tau_c / max(|theta'|, friction_speed): it brakes
+      // the hinge toward rest and never reverses it within a step
+      const double ts = (double)(n - ev->break_step[i]) * h;
+      const double ramp = g.friction_ramp_time > 0 ? std::min(1.0, ts / g.friction_ramp_time) : 1.0;
+      const double tc = g.friction_base * t.wmom[i] * (1.0 + (g.friction_growth - 1.0) * ramp);
+      const T w = sqrt(qd[2 * i] * qd[2 * i] + qd[2 * i + 1] * qd[2 * i + 1]);
+      kde = val(w) > g.friction_speed ? T(tc) / w : T(tc / g.friction_speed);
+    }
     for (int d = 0; d < 2; ++d) {
       const int k = 2 * i + d;
       hent(t, H, k, k) = hent(t, H, k, k) + h * kde + h * h * kpe;
@@ -465,6 +532,11 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
     V3<T> base = det[a] ? (det0[a] ? V3<T>(ax[3 * a], ax[3 * a + 1], ax[3 * a + 2]) : xh[a] + sa[a]) : sa[a];
     V3<T> xn = base + h * vn;
     for (int cc = 0; cc < 3; ++cc) { avo[3 * a + cc] = vn[cc]; axo[3 * a + cc] = xn[cc]; awo[3 * a + cc] = aw[3 * a + cc]; }
+    if (g.fruit_dof == 3) {  // translational fruit: no orientation state to advance
+      for (int cc = 0; cc < 4; ++cc) aqo[4 * a + cc] = aq[4 * a + cc];
+      for (int cc = 0; cc < 3; ++cc) finite = finite && std::isfinite(val(axo[3 * a + cc])) && std::isfinite(val(avo[3 * a + cc]));
+      continue;
+    }
     // quat+ = normalize(exp(h w / 2) * quat)
     V3<T> hw = (0.5 * h) * V3<T>(aw[3 * a], aw[3 * a + 1], aw[3 * a + 2]);
     double th = val(norm(hw));

@@ -31,13 +31,20 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+# the extras of the step, in the order of the C struct
+EXTRAS = ("drag_lin", "drag_ang", "drag_snapped", "friction_base", "friction_growth", "friction_ramp_time",
+          "friction_speed", "fade_speed", "brake_rate")
+
+
 class Globals(C.Structure):
     _fields_ = [("dt", C.c_double), ("gravity", C.c_double * 3), ("tether_k", C.c_double),
                 ("tether_zeta", C.c_double), ("damping_zeta", C.c_double), ("damping_cd", C.c_double),
                 ("tension_factor", C.c_double), ("v_cap", C.c_double), ("react_max_factor", C.c_double),
                 ("event_band", C.c_double), ("n_break", C.c_int32), ("n_pull", C.c_int32),
                 ("n_tension", C.c_int32), ("pad", C.c_int32), ("rng_seed", C.c_uint64),
-                ("wrench_fraction", C.c_double), ("wrench_sigma", C.c_double)]
+                ("wrench_fraction", C.c_double), ("wrench_sigma", C.c_double),
+                ("stiffness_k0", C.c_double), ("stiffness_gamma", C.c_double), ("fruit_dof", C.c_int32),
+                ("pad1", C.c_int32)] + [(k, C.c_double) for k in EXTRAS]
 
 
 _P = C.c_void_p
@@ -137,6 +144,11 @@ def make_globals(consts: dict) -> Globals:
     for k in ("n_break", "n_pull", "n_tension"):
         setattr(g, k, int(consts[k]))
     g.rng_seed = int(consts["rng_seed"])
+    g.stiffness_k0 = float(consts.get("stiffness_k0", 0.0))
+    g.stiffness_gamma = float(consts.get("stiffness_gamma", 1.0))
+    g.fruit_dof = int(consts.get("fruit_dof", 6))
+    for k in EXTRAS:
+        setattr(g, k, float(consts.get(k, 0.0)))
     return g
 
 

@@ -198,7 +198,23 @@ STEP_CONSTANTS = dict(
     event_band=1e-3,         # band of the event comparison
     n_break=5, n_pull=5, n_tension=20,
     rng_seed=0, wrench_fraction=0.0, wrench_sigma=5.0,
+    # variants: per-level exponential stiffness (off at k0 = 0), fruit degrees of freedom
+    stiffness_k0=0.0, stiffness_gamma=1.0, fruit_dof=6,
+    # extras, off at 0: drag, post-break friction ramp, power fade and speed brake
+    drag_lin=0.0, drag_ang=0.0, drag_snapped=1.0,
+    friction_base=0.0, friction_growth=1.0, friction_ramp_time=0.0, friction_speed=0.0,
+    fade_speed=0.0, brake_rate=0.0,
 )
+
+# the extras as a workload turns them on (readings of constants the paper does not
+# give): drag 1/s on segments (a tenth of it on a snapped sub-tree), friction from a
+# quarter of the limb's weight moment growing five-fold over 1.5 s, damper below
+# 0.05 rad/s, power fade from 0.5 m/s, speed brake 50/s above the impulse-cap speed
+EXTRAS_ON = dict(drag_lin=1.0, drag_ang=1.0, drag_snapped=0.1, friction_base=0.25, friction_growth=5.0,
+                 friction_ramp_time=1.5, friction_speed=0.05, fade_speed=0.5, brake_rate=50.0)
+# the per-level exponential stiffness as a workload uses it: about the trunk's Eq.-beam
+# stiffness at the root, falling to twig stiffness twenty levels down
+EXP_STIFFNESS = dict(stiffness_k0=1.0e5, stiffness_gamma=0.65)
 
 
 def step_constants(name: str | None = None, **over) -> dict:
