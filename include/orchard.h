@@ -83,6 +83,31 @@ typedef struct {
   uint64_t rng_seed;            /* in-step random body forces (see orchard_step)      */
   double wrench_fraction;       /* fraction of bodies pushed per step (0 = off)       */
   double wrench_sigma;          /* N(0, sigma) per force component                    */
+  /* model variants (Sec. "Compliant branch dynamics", Sec. "Fruit") */
+  double stiffness_k0;          /* > 0: per-level exponential stiffness instead of    */
+  double stiffness_gamma;       /*   Eq. beam: Kp = k0 gamma^depth, depth of the      */
+                                /*   joint below the root (root 0), 0 < gamma        */
+  int32_t fruit_dof;            /* 3: translational fruit (state: position and        */
+                                /*   velocity only); 6 or 0: rigid body (also the    */
+                                /*   quaternion and angular velocity)                */
+  int32_t pad1;
+  /* extras, each off at 0 (Sec. "Compliant branch dynamics", Sec. "Branch breaking",
+   * Sec. "Numerical Stability"); orchard_step_backward rejects a model that uses any */
+  double drag_lin;              /* c_v: drag force -c_v m v at the centre of mass (1/s) */
+  double drag_ang;              /* c_w: drag torque -c_w I w (1/s)                    */
+  double drag_snapped;          /* factor on both drags on a snapped sub-tree         */
+  double friction_base;         /* Coulomb torque at a broken joint right after the   */
+                                /*   break, as a fraction of the limb's largest      */
+                                /*   weight moment |g| sum_b m_b |c_b - p_joint|     */
+  double friction_growth;       /* factor the torque reaches at the end of the ramp   */
+  double friction_ramp_time;    /* length of the linear ramp (s)                      */
+  double friction_speed;        /* joint speed (rad/s) below which the friction acts  */
+                                /*   as a damper tau_c / friction_speed              */
+  double fade_speed;            /* power fade: the part of an applied force along the */
+                                /*   body's velocity that pushes it on falls from    */
+                                /*   full at this speed to none at twice it          */
+  double brake_rate;            /* speed brake: -rate m (|v| - v_cap) v/|v| on a body */
+                                /*   with an applied force above v_cap (1/s)         */
 } orchard_model_desc_t;
 
 /* Kernel mapping choices (nullable in create: defaults {128, 1.0, 1, 0, 0, 128, 0}).
@@ -113,13 +138,17 @@ typedef struct {
   int64_t n_env, n_seg, n_apple;
   int32_t n_pack, max_depth;
   int64_t scratch_bytes;        /* device memory the model owns                       */
+  int32_t apple_planes;         /* float planes of the apple state: 13 (rigid body) or */
+                                /*   6 (translational fruit)                          */
+  int32_t pad;
 } orchard_layout_t;
 
 /* Caller-owned device state (internal order). */
 typedef struct {
   float* q;            /* [n_seg][2]   bending angles (theta_x, theta_y)               */
   float* qd;           /* [n_seg][2]   their rates                                      */
-  float* apple;        /* [13][n_apple] planes: x(3) v(3) quat(4, w first) omega(3);   */
+  float* apple;        /* [P][n_apple] planes, P = layout.apple_planes: x(3) v(3) and  */
+                       /*   for a rigid-body fruit quat(4, w first) omega(3);          */
                        /*   v is the absolute velocity.  x: while attached, the stretch */
                        /*   x_abs - x_hang plus h v (the stretch advanced by the apple  */
                        /*   but not yet by the hang point); once detached, x_abs minus  */

@@ -28,14 +28,14 @@ struct DevAdj {
   float* gF;        // [n_steps][n_apple][3] or null (this step's slice is gF + s_call * 3 * n_apple)
 };
 
-// record words: q (2S) qd (2S) apple (13A) seg_evt (S) apple_evt (A) ...
+// record words: q (2S) qd (2S) apple (P A, P planes) seg_evt (S) apple_evt (A) ...
 struct RecView {
   const float* w;
-  int NS, NA;
+  int NS, NA, P;
   __device__ float2 q(int i) const { return make_float2(w[2 * i], w[2 * i + 1]); }
   __device__ float2 qd(int i) const { return make_float2(w[2 * NS + 2 * i], w[2 * NS + 2 * i + 1]); }
   __device__ float apple(int plane, int a) const { return w[4 * NS + plane * NA + a]; }
-  __device__ uint32_t apple_evt(int a) const { return __float_as_uint(w[4 * NS + 13 * NA + NS + a]); }
+  __device__ uint32_t apple_evt(int a) const { return __float_as_uint(w[4 * NS + P * NA + NS + a]); }
 };
 
 // Each pass is split, as in the forward step, into a load stage (the node's own data:
@@ -299,7 +299,9 @@ __device__ __forceinline__ void node_reverse(const DevModel& M, const DevState& 
     V3 F, T;
     const bool snp = in.snp != 0.f;
     const uint64_t hkey = (uint64_t)in.hk0 | ((uint64_t)in.hk1 << 32);
-    if (applied_force(M, I, i, splitmix64((uint64_t)n), s_call, m, snp, hkey, F, T)) zb = zb - (0.5f * l) * cross(F, na);
+    // (models with the rails on are not differentiated, so vc only completes the call)
+    const V3 vc = v + cross(om, (0.5f * l) * z);
+    if (applied_force(M, I, i, splitmix64((uint64_t)n), s_call, m, snp, hkey, vc, F, T)) zb = zb - (0.5f * l) * cross(F, na);
   }
   zb = fma3(0.5f * m * l, hb, zb);
 
@@ -532,7 +534,7 @@ __global__ __launch_bounds__(NT) void k_adjoint_packs(DevModel M, DevState W, co
   const int pk = blockIdx.x;
   const int lb = ldc(M.pack_lvl, pk), le = ldc(M.pack_lvl, pk + 1) - 1;
   const int64_t n = *W.step - 1;  // the forward step just taken on W
-  const RecView R0{rec, M.n_seg, M.n_apple};
+  const RecView R0{rec, M.n_seg, M.n_apple, M.apl};
   Lvl L;
   L.i0 = ldc(M.pack_node, pk) & ~63;
   L.nf = M.scr_nf;

@@ -70,6 +70,7 @@ struct orchard_model_s {
   size_t an_bytes = 0;                                // dense apple-node arrays after the scratch blocks
   int32_t n_anode = 0;
   int device = 0;                                     // the device the model lives on
+  int32_t apl = 13;                                   // float planes of the apple state
   size_t lds_bytes = 0;                               // dynamic LDS of the step kernels
   float* kp0 = nullptr;
   float* kd0 = nullptr;
@@ -159,6 +160,13 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       !(d->tension_factor > 0) || !(d->v_cap > 0) || !(d->react_max_factor > 0) || d->wrench_fraction < 0 ||
       d->wrench_fraction > 1)
     return fail(ORCHARD_ERR_INVALID_ARG, "step constant out of range");
+  if (d->stiffness_k0 < 0 || (d->stiffness_k0 > 0 && !(d->stiffness_gamma > 0)) ||
+      (d->fruit_dof != 0 && d->fruit_dof != 3 && d->fruit_dof != 6))
+    return fail(ORCHARD_ERR_INVALID_ARG, "variant out of range (stiffness_k0 >= 0, stiffness_gamma > 0, fruit_dof 0, 3 or 6)");
+  if (d->drag_lin < 0 || d->drag_ang < 0 || d->drag_snapped < 0 || d->friction_base < 0 || d->friction_growth < 0 ||
+      d->friction_ramp_time < 0 || d->friction_speed < 0 || d->fade_speed < 0 || d->brake_rate < 0 ||
+      (d->friction_base > 0 && !(d->friction_speed > 0)))
+    return fail(ORCHARD_ERR_INVALID_ARG, "extra out of range (all >= 0; friction needs friction_speed > 0)");
   orchard_tuning_t tun{128, 1.0f, 1, 0, 0, 128, 0};
   if (tuning) tun = *tuning;
   if (tun.lds_width < 0 || tun.lds_width > tun.threads)
@@ -179,7 +187,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     return fail(ORCHARD_ERR_INVALID_ARG, "missing apple array");
 
   // ---- validation and FP64 derived parameters ----
-  std::vector<double> mass(NS), Jt(NS), Iax(NS), kp(NS), mmax(NS), kd(NS);
+  std::vector<double> mass(NS), Jt(NS), Iax(NS), kp(NS), mmax(NS), kd(NS), wmom(NS, 0.0);
   std::vector<DM3> Rw(NS);
   std::vector<D3> pw(NS);
   std::vector<int32_t> depth(NS);
@@ -213,6 +221,20 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
         Rw[g] = mm(Rw[gp], Q);
         pw[g] = add(pw[gp], scl(d->seg_length[gp], d3(Rw[gp].m[2], Rw[gp].m[5], Rw[gp].m[8])));
         depth[g] = depth[gp] + 1;
+      }
+      // per-level exponential model: each level below the root scales the stiffness by gamma
+      if (d->stiffness_k0 > 0) kp[g] = d->stiffness_k0 * std::pow(d->stiffness_gamma, depth[g]);
+    }
+    // friction scale of each joint: its limb's largest weight moment, every body of the
+    // sub-tree at the distance of its centre of mass from the joint point (rest pose)
+    if (d->friction_base > 0) {
+      const double gn = std::sqrt(d->gravity[0] * d->gravity[0] + d->gravity[1] * d->gravity[1] + d->gravity[2] * d->gravity[2]);
+      for (int g = s0; g < s1; ++g) {
+        const D3 c = add(pw[g], scl(0.5 * d->seg_length[g], d3(Rw[g].m[2], Rw[g].m[5], Rw[g].m[8])));
+        for (int j = g - s0; j >= 0; j = d->seg_parent[s0 + j]) {
+          const D3 r = sub(c, pw[s0 + j]);
+          wmom[s0 + j] += gn * mass[g] * std::sqrt(ddot(r, r));
+        }
       }
     }
     // composite rotational inertia of every sub-tree about its joint point at rest:
@@ -454,7 +476,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   std::vector<int32_t> par_i(NS), child_i(NS), nchild_i(NS, 0), env_i(NS), orig_i(NS);
   std::vector<float4> rq(NS), geo(NS);
   std::vector<float> seglen(NS);
-  std::vector<float> mmax_f(NS), kp_f(NS), kd_f(NS);
+  std::vector<float> mmax_f(NS), kp_f(NS), kd_f(NS), wmom_f(NS);
   std::vector<int32_t> env_of_g(NS);
   for (int e = 0; e < B; ++e)
     for (int g = d->seg_offset[e]; g < d->seg_offset[e + 1]; ++g) env_of_g[g] = e;
@@ -472,6 +494,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     mmax_f[i] = (float)mmax[g];
     kp_f[i] = (float)kp[g];
     kd_f[i] = (float)kd[g];
+    wmom_f[i] = (float)wmom[g];
   }
   for (int64_t i = NS - 1; i >= 0; --i) {
     const int p = par_i[i];
@@ -567,6 +590,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
          o_nr = ar.put(nrec.data(), NS * sizeof(NodeRec)), o_ar2 = ar.put(arec.data(), NA * sizeof(AppleRec)),
          o_hk = ar.put(hkey.data(), NS * 8), o_pa = ar.put(pack_apl.data(), pack_apl.size() * 4),
          o_nt = ar.put(ntopo.data(), NS * 16), o_len = ar.put(seglen.data(), NS * 4),
+         o_wm = ar.put(wmom_f.data(), NS * 4),
          o_q = ar.put(&zero, 4 * 16);
   hipError_t he = hipMalloc(&M->arena, ar.off + 256);
   if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
@@ -618,6 +642,17 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.seed = d->rng_seed;
   dm.rng_thr = (uint32_t)std::floor(d->wrench_fraction * 16777216.0);
   dm.wsig = (float)d->wrench_sigma;
+  dm.apl = d->fruit_dof == 3 ? 6 : 13;
+  dm.drag = (d->drag_lin > 0 || d->drag_ang > 0) ? 1 : 0;
+  dm.rails = (d->fade_speed > 0 || d->brake_rate > 0) ? 1 : 0;
+  dm.fric = d->friction_base > 0 ? 1 : 0;
+  dm.drag_lin = (float)d->drag_lin; dm.drag_ang = (float)d->drag_ang; dm.drag_snp = (float)d->drag_snapped;
+  dm.fric_base = (float)d->friction_base; dm.fric_growth = (float)d->friction_growth;
+  dm.fric_inv_ramp = d->friction_ramp_time > 0 ? (float)(1.0 / d->friction_ramp_time) : -1.f;  // < 0: no ramp
+  dm.fric_speed = (float)d->friction_speed;
+  dm.fade = (float)d->fade_speed; dm.brake = (float)d->brake_rate;
+  dm.wmom = (const float*)(base + o_wm);
+  M->apl = dm.apl;
   dm.scr = M->scr;
   dm.asnap = (float*)((char*)M->scr + scr_bytes);
   dm.aext = dm.asnap + (size_t)std::max<int32_t>(n_anode, 1) * K_N;
@@ -650,7 +685,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     // work state: q, qd (float2), apple (13A), seg_evt (2S), apple_evt (4A), evt_step (S+A), status (B),
     // step; every piece starts on a 256-byte boundary
     auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
-    const size_t wb = 2 * r256(8 * (size_t)NS) + r256(52 * (size_t)NA) + r256(2 * (size_t)NS) + r256(4 * (size_t)NA) +
+    const size_t wb = 2 * r256(8 * (size_t)NS) + r256(4 * (size_t)M->apl * NA) + r256(2 * (size_t)NS) + r256(4 * (size_t)NA) +
                       r256(4 * (size_t)(NS + NA)) + r256(4 * (size_t)B) + r256(8);
     if (hipMalloc(&M->recs, rb) != hipSuccess || hipMalloc(&M->work, 2 * wb) != hipSuccess ||
         (pb > 0 && hipMalloc(&M->reps, pb) != hipSuccess)) {
@@ -669,7 +704,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     char* w = (char*)M->work;
     auto take = [&](size_t b) { char* r = w; w += (b + 255) & ~size_t(255); return r; };
     for (DevState* ws : {&M->ws, &M->ws2}) {
-      ws->q = (float2*)take(8 * NS); ws->qd = (float2*)take(8 * NS); ws->apple = (float*)take(52 * NA);
+      ws->q = (float2*)take(8 * NS); ws->qd = (float2*)take(8 * NS); ws->apple = (float*)take(4 * (size_t)M->apl * NA);
       ws->seg_evt = (uint8_t*)take(2 * NS); ws->apple_evt = (uint8_t*)take(4 * NA);
       ws->evt_step = (int32_t*)take(4 * (NS + NA)); ws->status = (uint32_t*)take(4 * B); ws->step = (int64_t*)take(8);
     }
@@ -696,6 +731,7 @@ orchard_status_t orchard_model_layout(orchard_model_t m, orchard_layout_t* out) 
   if (!m || !out) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
   out->n_env = m->n_env; out->n_seg = m->n_seg; out->n_apple = m->n_apple;
   out->n_pack = m->n_pack; out->max_depth = m->max_depth; out->scratch_bytes = m->bytes;
+  out->apple_planes = m->apl; out->pad = 0;
   return ORCHARD_OK;
 }
 
@@ -742,7 +778,7 @@ orchard_status_t orchard_state_rest(orchard_model_t m, const orchard_state_t* s,
 }
 
 int64_t orchard_ckpt_words(orchard_model_t m) {
-  return 4LL * m->n_seg + 13LL * m->n_apple + m->n_seg + m->n_apple + m->n_seg + m->n_apple + m->n_env + 2;
+  return 4LL * m->n_seg + (int64_t)m->apl * m->n_apple + m->n_seg + m->n_apple + m->n_seg + m->n_apple + m->n_env + 2;
 }
 
 static orchard_status_t launch_steps(orchard_model_t m, const DevModel& dm0, const DevState& ds, const DevInputs& di,
@@ -948,6 +984,8 @@ orchard_status_t orchard_step_backward(orchard_model_t m, const float* ckpt, int
     return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
   if (m->n_apple > 0 && (!adj->apple_x || !adj->apple_v)) return fail(ORCHARD_ERR_INVALID_ARG, "apple adjoint missing");
   if (m->adj_kmax <= 0) return fail(ORCHARD_ERR_INVALID_ARG, "model created without adjoint support (tuning.adjoint_ckpt_max)");
+  if (m->dm.drag || m->dm.rails || m->dm.fric)
+    return fail(ORCHARD_ERR_INVALID_ARG, "the adjoint does not cover drag, post-break friction or the power fade / speed brake");
   if (ckpt_every < 1 || ckpt_every > m->adj_kmax) return fail(ORCHARD_ERR_INVALID_ARG, "ckpt_every out of [1, adjoint_ckpt_max]");
   if (n_steps < 0) return fail(ORCHARD_ERR_INVALID_ARG, "n_steps < 0");
   DevInputs di{params->kp, params->kd, nullptr, 0, nullptr, 0};

@@ -138,6 +138,13 @@ struct DevModel {
   uint64_t seed;
   uint32_t rng_thr;
   float wsig;
+  int32_t apl;               // float planes of the apple state: 13 (rigid body) or 6 (translational)
+  // extras (all off at 0): drag, post-break friction ramp, power fade, speed brake
+  int32_t drag, rails, fric;  // which are on
+  float drag_lin, drag_ang, drag_snp;
+  float fric_base, fric_growth, fric_inv_ramp, fric_speed;
+  float fade, brake;
+  const float* wmom;         // per node: the limb's largest weight moment (friction scale)
   float* scr;                // blocks of 64 nodes, each [scr_nf][64] floats (see scr_idx)
   float* asnap;              // [n_anode][K_N] kinematics of the nodes that carry apples
   float* aext;               // [n_anode][E_N] apple sums per node that carries apples
@@ -248,9 +255,11 @@ __host__ __device__ __forceinline__ uint64_t rng_node_key(uint64_t seed, uint64_
 
 // Applied force on segment i at the step whose key is kstep = splitmix64(step): the input
 // wrench plus the counter-based random force (node key hkey), disabled on a snapped
-// sub-tree, the force impulse-capped at m v_cap / h.  Returns false if there is none.
+// sub-tree; then, with the rails on, the power fade and the speed brake on the body's
+// centre-of-mass velocity vc; last the impulse cap |F| <= m v_cap / h.  Returns false if
+// there is none.
 __device__ __forceinline__ bool applied_force(const DevModel& M, const DevInputs& I, int i, uint64_t kstep, int s_call,
-                                              float m, bool snp, uint64_t hkey, V3& F, V3& T) {
+                                              float m, bool snp, uint64_t hkey, V3 vc, V3& F, V3& T) {
   F = v3(0, 0, 0);
   T = v3(0, 0, 0);
   if (snp) return false;
@@ -278,6 +287,21 @@ __device__ __forceinline__ bool applied_force(const DevModel& M, const DevInputs
       sincosf(6.283185307179586f * u3, &s3, &c3);
       F = F + M.wsig * v3(r0 * c1v, r0 * s1, r1 * c3);
       any = true;
+    }
+  }
+  if (any && M.rails) {
+    const float sp = sqrtf(dot(vc, vc));
+    if (sp > 0.f) {
+      const V3 u = (1.f / sp) * vc;
+      const float fu = dot(F, u);
+      // power fade: the push along the motion falls from full at the fade speed to
+      // nothing at twice it
+      if (M.fade > 0.f && fu > 0.f && sp > M.fade) {
+        const float phi = fmaxf(0.f, 1.f - (sp - M.fade) / M.fade);
+        F = F - ((1.f - phi) * fu) * u;
+      }
+      // soft speed brake above the speed limit
+      if (M.brake > 0.f && sp > M.vcap) F = F - (M.brake * m * (sp - M.vcap)) * u;
     }
   }
   if (any) {

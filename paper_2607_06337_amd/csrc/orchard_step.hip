@@ -59,9 +59,10 @@ __device__ __forceinline__ void vel_product(V3 a0, V3 a1, float2 qd, V3 wi, V3 v
 }
 
 // Bias wrench (ang, lin) of a segment's own body about its joint point: v x* (I v) minus
-// the applied body force (input and counter-based random, impulse-capped, none on a
-// snapped sub-tree) acting at the segment's midpoint.  Down 1 needs none of it; the up
-// pass forms it from the stored velocities.
+// the applied body force (input and counter-based random, through the rails and the
+// impulse cap, none on a snapped sub-tree) and, with drag on, minus the drag wrench, both
+// acting at the segment's midpoint.  Down 1 needs none of it; the up pass forms it from
+// the stored velocities.
 __device__ __forceinline__ void body_bias(const DevModel& M, const DevInputs& I, int i, uint64_t kstep, int s_call,
                                           float4 geo, V3 z, V3 wi, V3 v, bool snp, uint64_t hkey, V3& pang, V3& plin) {
   const float l = geo.x, m = geo.y;
@@ -72,10 +73,23 @@ __device__ __forceinline__ void body_bias(const DevModel& M, const DevInputs& I,
   const V3 Lm = m * v - cross(ho, wi);
   pang = cross(wi, K) + cross(v, Lm);
   plin = cross(wi, Lm);
+  const V3 rc = (0.5f * l) * z;          // joint point -> centre of mass
+  const V3 vc = v + cross(wi, rc);       // centre-of-mass velocity
   V3 F, T;
-  if (applied_force(M, I, i, kstep, s_call, m, snp, hkey, F, T)) {
-    pang = pang - (T + cross(0.5f * (l * z), F));
+  if (applied_force(M, I, i, kstep, s_call, m, snp, hkey, vc, F, T)) {
+    pang = pang - (T + cross(rc, F));
     plin = plin - F;
+  }
+  if (M.drag) {
+    // velocity-proportional drag F = -c_v m v_c, tau = -c_w I_c w (inertia about the
+    // centre of mass), reduced on a snapped sub-tree
+    const float f = snp ? M.drag_snp : 1.f;
+    const float Itc = geo.z - 0.25f * m * l * l, Ia = geo.w;
+    const V3 Iw = fma3((Ia - Itc) * dot(z, wi), z, Itc * wi);
+    const V3 Fd = (-f * M.drag_lin * m) * vc;
+    const V3 Td = (-f * M.drag_ang) * Iw;
+    pang = pang - (Td + cross(rc, Fd));
+    plin = plin - Fd;
   }
 }
 
@@ -364,9 +378,9 @@ __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S
       if (live) {
         at(Pa, ua) = x.x; at(Pa, NA + ua) = x.y; at(Pa, 2 * NA + ua) = x.z;
         at(Pa, 3 * NA + ua) = va.x; at(Pa, 4 * NA + ua) = va.y; at(Pa, 5 * NA + ua) = va.z;
-        // orientation: no torque acts on an apple, so omega is carried and the
-        // quaternion only turns while omega is non-zero
-        const V3 om = v3(at(Pa, 10 * NA + ua), at(Pa, 11 * NA + ua), at(Pa, 12 * NA + ua));
+        // orientation (rigid-body fruit only): no torque acts on an apple, so omega is
+        // carried and the quaternion only turns while omega is non-zero
+        const V3 om = M.apl == 13 ? v3(at(Pa, 10 * NA + ua), at(Pa, 11 * NA + ua), at(Pa, 12 * NA + ua)) : v3(0, 0, 0);
         const V3 hw = (0.5f * h) * om;
         const float th = sqrtf(dot(hw, hw));
         if (th > 0.f) {
@@ -502,8 +516,18 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevState& S, co
   // spring / damper with the implicit diagonal; a broken joint has none
   const float h = M.h;
   const bool brk = fl.brk;
-  const float kpe = brk ? 0.f : in.kp, kde = brk ? 0.f : in.kd;
   const float2 q = in.q, qd = in.qd;
+  const float kpe = brk ? 0.f : in.kp;
+  float kde = brk ? 0.f : in.kd;
+  if (brk && M.fric) {
+    // Coulomb friction of the torn fibres: tau_c ramps linearly from friction_base to
+    // friction_growth x friction_base of the limb's weight moment, acting as the linearly
+    // implicit damper tau_c / max(|qd|, friction_speed)
+    const int64_t nb = fl.brk0 ? (int64_t)at(S.evt_step, (uint32_t)i) : n;  // step of the break
+    const float ramp = M.fric_inv_ramp < 0.f ? 1.f : fminf(1.f, (float)(n - nb) * h * M.fric_inv_ramp);
+    const float tc = M.fric_base * at(M.wmom, (uint32_t)i) * fmaf(M.fric_growth - 1.f, ramp, 1.f);
+    kde = tc / fmaxf(sqrtf(fmaf(qd.x, qd.x, qd.y * qd.y)), M.fric_speed);
+  }
   const float tau0 = -kpe * fmaf(h, qd.x, q.x) - kde * qd.x;
   const float tau1 = -kpe * fmaf(h, qd.y, q.y) - kde * qd.y;
   const float dg = fmaf(h, kde, h * h * kpe);
@@ -973,8 +997,11 @@ __global__ void k_state_rest(DevModel M, DevState S, const float* apple_rest) {
       S.evt_step[i] = -1;
     } else {
       const int a = (int)(k - NS);
-      for (int c = 0; c < 3; ++c) { S.apple[c * NA + a] = apple_rest[c * NA + a]; S.apple[(3 + c) * NA + a] = 0.f; S.apple[(10 + c) * NA + a] = 0.f; }
-      S.apple[6 * NA + a] = 1.f; S.apple[7 * NA + a] = 0.f; S.apple[8 * NA + a] = 0.f; S.apple[9 * NA + a] = 0.f;
+      for (int c = 0; c < 3; ++c) { S.apple[c * NA + a] = apple_rest[c * NA + a]; S.apple[(3 + c) * NA + a] = 0.f; }
+      if (M.apl == 13) {
+        for (int c = 0; c < 3; ++c) S.apple[(10 + c) * NA + a] = 0.f;
+        S.apple[6 * NA + a] = 1.f; S.apple[7 * NA + a] = 0.f; S.apple[8 * NA + a] = 0.f; S.apple[9 * NA + a] = 0.f;
+      }
       for (int c = 0; c < 4; ++c) S.apple_evt[c * NA + a] = 0;
       S.evt_step[NS + a] = -1;
     }
@@ -984,21 +1011,22 @@ __global__ void k_state_rest(DevModel M, DevState S, const float* apple_rest) {
 }
 
 // checkpoint: copy the state into one contiguous 32-bit record
-//   q (2S) qd (2S) apple (13A) seg_evt (S words) apple_evt (A words) evt_step (S+A) status (B) step (2)
+//   q (2S) qd (2S) apple (P A, P planes) seg_evt (S words) apple_evt (A words) evt_step (S+A) status (B) step (2)
 __device__ __forceinline__ int64_t ckpt_words(const DevModel& M) {
-  return 4LL * M.n_seg + 13LL * M.n_apple + M.n_seg + M.n_apple + M.n_seg + M.n_apple + M.n_env + 2;
+  return 4LL * M.n_seg + (int64_t)M.apl * M.n_apple + M.n_seg + M.n_apple + M.n_seg + M.n_apple + M.n_env + 2;
 }
 
 __global__ void k_ckpt_save(DevModel M, DevState S, uint32_t* out) {
   const int NS = M.n_seg, NA = M.n_apple, NB = M.n_env;
+  const int64_t PA = (int64_t)M.apl * NA;
   const int64_t tot = ckpt_words(M);
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = k;
     uint32_t v;
     if (j < 2LL * NS) v = __float_as_uint(reinterpret_cast<const float*>(S.q)[j]);
     else if ((j -= 2LL * NS) < 2LL * NS) v = __float_as_uint(reinterpret_cast<const float*>(S.qd)[j]);
-    else if ((j -= 2LL * NS) < 13LL * NA) v = __float_as_uint(S.apple[j]);
-    else if ((j -= 13LL * NA) < NS) v = (uint32_t)S.seg_evt[j] | ((uint32_t)S.seg_evt[NS + j] << 8);
+    else if ((j -= 2LL * NS) < PA) v = __float_as_uint(S.apple[j]);
+    else if ((j -= PA) < NS) v = (uint32_t)S.seg_evt[j] | ((uint32_t)S.seg_evt[NS + j] << 8);
     else if ((j -= NS) < NA) v = (uint32_t)S.apple_evt[j] | ((uint32_t)S.apple_evt[NA + j] << 8) |
                                  ((uint32_t)S.apple_evt[2 * NA + j] << 16) | ((uint32_t)S.apple_evt[3 * NA + j] << 24);
     else if ((j -= NA) < (int64_t)NS + NA) v = (uint32_t)S.evt_step[j];
@@ -1010,14 +1038,15 @@ __global__ void k_ckpt_save(DevModel M, DevState S, uint32_t* out) {
 
 __global__ void k_ckpt_load(DevModel M, DevState S, const uint32_t* in) {
   const int NS = M.n_seg, NA = M.n_apple, NB = M.n_env;
+  const int64_t PA = (int64_t)M.apl * NA;
   const int64_t tot = ckpt_words(M);
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = k;
     const uint32_t v = in[k];
     if (j < 2LL * NS) reinterpret_cast<float*>(S.q)[j] = __uint_as_float(v);
     else if ((j -= 2LL * NS) < 2LL * NS) reinterpret_cast<float*>(S.qd)[j] = __uint_as_float(v);
-    else if ((j -= 2LL * NS) < 13LL * NA) S.apple[j] = __uint_as_float(v);
-    else if ((j -= 13LL * NA) < NS) { S.seg_evt[j] = v & 255u; S.seg_evt[NS + j] = (v >> 8) & 255u; }
+    else if ((j -= 2LL * NS) < PA) S.apple[j] = __uint_as_float(v);
+    else if ((j -= PA) < NS) { S.seg_evt[j] = v & 255u; S.seg_evt[NS + j] = (v >> 8) & 255u; }
     else if ((j -= NS) < NA) {
       S.apple_evt[j] = v & 255u; S.apple_evt[NA + j] = (v >> 8) & 255u; S.apple_evt[2 * NA + j] = (v >> 16) & 255u;
       S.apple_evt[3 * NA + j] = (v >> 24) & 255u;

@@ -30,7 +30,15 @@ class Desc(C.Structure):
         ("tether_zeta", C.c_double), ("damping_zeta", C.c_double), ("damping_cd", C.c_double),
         ("tension_factor", C.c_double), ("v_cap", C.c_double), ("react_max_factor", C.c_double),
         ("n_break", C.c_int32), ("n_pull", C.c_int32), ("n_tension", C.c_int32), ("pad0", C.c_int32),
-        ("rng_seed", C.c_uint64), ("wrench_fraction", C.c_double), ("wrench_sigma", C.c_double)]
+        ("rng_seed", C.c_uint64), ("wrench_fraction", C.c_double), ("wrench_sigma", C.c_double),
+        ("stiffness_k0", C.c_double), ("stiffness_gamma", C.c_double), ("fruit_dof", C.c_int32), ("pad1", C.c_int32)] + [
+        (k, C.c_double) for k in ("drag_lin", "drag_ang", "drag_snapped", "friction_base", "friction_growth",
+                                  "friction_ramp_time", "friction_speed", "fade_speed", "brake_rate")]
+
+# descriptor fields a constants dict may leave out (their "off" values)
+_DESC_DEFAULTS = dict(stiffness_k0=0.0, stiffness_gamma=1.0, fruit_dof=6, drag_lin=0.0, drag_ang=0.0, drag_snapped=1.0,
+                      friction_base=0.0, friction_growth=1.0, friction_ramp_time=0.0, friction_speed=0.0,
+                      fade_speed=0.0, brake_rate=0.0)
 
 
 # the library's defaults (orchard_model_create with a null tuning)
@@ -50,7 +58,8 @@ class CAdjoint(C.Structure):
 
 class Layout(C.Structure):
     _fields_ = [("n_env", C.c_int64), ("n_seg", C.c_int64), ("n_apple", C.c_int64), ("n_pack", C.c_int32),
-                ("max_depth", C.c_int32), ("scratch_bytes", C.c_int64)]
+                ("max_depth", C.c_int32), ("scratch_bytes", C.c_int64), ("apple_planes", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class CState(C.Structure):
@@ -173,7 +182,7 @@ class State:
     """Device state of a batch (torch tensors, the model's internal order)."""
     q: "torch.Tensor"          # float32 [n_seg, 2]
     qd: "torch.Tensor"         # float32 [n_seg, 2]
-    apple: "torch.Tensor"      # float32 [13, n_apple]
+    apple: "torch.Tensor"      # float32 [apple_planes, n_apple] (13, or 6 for a translational fruit)
     seg_evt: "torch.Tensor"    # uint8 [2, n_seg]
     apple_evt: "torch.Tensor"  # uint8 [4, n_apple]
     evt_step: "torch.Tensor"   # int32 [n_seg + n_apple]
@@ -213,6 +222,8 @@ def _desc(batch, consts: dict, keep: list) -> Desc:
     for k in ("n_break", "n_pull", "n_tension"):
         setattr(d, k, int(consts[k]))
     d.rng_seed = int(consts["rng_seed"])
+    for k, v in _DESC_DEFAULTS.items():
+        setattr(d, k, type(v)(consts.get(k, v)))
     return d
 
 
@@ -309,6 +320,7 @@ class Model:
         lay = Layout()
         _check(L.orchard_model_layout(self.h, C.byref(lay)))
         self.n_env, self.n_seg, self.n_apple = int(lay.n_env), int(lay.n_seg), int(lay.n_apple)
+        self.apple_planes = int(lay.apple_planes)
         self.n_pack, self.max_depth, self.scratch_bytes = int(lay.n_pack), int(lay.max_depth), int(lay.scratch_bytes)
         self.seg_map = np.zeros(self.n_seg, np.int32)
         self.apple_map = np.zeros(self.n_apple, np.int32)
@@ -327,7 +339,7 @@ class Model:
         import torch
         dev = torch.device("cuda")
         return State(q=torch.zeros(self.n_seg, 2, device=dev), qd=torch.zeros(self.n_seg, 2, device=dev),
-                     apple=torch.zeros(13, self.n_apple, device=dev),
+                     apple=torch.zeros(self.apple_planes, self.n_apple, device=dev),
                      seg_evt=torch.zeros(2, self.n_seg, dtype=torch.uint8, device=dev),
                      apple_evt=torch.zeros(4, self.n_apple, dtype=torch.uint8, device=dev),
                      evt_step=torch.full((self.n_seg + self.n_apple,), -1, dtype=torch.int32, device=dev),
