@@ -199,12 +199,31 @@ orchard_status_t orchard_model_maps(orchard_model_t model, int32_t* seg_map, int
 /* Rest hang points of the apples, host double [n_apple][3], internal order (the
  * origin of a detached apple's position state).  Attached apples keep their stretch
  * relative to the current hang point as state, so the stiff tether never sees
- * absolute-position round-off in FP32. */
+ * absolute-position round-off in FP32.  Synchronises the device (the points follow
+ * orchard_model_rebuild). */
 orchard_status_t orchard_model_apple_rest(orchard_model_t model, double* host_out);
 
 /* Derived Kp, Kd (device arrays [n_seg], internal order) -- the defaults of the
  * differentiable parameters. */
 orchard_status_t orchard_default_params(orchard_model_t model, float* kp, float* kd, orchard_stream_t stream);
+
+/* On-device rebuild of every world's geometry (Sec. "Parallelism and cost": the
+ * per-world geometry build as one kernel, one thread per world).  seg_perturb: device
+ * double [n_seg][4] in DESCRIPTOR order — length factor, radius factor, and a bend of the
+ * segment's rest orientation about its own x axis then its y axis (radians).  The
+ * factors apply to the descriptor values given at create; every parameter that depends
+ * on them is derived again on the device in FP64 with the operations create uses (mass
+ * properties, Kp by Eq. beam or the per-level model, M_max by Eq. break, Kd from the rest
+ * mass-matrix diagonal, the friction scale, the rest pose and the fruit's rest hang
+ * points; a hang point keeps its place in its segment's frame, scaled with the length).
+ * Factors (1, 1, 0, 0) reproduce the created model.  Topology, packing, fruit masses and
+ * detach forces are unchanged; the default gains change, so call orchard_default_params
+ * again.  A world with a non-positive or non-finite factor is left as it is and counted
+ * in *rejected (device int32, nullable, zeroed by the call).  Stream-ordered, no
+ * allocation; it uses the model's step scratch as workspace, so it must not overlap a
+ * step of the same model. */
+orchard_status_t orchard_model_rebuild(orchard_model_t model, const double* seg_perturb, int32_t* rejected,
+                                       orchard_stream_t stream);
 
 /* Rest state: q = qd = 0 (the generated skeleton pose), apples hanging
  * m |g| / k_s below their hang point at rest, counters and flags zero, event steps

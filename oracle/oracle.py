@@ -411,3 +411,29 @@ def adjoint(o, env, x0, kp, kd, F, n_steps, tips, target, step0=0, w_state=None)
     g0 = dict(q=gx[:2 * S].reshape(S, 2), qd=gx[2 * S:4 * S].reshape(S, 2), ax=gx[4 * S:4 * S + 3 * A].reshape(A, 3),
               av=gx[4 * S + 3 * A:].reshape(A, 3))
     return v, gkp, gkd, gF, g0
+
+
+# ---- per-world geometry perturbation (the on-device rebuild's definition) --------------
+def _qmul(a, b):
+    """Hamilton product of quaternions (w, x, y, z), row-wise."""
+    w1, x1, y1, z1 = a[..., 0], a[..., 1], a[..., 2], a[..., 3]
+    w2, x2, y2, z2 = b[..., 0], b[..., 1], b[..., 2], b[..., 3]
+    return np.stack([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2], axis=-1)
+
+
+def perturbed_batch(batch, factors):
+    """The batch with every segment's length and radius scaled by factors[:, 0] and [:, 1]
+    and its rest orientation bent by factors[:, 2] about its own x axis, then by
+    factors[:, 3] about its y axis; a fruit's hang point keeps its place in its segment's
+    frame, scaled with the segment's length.  factors: [S_tot, 4] descriptor order."""
+    from dataclasses import replace
+    f = np.asarray(factors, np.float64)
+    zero = np.zeros(len(f))
+    qx = np.stack([np.cos(f[:, 2] / 2), np.sin(f[:, 2] / 2), zero, zero], axis=1)
+    qy = np.stack([np.cos(f[:, 3] / 2), zero, np.sin(f[:, 3] / 2), zero], axis=1)
+    quat = _qmul(_qmul(batch.seg_rest_quat, qx), qy)
+    env_of_apple = np.repeat(np.arange(batch.n_env), np.diff(batch.apple_offset))
+    gseg = batch.seg_offset[env_of_apple] + batch.apple_seg
+    return replace(batch, seg_length=batch.seg_length * f[:, 0], seg_radius=batch.seg_radius * f[:, 1],
+                   seg_rest_quat=quat, apple_hang=batch.apple_hang * f[gseg, 0:1])

@@ -153,6 +153,19 @@ def pull_forces(batch: Batch, seed: int = 2_000_000, fraction: float = 0.10,
     return np.where(sel[:, None], d * mag[:, None], 0.0)
 
 
+def geometry_perturbation(batch: Batch, seed: int = 5_000_000, strength: float = 1.0) -> np.ndarray:
+    """Per-world geometry perturbation for the on-device rebuild: [S_tot, 4] float64 in
+    descriptor order — length factor 1 + 0.25 s U(-1, 1), radius factor 1 + 0.15 s U(-1, 1),
+    bends about the segment's x and y axes s N(0, 4 deg) each.  s = 0 gives (1, 1, 0, 0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    S = batch.n_seg
+    f = np.empty((S, 4))
+    f[:, 0] = 1.0 + 0.25 * strength * rng.uniform(-1.0, 1.0, S)
+    f[:, 1] = 1.0 + 0.15 * strength * rng.uniform(-1.0, 1.0, S)
+    f[:, 2:] = strength * np.deg2rad(4.0) * rng.normal(size=(S, 2))
+    return f
+
+
 def grad_apple_forces(batch: Batch, n_steps: int, seed: int = 4_000_000,
                       sigma: float = 2.0) -> np.ndarray:
     """Per-step apple forces of the grad512 workload, N(0, sigma) per component.

@@ -13,7 +13,9 @@
 #include <vector>
 
 #include "../../include/orchard.h"
+#include "orchard_build.h"
 #include "orchard_dev.h"
+#include "orchard_rebuild.h"
 
 namespace orchard {
 
@@ -52,6 +54,12 @@ static orchard_status_t fail(orchard_status_t s, const std::string& msg) {
     if (_e != hipSuccess) return fail(ORCHARD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
   } while (0)
 
+// zero n counters (a kernel, not a memset, so that callers may capture the work)
+__global__ void k_zero_i32(int32_t* p, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0;
+}
+
 }  // namespace orchard
 
 using namespace orchard;
@@ -71,6 +79,7 @@ struct orchard_model_s {
   int32_t n_anode = 0;
   int device = 0;                                     // the device the model lives on
   int32_t apl = 13;                                   // float planes of the apple state
+  RebuildArgs rb{};                                   // the on-device rebuild's view of the model
   size_t lds_bytes = 0;                               // dynamic LDS of the step kernels
   float* kp0 = nullptr;
   float* kd0 = nullptr;
@@ -92,29 +101,12 @@ struct orchard_model_s {
 
 namespace {
 
-struct D3 { double x, y, z; };
-inline D3 d3(double a, double b, double c) { return D3{a, b, c}; }
-inline D3 add(D3 a, D3 b) { return d3(a.x + b.x, a.y + b.y, a.z + b.z); }
-inline D3 sub(D3 a, D3 b) { return d3(a.x - b.x, a.y - b.y, a.z - b.z); }
-inline D3 scl(double s, D3 a) { return d3(s * a.x, s * a.y, s * a.z); }
-inline double ddot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-struct DM3 { double m[9]; };
-inline DM3 mm(const DM3& a, const DM3& b) {
-  DM3 r;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) r.m[3 * i + j] = a.m[3 * i] * b.m[j] + a.m[3 * i + 1] * b.m[3 + j] + a.m[3 * i + 2] * b.m[6 + j];
-  return r;
-}
-inline D3 mv(const DM3& a, D3 v) {
-  return d3(a.m[0] * v.x + a.m[1] * v.y + a.m[2] * v.z, a.m[3] * v.x + a.m[4] * v.y + a.m[5] * v.z,
-            a.m[6] * v.x + a.m[7] * v.y + a.m[8] * v.z);
-}
-inline DM3 quatm(const double* q) {
-  const double w = q[0], x = q[1], y = q[2], z = q[3];
-  return DM3{{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y), 2 * (x * y + w * z),
-              1 - 2 * (x * x + z * z), 2 * (y * z - w * x), 2 * (x * z - w * y), 2 * (y * z + w * x),
-              1 - 2 * (x * x + y * y)}};
-}
+using build::D3;
+using build::DM3;
+using build::add;
+using build::d3;
+using build::ddot;
+using build::mv;
 
 struct Arena {
   size_t off = 0;
@@ -147,6 +139,17 @@ extern "C" {
 
 const char* orchard_last_error(void) { return g_err.c_str(); }
 int64_t orchard_ckpt_words(orchard_model_t m);
+
+static build::DeriveConsts derive_consts(const orchard_model_desc_t* d) {
+  build::DeriveConsts c;
+  c.stiffness_k0 = d->stiffness_k0;
+  c.stiffness_gamma = d->stiffness_gamma;
+  c.damping_cd = d->damping_cd;
+  c.damping_zeta = d->damping_zeta;
+  c.gnorm = std::sqrt(d->gravity[0] * d->gravity[0] + d->gravity[1] * d->gravity[1] + d->gravity[2] * d->gravity[2]);
+  c.friction = d->friction_base > 0 ? 1 : 0;
+  return c;
+}
 
 orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orchard_tuning_t* tuning,
                                       orchard_model_t* out) {
@@ -187,10 +190,12 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     return fail(ORCHARD_ERR_INVALID_ARG, "missing apple array");
 
   // ---- validation and FP64 derived parameters ----
-  std::vector<double> mass(NS), Jt(NS), Iax(NS), kp(NS), mmax(NS), kd(NS), wmom(NS, 0.0);
+  std::vector<double> mass(NS), Jt(NS), Iax(NS), kp(NS), mmax(NS), kd(NS), wmom(NS, 0.0), qn(4 * NS);
   std::vector<DM3> Rw(NS);
   std::vector<D3> pw(NS);
   std::vector<int32_t> depth(NS);
+  const build::DeriveConsts dc = derive_consts(d);
+  std::vector<double> tmp;
   for (int e = 0; e < B; ++e) {
     const int s0 = d->seg_offset[e], s1 = d->seg_offset[e + 1];
     for (int g = s0; g < s1; ++g) {
@@ -203,94 +208,14 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       const double* q = d->seg_rest_quat + 4 * (int64_t)g;
       const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
       if (!(std::fabs(nq - 1.0) <= 1e-6)) return fail(ORCHARD_ERR_INVALID_TOPOLOGY, "rest quaternion not unit");
-      // capsule: cylinder + two hemispheres
-      const double mc = rho * M_PI * r * r * l, mh = rho * 4.0 / 3.0 * M_PI * r * r * r;
-      mass[g] = mc + mh;
-      Iax[g] = mc * r * r / 2.0 + mh * 2.0 * r * r / 5.0;
-      const double It = mc * (l * l / 12.0 + r * r / 4.0) + mh * (2.0 * r * r / 5.0 + l * l / 4.0 + 3.0 * l * r / 8.0);
-      Jt[g] = It + mass[g] * l * l / 4.0;  // transverse inertia about the joint point
-      kp[g] = M_PI / 4.0 * d->seg_youngs[g] * r * r * r * r / l;  // Eq. beam
-      mmax[g] = d->seg_mor[g] * M_PI * r * r * r / 4.0;           // Eq. break
-      // rest pose
-      double qn[4] = {q[0] / nq, q[1] / nq, q[2] / nq, q[3] / nq};
-      const DM3 Q = quatm(qn);
-      if (p < 0) {
-        Rw[g] = Q; pw[g] = d3(0, 0, 0); depth[g] = 0;
-      } else {
-        const int gp = s0 + p;
-        Rw[g] = mm(Rw[gp], Q);
-        pw[g] = add(pw[gp], scl(d->seg_length[gp], d3(Rw[gp].m[2], Rw[gp].m[5], Rw[gp].m[8])));
-        depth[g] = depth[gp] + 1;
-      }
-      // per-level exponential model: each level below the root scales the stiffness by gamma
-      if (d->stiffness_k0 > 0) kp[g] = d->stiffness_k0 * std::pow(d->stiffness_gamma, depth[g]);
     }
-    // friction scale of each joint: its limb's largest weight moment, every body of the
-    // sub-tree at the distance of its centre of mass from the joint point (rest pose)
-    if (d->friction_base > 0) {
-      const double gn = std::sqrt(d->gravity[0] * d->gravity[0] + d->gravity[1] * d->gravity[1] + d->gravity[2] * d->gravity[2]);
-      for (int g = s0; g < s1; ++g) {
-        const D3 c = add(pw[g], scl(0.5 * d->seg_length[g], d3(Rw[g].m[2], Rw[g].m[5], Rw[g].m[8])));
-        for (int j = g - s0; j >= 0; j = d->seg_parent[s0 + j]) {
-          const D3 r = sub(c, pw[s0 + j]);
-          wmom[s0 + j] += gn * mass[g] * std::sqrt(ddot(r, r));
-        }
-      }
-    }
-    // composite rotational inertia of every sub-tree about its joint point at rest:
-    // accumulate mass, first moment and inertia about the world origin leaf -> root
-    const int S = s1 - s0;
-    std::vector<double> Msum(S, 0.0);
-    std::vector<D3> Csum(S, d3(0, 0, 0));
-    std::vector<std::array<double, 6>> JO(S);
-    for (int i = S - 1; i >= 0; --i) {
-      const int g = s0 + i;
-      const D3 z = d3(Rw[g].m[2], Rw[g].m[5], Rw[g].m[8]);
-      const D3 c = add(pw[g], scl(0.5 * d->seg_length[g], z));
-      const double It = Jt[g] - mass[g] * d->seg_length[g] * d->seg_length[g] / 4.0, dI = Iax[g] - It;
-      const double m = mass[g], cc = ddot(c, c);
-      std::array<double, 6>& J = JO[i];
-      J[0] += It + dI * z.x * z.x + m * (cc - c.x * c.x);
-      J[1] += It + dI * z.y * z.y + m * (cc - c.y * c.y);
-      J[2] += It + dI * z.z * z.z + m * (cc - c.z * c.z);
-      J[3] += dI * z.x * z.y - m * c.x * c.y;
-      J[4] += dI * z.x * z.z - m * c.x * c.z;
-      J[5] += dI * z.y * z.z - m * c.y * c.z;
-      Msum[i] += m;
-      Csum[i] = add(Csum[i], scl(m, c));
-      const int p = d->seg_parent[g];
-      if (p >= 0) {
-        for (int k = 0; k < 6; ++k) JO[p][k] += J[k];
-        Msum[p] += Msum[i];
-        Csum[p] = add(Csum[p], Csum[i]);
-      }
-    }
-    for (int i = 0; i < S; ++i) {
-      const int g = s0 + i, p = d->seg_parent[g];
-      const double M = Msum[i];
-      const D3 C = scl(1.0 / M, Csum[i]), P = pw[g], Cp = sub(C, P);
-      // J_P = J_O - M(|C|^2 1 - C C^T) + M(|C-P|^2 1 - (C-P)(C-P)^T)
-      const double cc = ddot(C, C), pp = ddot(Cp, Cp);
-      double J[6];
-      J[0] = JO[i][0] - M * (cc - C.x * C.x) + M * (pp - Cp.x * Cp.x);
-      J[1] = JO[i][1] - M * (cc - C.y * C.y) + M * (pp - Cp.y * Cp.y);
-      J[2] = JO[i][2] - M * (cc - C.z * C.z) + M * (pp - Cp.z * Cp.z);
-      J[3] = JO[i][3] + M * C.x * C.y - M * Cp.x * Cp.y;
-      J[4] = JO[i][4] + M * C.x * C.z - M * Cp.x * Cp.z;
-      J[5] = JO[i][5] + M * C.y * C.z - M * Cp.y * Cp.z;
-      const DM3 Rpar = p < 0 ? DM3{{1, 0, 0, 0, 1, 0, 0, 0, 1}} : Rw[s0 + p];
-      const double* q = d->seg_rest_quat + 4 * (int64_t)g;
-      const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-      double qn[4] = {q[0] / nq, q[1] / nq, q[2] / nq, q[3] / nq};
-      const DM3 Jf = mm(Rpar, quatm(qn));
-      const D3 a0 = d3(Jf.m[0], Jf.m[3], Jf.m[6]), a1 = d3(Rw[g].m[1], Rw[g].m[4], Rw[g].m[7]);
-      auto quad = [&](D3 a) {
-        return J[0] * a.x * a.x + J[1] * a.y * a.y + J[2] * a.z * a.z +
-               2.0 * (J[3] * a.x * a.y + J[4] * a.x * a.z + J[5] * a.y * a.z);
-      };
-      const double Jj = 0.5 * (quad(a0) + quad(a1));
-      kd[g] = d->damping_cd > 0 ? d->damping_cd * kp[g] : 2.0 * d->damping_zeta * std::sqrt(kp[g] * Jj);
-    }
+    tmp.resize(10 * (size_t)(s1 - s0));
+    const build::DeriveIO io{s1 - s0, d->seg_parent + s0, d->seg_rest_quat + 4 * (int64_t)s0, d->seg_length + s0,
+                             d->seg_radius + s0, d->seg_density + s0, d->seg_youngs + s0, d->seg_mor + s0,
+                             mass.data() + s0, Jt.data() + s0, Iax.data() + s0, kp.data() + s0, mmax.data() + s0,
+                             kd.data() + s0, wmom.data() + s0, qn.data() + 4 * (int64_t)s0, Rw.data() + s0,
+                             pw.data() + s0, depth.data() + s0, tmp.data()};
+    build::derive_tree(dc, io);
   }
   std::vector<float> arest(3 * NA);
   std::vector<float4> ahang_h(NA), apar_h(NA), ahrest_h(NA);
@@ -486,9 +411,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     child_i[i] = (int32_t)NS;  // no children marker, replaced below
     env_i[i] = e;
     orig_i[i] = g - s0;
-    const double* q = d->seg_rest_quat + 4 * (int64_t)g;
-    const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    rq[i] = make_float4((float)(q[0] / nq), (float)(q[1] / nq), (float)(q[2] / nq), (float)(q[3] / nq));
+    const double* q = qn.data() + 4 * (int64_t)g;
+    rq[i] = make_float4((float)q[0], (float)q[1], (float)q[2], (float)q[3]);
     geo[i] = make_float4((float)d->seg_length[g], (float)mass[g], (float)Jt[g], (float)Iax[g]);
     seglen[i] = geo[i].x;
     mmax_f[i] = (float)mmax[g];
@@ -517,7 +441,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     const D3 hl = d3(d->apple_hang[3 * a], d->apple_hang[3 * a + 1], d->apple_hang[3 * a + 2]);
     // attached apples store their stretch from the hang point (plus h v); at rest the
     // apple hangs m |g| / k_s below it
-    const D3 xh0 = add(pw[g], mv(Rw[g], hl));
+    const D3 xh0 = build::hang_point(Rw[g], pw[g], hl);
     ahang_rest[3 * k] = xh0.x; ahang_rest[3 * k + 1] = xh0.y; ahang_rest[3 * k + 2] = xh0.z;
     ahrest_h[k] = make_float4((float)xh0.x, (float)xh0.y, (float)xh0.z, 0.f);
     arest[k] = (float)(ma / d->tether_k * d->gravity[0]);
@@ -592,6 +516,16 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
          o_nt = ar.put(ntopo.data(), NS * 16), o_len = ar.put(seglen.data(), NS * 4),
          o_wm = ar.put(wmom_f.data(), NS * 4),
          o_q = ar.put(&zero, 4 * 16);
+  // the descriptor as given (descriptor order) and the order maps, for the on-device rebuild
+  std::vector<int32_t> int_apple_of(NA);
+  for (int64_t k = 0; k < NA; ++k) int_apple_of[aord[k]] = (int32_t)k;
+  const size_t o_bso = ar.put(d->seg_offset, (B + 1) * 4), o_bpar = ar.put(d->seg_parent, NS * 4),
+               o_bq = ar.put(d->seg_rest_quat, NS * 32), o_bl = ar.put(d->seg_length, NS * 8),
+               o_br = ar.put(d->seg_radius, NS * 8), o_brho = ar.put(d->seg_density, NS * 8),
+               o_bE = ar.put(d->seg_youngs, NS * 8), o_bmor = ar.put(d->seg_mor, NS * 8),
+               o_bao = ar.put(d->apple_offset, (B + 1) * 4), o_bas = ar.put(d->apple_seg, NA * 4),
+               o_bh = ar.put(d->apple_hang, NA * 24), o_io = ar.put(int_of.data(), NS * 4),
+               o_iao = ar.put(int_apple_of.data(), NA * 4), o_hr64 = ar.put(ahang_rest.data(), NA * 24);
   hipError_t he = hipMalloc(&M->arena, ar.off + 256);
   if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
   std::vector<char> zeros(64, 0);
@@ -652,6 +586,20 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.fric_speed = (float)d->friction_speed;
   dm.fade = (float)d->fade_speed; dm.brake = (float)d->brake_rate;
   dm.wmom = (const float*)(base + o_wm);
+  {
+    RebuildArgs& rb = M->rb;
+    rb.n_env = B; rb.n_seg = NS; rb.consts = dc;
+    rb.seg_off = (const int32_t*)(base + o_bso); rb.parent = (const int32_t*)(base + o_bpar);
+    rb.quat = (const double*)(base + o_bq); rb.blen = (const double*)(base + o_bl); rb.rad = (const double*)(base + o_br);
+    rb.rho = (const double*)(base + o_brho); rb.E = (const double*)(base + o_bE); rb.mor = (const double*)(base + o_bmor);
+    rb.apple_off = (const int32_t*)(base + o_bao); rb.aseg = (const int32_t*)(base + o_bas);
+    rb.hang = (const double*)(base + o_bh); rb.int_of = (const int32_t*)(base + o_io);
+    rb.int_apple_of = (const int32_t*)(base + o_iao);
+    rb.rq = (float4*)(base + o_rq); rb.nrec = (NodeRec*)(base + o_nr); rb.geo = (float4*)(base + o_geo);
+    rb.lenf = (float*)(base + o_len); rb.mmaxf = (float*)(base + o_mm); rb.kp0 = (float*)(base + o_kp);
+    rb.kd0 = (float*)(base + o_kd); rb.wmomf = (float*)(base + o_wm); rb.ahang = (float4*)(base + o_ah);
+    rb.arec = (AppleRec*)(base + o_ar2); rb.ahrest = (float4*)(base + o_hr); rb.ahrest64 = (double*)(base + o_hr64);
+  }
   M->apl = dm.apl;
   dm.scr = M->scr;
   dm.asnap = (float*)((char*)M->scr + scr_bytes);
@@ -744,7 +692,27 @@ orchard_status_t orchard_model_maps(orchard_model_t m, int32_t* seg_map, int32_t
 
 orchard_status_t orchard_model_apple_rest(orchard_model_t m, double* host_out) {
   if (!m || (!host_out && m->n_apple)) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
-  std::copy(m->apple_hang_rest.begin(), m->apple_hang_rest.end(), host_out);
+  // the device copy is the current one (orchard_model_rebuild rewrites it)
+  if (m->n_apple) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(host_out, m->rb.ahrest64, m->n_apple * 24, hipMemcpyDeviceToHost));
+  }
+  return ORCHARD_OK;
+}
+
+orchard_status_t orchard_model_rebuild(orchard_model_t m, const double* seg_perturb, int32_t* rejected,
+                                       orchard_stream_t stream) {
+  if (!m || !seg_perturb) return fail(ORCHARD_ERR_INVALID_ARG, "null model or perturbation");
+  // workspace: the model's step scratch (40 doubles per segment; it holds at least 128 floats each)
+  static_assert(N_FIELDS * 4 >= 40 * 8, "the step scratch holds the rebuild's workspace");
+  RebuildArgs a = m->rb;
+  a.factors = seg_perturb;
+  a.work = reinterpret_cast<double*>(m->scr);
+  a.rejected = rejected;
+  hipStream_t hs = (hipStream_t)stream;
+  if (rejected) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, hs, rejected, 1);
+  hipLaunchKernelGGL(k_rebuild, dim3((m->n_env + 63) / 64), dim3(64), 0, hs, a);
+  HIPCHK(hipGetLastError());
   return ORCHARD_OK;
 }
 
@@ -889,10 +857,6 @@ static orchard_status_t scratch_address(int dev, float** out) {
   return ORCHARD_OK;
 }
 
-__global__ void k_zero_i32(int32_t* p, int n) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) p[k] = 0;
-}
 
 orchard_status_t orchard_step_static_scratch(orchard_model_t m, const orchard_state_t* s,
                                              const orchard_params_t* params, const orchard_inputs_t* inputs,

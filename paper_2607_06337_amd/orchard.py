@@ -81,7 +81,7 @@ class Event(C.Structure):
 
 # every exported entry point of include/orchard.h
 EXPORTS = ("orchard_model_create", "orchard_model_destroy", "orchard_model_layout", "orchard_model_maps",
-           "orchard_model_apple_rest",
+           "orchard_model_apple_rest", "orchard_model_rebuild",
            "orchard_default_params", "orchard_state_rest", "orchard_step", "orchard_step_static_scratch",
            "orchard_ckpt_words",
            "orchard_ckpt_load", "orchard_events", "orchard_status", "orchard_last_error", "orchard_step_backward",
@@ -117,6 +117,8 @@ def load_library(path: str = LIB_PATH):
     L.orchard_model_maps.restype = st
     L.orchard_model_apple_rest.argtypes = [_P, _P]
     L.orchard_model_apple_rest.restype = st
+    L.orchard_model_rebuild.argtypes = [_P, _P, _P, _P]
+    L.orchard_model_rebuild.restype = st
     L.orchard_default_params.argtypes = [_P, _P, _P, _P]
     L.orchard_default_params.restype = st
     L.orchard_state_rest.argtypes = [_P, C.POINTER(CState), _P]
@@ -353,6 +355,18 @@ class Model:
 
     def rest_state(self) -> State:
         return self.rest(self.new_state())
+
+    def rebuild(self, seg_perturb, rejected=None, stream=None):
+        """On-device rebuild of every world's geometry (orchard_model_rebuild).
+        seg_perturb: float64 [n_seg, 4] in DESCRIPTOR order (length factor, radius factor,
+        bend about x, bend about y), numpy or a device tensor; rejected: optional device
+        int32 tensor [1] receiving the number of worlds left unchanged."""
+        import torch
+        f = torch.as_tensor(seg_perturb, dtype=torch.float64, device="cuda").contiguous()
+        assert f.shape == (self.n_seg, 4)
+        self._rebuild_factors = f  # kept alive until the stream has used it
+        _check(load_library().orchard_model_rebuild(self.h, _tptr(f), _tptr(rejected), _stream(stream)))
+        _check(load_library().orchard_model_apple_rest(self.h, _np_ptr(self.apple_hang_rest)))
 
     def default_params(self, stream=None):
         import torch

@@ -112,18 +112,19 @@ def compare_events(batch, gpu_ev, ora_ev, band: Band, envs):
 
 
 def run_parity(batch, consts, n_steps, every, *, envs=None, tuning=None, aforce_desc=None, aforce_from=0,
-               wrench_desc=None, threads=None):
+               wrench_desc=None, threads=None, model=None):
     """Run the whole batch on the GPU and the listed envs on the oracle.
 
     aforce_desc: constant apple force [A_tot, 3] (descriptor order) applied from step
-    aforce_from on.  Returns (errors per env, event mismatches, in-band count, model,
-    gpu state, oracle state)."""
+    aforce_from on.  model: an existing GPU model of this batch (else one is created).
+    Returns (errors per env, event mismatches, in-band count, model, gpu state, oracle
+    state)."""
     import torch
 
     from paper_2607_06337_amd import Model
 
     envs = list(range(batch.n_env)) if envs is None else list(envs)
-    m = Model(batch, consts, tuning)
+    m = Model(batch, consts, tuning) if model is None else model
     st = m.rest_state()
     kp, kd = m.default_params()
     o = Oracle(batch, consts)
