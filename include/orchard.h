@@ -242,6 +242,28 @@ orchard_status_t orchard_step(orchard_model_t model, const orchard_state_t* stat
                               const orchard_inputs_t* inputs, int32_t n_steps, float* ckpt, int32_t ckpt_every,
                               orchard_stream_t stream);
 
+/* ---- batched sphere-fit detector (Sec. "Geometric fruit perception", Eq. spherefit) ---- */
+
+/* Gate of a sphere candidate: radius in [r_min, r_max] (m), RMS geometric residual at
+ * most rms_max (m), at least min_points points (and at least 4). */
+typedef struct {
+  float r_min, r_max, rms_max;
+  int32_t min_points;
+} orchard_sphere_gate_t;
+
+/* Fit a sphere to every patch of back-projected depth points: the least-squares solution
+ * of 2 p.c + b = |p|^2 with b = R^2 - |c|^2 over the patch's points, its radius
+ * R = sqrt(b + |c|^2), the RMS of the geometric residuals |p - c| - R, and the gate.
+ * points: device float [n_points][3]; patch_offset: device int32 [n_patch + 1],
+ * non-decreasing, patch k = points[patch_offset[k] .. patch_offset[k+1]); gate: host.
+ * out: device float [n_patch][8] = centre x, y, z, radius, rms residual, point count,
+ * status (0 accepted, 1 too few points, 2 degenerate (no volume spanned), 3 radius out
+ * of range, 4 residual too large), 0.  Stream-ordered, no allocation.  Errors:
+ * INVALID_ARG (null pointer with n_patch > 0, n_patch < 0, a gate with r_max < r_min or
+ * negative bounds), HIP. */
+orchard_status_t orchard_sphere_fit(const float* points, const int32_t* patch_offset, int32_t n_patch,
+                                    const orchard_sphere_gate_t* gate, float* out, orchard_stream_t stream);
+
 /* Bytes of the library's fixed step scratch (one array per GPU, held until the process
  * ends). */
 #define ORCHARD_STATIC_SCRATCH_BYTES ((uint64_t)64 << 20)

@@ -24,6 +24,7 @@ from __future__ import annotations
 import math
 import multiprocessing
 import os
+import sys
 from concurrent.futures import ProcessPoolExecutor
 from dataclasses import dataclass
 
@@ -69,7 +70,10 @@ def make_trees(name: str, env_ids=None, workers: int | None = None) -> list[Tree
     jobs = [_sizes(name, int(e)) for e in env_ids]
     if workers is None:
         workers = min(8, os.cpu_count() or 1)
-    if len(jobs) < 64 or workers <= 1:
+    # the fork server re-imports the main script in its workers: without one (an
+    # interactive session, a script on stdin) the trees are generated here
+    main_file = getattr(sys.modules.get("__main__"), "__file__", None)
+    if len(jobs) < 64 or workers <= 1 or not main_file or not os.path.exists(main_file):
         return [_gen_one(j) for j in jobs]
     # workers come from a fork server (a fresh interpreter), never forked from a caller
     # that may already hold a GPU context

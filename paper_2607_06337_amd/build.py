@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liborchard.so")
-SOURCES = ["orchard_api.hip", "orchard_step.hip", "orchard_adjoint.hip", "orchard_build.hip"]
+SOURCES = ["orchard_api.hip", "orchard_step.hip", "orchard_adjoint.hip", "orchard_build.hip", "orchard_sphere.hip"]
 # packed FP32 instructions are kept out of every kernel (-packed-fp32-ops); a*b + c is
 # fused into an FMA only within one source expression (-ffp-contract=on), so an inline
 # function rounds the same way in every kernel and pass it is instantiated in

@@ -54,6 +54,8 @@ static orchard_status_t fail(orchard_status_t s, const std::string& msg) {
     if (_e != hipSuccess) return fail(ORCHARD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
   } while (0)
 
+orchard_status_t report_error(orchard_status_t s, const char* msg) { return fail(s, msg); }
+
 // zero n counters (a kernel, not a memset, so that callers may capture the work)
 __global__ void k_zero_i32(int32_t* p, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;

@@ -75,6 +75,10 @@ class CInputs(C.Structure):
                 ("apple_force_stride", C.c_int64)]
 
 
+class SphereGate(C.Structure):
+    _fields_ = [("r_min", C.c_float), ("r_max", C.c_float), ("rms_max", C.c_float), ("min_points", C.c_int32)]
+
+
 class Event(C.Structure):
     _fields_ = [("env", C.c_int32), ("kind", C.c_int32), ("id", C.c_int32), ("step", C.c_int32)]
 
@@ -86,7 +90,7 @@ EXPORTS = ("orchard_model_create", "orchard_model_destroy", "orchard_model_layou
            "orchard_ckpt_words",
            "orchard_ckpt_load", "orchard_events", "orchard_status", "orchard_last_error", "orchard_step_backward",
            "orchard_tips", "orchard_tips_backward", "orchard_graph_create", "orchard_graph_launch",
-           "orchard_graph_destroy", "orchard_autotune")
+           "orchard_graph_destroy", "orchard_autotune", "orchard_sphere_fit")
 
 _lib = None
 
@@ -153,6 +157,8 @@ def load_library(path: str = LIB_PATH):
     L.orchard_autotune.argtypes = [C.POINTER(Desc), C.POINTER(Tuning), C.c_int32, C.c_int32, C.c_int32,
                                    C.POINTER(Tuning), _P, _P]
     L.orchard_autotune.restype = st
+    L.orchard_sphere_fit.argtypes = [_P, _P, C.c_int32, C.POINTER(SphereGate), _P, _P]
+    L.orchard_sphere_fit.restype = st
     L.orchard_last_error.argtypes = []
     L.orchard_last_error.restype = C.c_char_p
     _lib = L
@@ -492,3 +498,19 @@ class Model:
 
     def apple_from_desc(self, x_desc: np.ndarray, axis: int = 0) -> np.ndarray:
         return np.take(x_desc, self.apple_map, axis=axis)
+
+
+def sphere_fit(points, offsets, gate: dict, out=None, stream=None):
+    """Batched sphere fit (orchard_sphere_fit).  points: device float32 [N, 3]; offsets:
+    device int32 [n_patch + 1]; gate: r_min, r_max, rms_max, min_points.  Returns (and
+    fills) out: device float32 [n_patch, 8] = centre, radius, rms, count, status, 0."""
+    import torch
+    assert points.dtype == torch.float32 and points.is_contiguous() and points.shape[-1] == 3
+    assert offsets.dtype == torch.int32 and offsets.is_contiguous()
+    n_patch = offsets.numel() - 1
+    if out is None:
+        out = torch.empty(n_patch, 8, dtype=torch.float32, device=points.device)
+    g = SphereGate(float(gate["r_min"]), float(gate["r_max"]), float(gate["rms_max"]), int(gate["min_points"]))
+    _check(load_library().orchard_sphere_fit(_tptr(points), _tptr(offsets), int(n_patch), C.byref(g), _tptr(out),
+                                             _stream(stream)))
+    return out

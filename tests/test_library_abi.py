@@ -89,3 +89,17 @@ def test_create_rejects_empty_and_null_descriptions():
     d.n_env = 1
     assert L.orchard_model_create(C.byref(d), None, None) == 1
     assert L.orchard_last_error()
+
+
+def test_sphere_fit_rejects_bad_arguments_before_device_work():
+    import ctypes as C
+    from paper_2607_06337_amd import load_library
+    from paper_2607_06337_amd.orchard import SphereGate
+    L = load_library()
+    good = SphereGate(0.02, 0.058, 0.002, 8)
+    bad = SphereGate(0.06, 0.02, 0.002, 8)
+    assert L.orchard_sphere_fit(None, None, -1, C.byref(good), None, None) == 1
+    assert L.orchard_sphere_fit(None, None, 5, C.byref(good), None, None) == 1
+    assert L.orchard_sphere_fit(None, None, 0, C.byref(bad), None, None) == 1
+    assert b"gate" in L.orchard_last_error()
+    assert L.orchard_sphere_fit(None, None, 0, C.byref(good), None, None) == 0
