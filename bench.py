@@ -103,7 +103,7 @@ def time_gpu(model, n_steps, warmup, graph_steps=0):
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    spl = max(1, int(model.tuning["steps_per_launch"]))
+    spl = max(1, int(model.tuning.steps_per_launch))
     launches = lambda k: -(-k // spl)
     t0 = time.perf_counter()
     ev0.record(stream)
@@ -251,6 +251,46 @@ def row_scale(fwd_steps: int = 200, warm: int = 10, lead: int = 900, tail: int =
                                    backward_alg_GBps=round(lb / (bw / 1e3) / 1e9, 1)))
 
 
+def sphere_fit_leg(n_patch: int = 65536, reps: int = 20, cpu_patches: int = 2000):
+    """Batched sphere-fit detector on synthetic depth patches (fruit caps, branch sections,
+    leaves; about 400 points per patch): one launch per batch, HIP events over `reps`
+    launches.  Algorithmic bytes: 12 per point read, 4 per patch offset, 32 per patch
+    written.  CPU baseline: the FP64 reference on a sample of patches, one thread."""
+    import torch
+    from orchard_inputs.patches import GATE, make_patches
+    from oracle.sphere import fit_patches
+    from paper_2607_06337_amd import sphere_fit
+    pts, off, kind, _ = make_patches(n_patch)
+    P = torch.tensor(pts, device="cuda")
+    O = torch.tensor(off, device="cuda")
+    out = torch.empty(n_patch, 8, device="cuda")
+    sphere_fit(P, O, GATE, out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        sphere_fit(P, O, GATE, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    n_pts = int(off[-1])
+    alg = 12 * n_pts + 4 * (n_patch + 1) + 32 * n_patch
+    acc = out[:, 6].cpu().numpy() == 0
+    pick = np.unique(np.linspace(0, n_patch - 1, cpu_patches).round().astype(int))
+    t0 = time.perf_counter()
+    fit_patches(pts, off, GATE, patches=pick)
+    cpu_s = time.perf_counter() - t0
+    return dict(workload=f"{n_patch} synthetic depth patches ({n_pts} points; fruit caps, branch sections, leaves)",
+                us_per_launch=round(us, 2), patches_per_s=round(n_patch / (us * 1e-6), 1),
+                points_per_s=round(n_pts / (us * 1e-6), 1), accepted=int(acc.sum()),
+                fruit_recall=round(float(acc[kind == 0].mean()), 4),
+                roofline=dict(bound="hbm", achieved=round(alg / (us * 1e-6) / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=round(alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), bytes_per_launch=alg),
+                cpu_baseline=dict(value=round(len(pick) / cpu_s, 1), unit="patches/s", cores=1, kind="oracle",
+                                  sample=f"{len(pick)} patches of the workload, FP64 least squares, {cpu_s:.1f} s"))
+
+
 def _copy_probe():
     """Three launches of one plain elementwise kernel (256 MiB read, 256 MiB written): the
     reference that scales the HBM counters."""
@@ -271,6 +311,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-row-scale", action="store_true")
+    ap.add_argument("--no-sphere", action="store_true")
+    ap.add_argument("--sphere-only", action="store_true", help="run only the sphere-fit leg (for its profile)")
     ap.add_argument("--tuning", type=str, default=None,
                     help="kernel mapping as JSON (skips the autotuner), e.g. the one a profile was taken with")
     ap.add_argument("--row-scale-only", action="store_true",
@@ -282,6 +324,12 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (trees are independent, "
               "a multi-GPU run would give each GPU a share of the envs balanced by segment count and depth)", file=sys.stderr)
         sys.exit(2)
+
+    if args.sphere_only:
+        import torch
+        torch.cuda.init()
+        print(json.dumps(dict(sphere_fit=sphere_fit_leg())), flush=True)
+        return
 
     if args.row_scale_only:
         import torch
@@ -360,6 +408,10 @@ def main():
     if not args.no_row_scale:
         rows = row_scale()
         print(f"# row scale: {rows}", file=sys.stderr, flush=True)
+    sph = None
+    if not args.no_sphere:
+        sph = sphere_fit_leg()
+        print(f"# sphere fit: {sph}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, consts)
@@ -373,7 +425,7 @@ def main():
                            n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=tuning,
                            rollout=what, autotune=tune_log),
                adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
-               roofline=roof, cpu_baseline=cpu, row_scale=rows)
+               roofline=roof, cpu_baseline=cpu, row_scale=rows, sphere_fit=sph)
     print(json.dumps(out), flush=True)
 
 

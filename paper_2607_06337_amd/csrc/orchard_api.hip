@@ -518,6 +518,12 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
          o_nt = ar.put(ntopo.data(), NS * 16), o_len = ar.put(seglen.data(), NS * 4),
          o_wm = ar.put(wmom_f.data(), NS * 4),
          o_q = ar.put(&zero, 4 * 16);
+  // the extras' constants; their friction-scale pointer is set once the arena exists
+  ExtraConsts xc_h{(float)d->drag_lin, (float)d->drag_ang, (float)d->drag_snapped, (float)d->friction_base,
+                   (float)d->friction_growth,
+                   d->friction_ramp_time > 0 ? (float)(1.0 / d->friction_ramp_time) : -1.f,  // < 0: no ramp
+                   (float)d->friction_speed, (float)d->fade_speed, (float)d->brake_rate, nullptr};
+  const size_t o_xc = ar.put(&xc_h, sizeof(ExtraConsts));
   // the descriptor as given (descriptor order) and the order maps, for the on-device rebuild
   std::vector<int32_t> int_apple_of(NA);
   for (int64_t k = 0; k < NA; ++k) int_apple_of[aord[k]] = (int32_t)k;
@@ -530,6 +536,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
                o_iao = ar.put(int_apple_of.data(), NA * 4), o_hr64 = ar.put(ahang_rest.data(), NA * 24);
   hipError_t he = hipMalloc(&M->arena, ar.off + 256);
   if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
+  xc_h.wmom = (const float*)((char*)M->arena + o_wm);
   std::vector<char> zeros(64, 0);
   for (auto& it : ar.items) {
     const void* src = it.src == &zero ? zeros.data() : it.src;
@@ -579,15 +586,9 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.rng_thr = (uint32_t)std::floor(d->wrench_fraction * 16777216.0);
   dm.wsig = (float)d->wrench_sigma;
   dm.apl = d->fruit_dof == 3 ? 6 : 13;
-  dm.drag = (d->drag_lin > 0 || d->drag_ang > 0) ? 1 : 0;
-  dm.rails = (d->fade_speed > 0 || d->brake_rate > 0) ? 1 : 0;
-  dm.fric = d->friction_base > 0 ? 1 : 0;
-  dm.drag_lin = (float)d->drag_lin; dm.drag_ang = (float)d->drag_ang; dm.drag_snp = (float)d->drag_snapped;
-  dm.fric_base = (float)d->friction_base; dm.fric_growth = (float)d->friction_growth;
-  dm.fric_inv_ramp = d->friction_ramp_time > 0 ? (float)(1.0 / d->friction_ramp_time) : -1.f;  // < 0: no ramp
-  dm.fric_speed = (float)d->friction_speed;
-  dm.fade = (float)d->fade_speed; dm.brake = (float)d->brake_rate;
-  dm.wmom = (const float*)(base + o_wm);
+  dm.xflags = ((d->drag_lin > 0 || d->drag_ang > 0) ? X_DRAG : 0) | ((d->fade_speed > 0 || d->brake_rate > 0) ? X_RAILS : 0) |
+              (d->friction_base > 0 ? X_FRIC : 0);
+  dm.xc = (const ExtraConsts*)(base + o_xc);
   {
     RebuildArgs& rb = M->rb;
     rb.n_env = B; rb.n_seg = NS; rb.consts = dc;
@@ -950,7 +951,7 @@ orchard_status_t orchard_step_backward(orchard_model_t m, const float* ckpt, int
     return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
   if (m->n_apple > 0 && (!adj->apple_x || !adj->apple_v)) return fail(ORCHARD_ERR_INVALID_ARG, "apple adjoint missing");
   if (m->adj_kmax <= 0) return fail(ORCHARD_ERR_INVALID_ARG, "model created without adjoint support (tuning.adjoint_ckpt_max)");
-  if (m->dm.drag || m->dm.rails || m->dm.fric)
+  if (m->dm.xflags)
     return fail(ORCHARD_ERR_INVALID_ARG, "the adjoint does not cover drag, post-break friction or the power fade / speed brake");
   if (ckpt_every < 1 || ckpt_every > m->adj_kmax) return fail(ORCHARD_ERR_INVALID_ARG, "ckpt_every out of [1, adjoint_ckpt_max]");
   if (n_steps < 0) return fail(ORCHARD_ERR_INVALID_ARG, "n_steps < 0");

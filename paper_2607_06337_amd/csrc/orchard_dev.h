@@ -104,6 +104,14 @@ struct AppleRec {
   int4 link;    // (node, env, 1 if the first apple of its node, the node's apple-node index)
 };
 
+enum : int32_t { X_DRAG = 1, X_RAILS = 2, X_FRIC = 4 };
+struct ExtraConsts {
+  float drag_lin, drag_ang, drag_snp;
+  float fric_base, fric_growth, fric_inv_ramp, fric_speed;  // fric_inv_ramp < 0: no ramp
+  float fade, brake;
+  const float* wmom;         // per node: the limb's largest weight moment (friction scale)
+};
+
 struct DevModel {
   int32_t n_env, n_seg, n_apple, n_pack;
   // packs: nodes [pack_node[p], pack_node[p+1]); levels lvl_off[pack_lvl[p] .. pack_lvl[p+1]-1]
@@ -139,12 +147,11 @@ struct DevModel {
   uint32_t rng_thr;
   float wsig;
   int32_t apl;               // float planes of the apple state: 13 (rigid body) or 6 (translational)
-  // extras (all off at 0): drag, post-break friction ramp, power fade, speed brake
-  int32_t drag, rails, fric;  // which are on
-  float drag_lin, drag_ang, drag_snp;
-  float fric_base, fric_growth, fric_inv_ramp, fric_speed;
-  float fade, brake;
-  const float* wmom;         // per node: the limb's largest weight moment (friction scale)
+  // extras (drag, post-break friction ramp, power fade, speed brake): which are on, and
+  // their constants in device memory, read only where an extra is on (so they hold no
+  // scalar registers through the step's loops)
+  int32_t xflags;            // X_DRAG | X_RAILS | X_FRIC
+  const struct ExtraConsts* xc;
   float* scr;                // blocks of 64 nodes, each [scr_nf][64] floats (see scr_idx)
   float* asnap;              // [n_anode][K_N] kinematics of the nodes that carry apples
   float* aext;               // [n_anode][E_N] apple sums per node that carries apples
@@ -289,19 +296,20 @@ __device__ __forceinline__ bool applied_force(const DevModel& M, const DevInputs
       any = true;
     }
   }
-  if (any && M.rails) {
+  if (any && (M.xflags & X_RAILS)) {
     const float sp = sqrtf(dot(vc, vc));
     if (sp > 0.f) {
+      const float fade = M.xc->fade, brake = M.xc->brake;
       const V3 u = (1.f / sp) * vc;
       const float fu = dot(F, u);
       // power fade: the push along the motion falls from full at the fade speed to
       // nothing at twice it
-      if (M.fade > 0.f && fu > 0.f && sp > M.fade) {
-        const float phi = fmaxf(0.f, 1.f - (sp - M.fade) / M.fade);
+      if (fade > 0.f && fu > 0.f && sp > fade) {
+        const float phi = fmaxf(0.f, 1.f - (sp - fade) / fade);
         F = F - ((1.f - phi) * fu) * u;
       }
       // soft speed brake above the speed limit
-      if (M.brake > 0.f && sp > M.vcap) F = F - (M.brake * m * (sp - M.vcap)) * u;
+      if (brake > 0.f && sp > M.vcap) F = F - (brake * m * (sp - M.vcap)) * u;
     }
   }
   if (any) {

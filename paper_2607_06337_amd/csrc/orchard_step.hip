@@ -80,14 +80,15 @@ __device__ __forceinline__ void body_bias(const DevModel& M, const DevInputs& I,
     pang = pang - (T + cross(rc, F));
     plin = plin - F;
   }
-  if (M.drag) {
+  if (M.xflags & X_DRAG) {
     // velocity-proportional drag F = -c_v m v_c, tau = -c_w I_c w (inertia about the
     // centre of mass), reduced on a snapped sub-tree
-    const float f = snp ? M.drag_snp : 1.f;
+    const ExtraConsts& X = *M.xc;
+    const float f = snp ? X.drag_snp : 1.f;
     const float Itc = geo.z - 0.25f * m * l * l, Ia = geo.w;
     const V3 Iw = fma3((Ia - Itc) * dot(z, wi), z, Itc * wi);
-    const V3 Fd = (-f * M.drag_lin * m) * vc;
-    const V3 Td = (-f * M.drag_ang) * Iw;
+    const V3 Fd = (-f * X.drag_lin * m) * vc;
+    const V3 Td = (-f * X.drag_ang) * Iw;
     pang = pang - (Td + cross(rc, Fd));
     plin = plin - Fd;
   }
@@ -519,14 +520,15 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevState& S, co
   const float2 q = in.q, qd = in.qd;
   const float kpe = brk ? 0.f : in.kp;
   float kde = brk ? 0.f : in.kd;
-  if (brk && M.fric) {
+  if (brk && (M.xflags & X_FRIC)) {
     // Coulomb friction of the torn fibres: tau_c ramps linearly from friction_base to
     // friction_growth x friction_base of the limb's weight moment, acting as the linearly
     // implicit damper tau_c / max(|qd|, friction_speed)
+    const ExtraConsts& X = *M.xc;
     const int64_t nb = fl.brk0 ? (int64_t)at(S.evt_step, (uint32_t)i) : n;  // step of the break
-    const float ramp = M.fric_inv_ramp < 0.f ? 1.f : fminf(1.f, (float)(n - nb) * h * M.fric_inv_ramp);
-    const float tc = M.fric_base * at(M.wmom, (uint32_t)i) * fmaf(M.fric_growth - 1.f, ramp, 1.f);
-    kde = tc / fmaxf(sqrtf(fmaf(qd.x, qd.x, qd.y * qd.y)), M.fric_speed);
+    const float ramp = X.fric_inv_ramp < 0.f ? 1.f : fminf(1.f, (float)(n - nb) * h * X.fric_inv_ramp);
+    const float tc = X.fric_base * at(X.wmom, (uint32_t)i) * fmaf(X.fric_growth - 1.f, ramp, 1.f);
+    kde = tc / fmaxf(sqrtf(fmaf(qd.x, qd.x, qd.y * qd.y)), X.fric_speed);
   }
   const float tau0 = -kpe * fmaf(h, qd.x, q.x) - kde * qd.x;
   const float tau1 = -kpe * fmaf(h, qd.y, q.y) - kde * qd.y;
