@@ -312,6 +312,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-row-scale", action="store_true")
     ap.add_argument("--no-sphere", action="store_true")
+    ap.add_argument("--batch-cache", type=str, default=None,
+                    help="npz file holding the generated batch (written if missing): profiler runs load it instead "
+                         "of generating the trees in worker processes")
+    ap.add_argument("--cache-only", action="store_true", help="write --batch-cache and exit (no GPU)")
     ap.add_argument("--sphere-only", action="store_true", help="run only the sphere-fit leg (for its profile)")
     ap.add_argument("--tuning", type=str, default=None,
                     help="kernel mapping as JSON (skips the autotuner), e.g. the one a profile was taken with")
@@ -328,6 +332,8 @@ def main():
     if args.sphere_only:
         import torch
         torch.cuda.init()
+        if args.copy_probe:
+            _copy_probe()
         print(json.dumps(dict(sphere_fit=sphere_fit_leg())), flush=True)
         return
 
@@ -341,7 +347,19 @@ def main():
 
     from orchard_inputs import make_batch, step_constants
     t_gen = time.perf_counter()
-    batch = make_batch(WORKLOAD)
+    if args.batch_cache and os.path.exists(args.batch_cache):
+        import dataclasses
+
+        from orchard_inputs import Batch
+        with np.load(args.batch_cache) as z:
+            batch = Batch(**{f.name: z[f.name] for f in dataclasses.fields(Batch)})
+    else:
+        batch = make_batch(WORKLOAD)
+        if args.batch_cache:
+            import dataclasses
+            np.savez(args.batch_cache, **dataclasses.asdict(batch))
+    if args.cache_only:
+        return
     consts = step_constants(WORKLOAD)
     t_gen = time.perf_counter() - t_gen
     print(f"# generated {batch.n_env} trees, {batch.n_seg} segments, {batch.n_apple} apples in {t_gen:.1f} s",

@@ -4,13 +4,15 @@
 // RMS geometric residual.  One wavefront per patch; the work is a few streaming passes
 // over 12 bytes per point, so the kernel is bound by memory, not by arithmetic.
 //
-// Numerics: the FP32 points are shifted by the patch's first point and centred on their
-// mean in FP64 (the shift is exact there), and the moments, the solve and the residual
-// run in FP64 as well, which costs nothing here (the vector units issue FP64 at the
-// FP32 rate without packed math, and the kernel waits on memory) and removes the FP32
-// error the fit of a shallow cap amplifies by 10^3..10^4.  Centring turns the 4x4 normal
-// equations into a 3x3 system for the centre in the central second moments (the mean row
-// decouples: b' = sum |u|^2 / n).
+// Numerics: the FP32 points are shifted by the patch's first point in FP64 (exact), and
+// one pass gathers the shifted sums n, sum q, sum q q^T, sum |q|^2 q and sum |q|^2 in FP64;
+// the central moments follow from them in closed form (with shifts of a few centimetres
+// FP64 loses nothing there), the centre from the 3x3 system C c' = (1/2) sum |u|^2 u of
+// the centred coordinates u (centring decouples the mean row of the 4x4 normal equations:
+// b' = sum |u|^2 / n), and a second pass sums the squared geometric residuals
+// d = (|u - c'|^2 - R^2) / (|u - c'| + R), the numerator in FP64, the denominator in
+// FP32 (relative error 1e-7 in d, without a FP64 square root per point).  FP64 costs
+// little here: the vector units issue it at the FP32 rate without packed math.
 #include <hip/hip_runtime.h>
 
 #include "../../include/orchard.h"
@@ -28,6 +30,114 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Points are read in chunks of 64 x KP: each lane issues all KP loads of a chunk before it
+// uses any, and a patch that fits one chunk is read from memory once, its second pass
+// working from registers.
+constexpr int KP = 4;
+
+struct Chunk {
+  float x[KP], y[KP], z[KP];
+};
+// The loads carry no branch (a lane past the patch's end re-reads its last point, which
+// the passes then weigh zero), so the compiler issues all of them before the first wait.
+__device__ __forceinline__ void load_chunk(const float* __restrict__ pts, int k0, int e, int lane, Chunk& c) {
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    const int k = min(k0 + 64 * j + lane, e - 1);
+    const float* p = pts + 3 * (int64_t)k;
+    c.x[j] = p[0]; c.y[j] = p[1]; c.z[j] = p[2];
+  }
+}
+
+// the fit of one patch (points b .. e-1, n = e - b >= 4) by one wavefront; res as out[]
+__device__ __forceinline__ void fit_patch(const float* __restrict__ pts, int b, int e, int lane,
+                                          const orchard_sphere_gate_t& gate, float (&res)[8]) {
+  const int n = e - b;
+  const double x0 = pts[3 * (int64_t)b], y0 = pts[3 * (int64_t)b + 1], z0 = pts[3 * (int64_t)b + 2];
+  const bool one = n <= 64 * KP;  // the whole patch stays in registers
+  Chunk c;
+  // pass 1: sums of the shifted points q = p - p0
+  double sx = 0.0, sy = 0.0, sz = 0.0, qxx = 0.0, qxy = 0.0, qxz = 0.0, qyy = 0.0, qyz = 0.0, qzz = 0.0;
+  double wx = 0.0, wy = 0.0, wz = 0.0, ww = 0.0;
+  for (int k0 = b; k0 < e; k0 += 64 * KP) {
+    load_chunk(pts, k0, e, lane, c);
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const bool v = k0 + 64 * j + lane < e;  // a point past the end contributes q = 0
+      const double qx = v ? (double)c.x[j] - x0 : 0.0, qy = v ? (double)c.y[j] - y0 : 0.0,
+                   qz = v ? (double)c.z[j] - z0 : 0.0;
+      const double w = fma(qx, qx, fma(qy, qy, qz * qz));
+      sx += qx; sy += qy; sz += qz;
+      qxx = fma(qx, qx, qxx); qxy = fma(qx, qy, qxy); qxz = fma(qx, qz, qxz);
+      qyy = fma(qy, qy, qyy); qyz = fma(qy, qz, qyz); qzz = fma(qz, qz, qzz);
+      wx = fma(w, qx, wx); wy = fma(w, qy, wy); wz = fma(w, qz, wz);
+      ww += w;
+    }
+  }
+  sx = wave_sum(sx); sy = wave_sum(sy); sz = wave_sum(sz);
+  qxx = wave_sum(qxx); qxy = wave_sum(qxy); qxz = wave_sum(qxz);
+  qyy = wave_sum(qyy); qyz = wave_sum(qyz); qzz = wave_sum(qzz);
+  wx = wave_sum(wx); wy = wave_sum(wy); wz = wave_sum(wz); ww = wave_sum(ww);
+  // central moments of u = q - m, m the mean: C = S_qq - n m m^T,
+  // sum |u|^2 u = S_wq - m S_w - 2 S_qq m + 2 n |m|^2 m, sum |u|^2 = S_w - n |m|^2
+  const double nd = (double)n, inv_n = 1.0 / nd;
+  const double mx = sx * inv_n, my = sy * inv_n, mz = sz * inv_n;
+  const double mm = fma(mx, mx, fma(my, my, mz * mz));
+  const double cxx = qxx - nd * mx * mx, cxy = qxy - nd * mx * my, cxz = qxz - nd * mx * mz;
+  const double cyy = qyy - nd * my * my, cyz = qyz - nd * my * mz, czz = qzz - nd * mz * mz;
+  const double Qmx = qxx * mx + qxy * my + qxz * mz, Qmy = qxy * mx + qyy * my + qyz * mz,
+               Qmz = qxz * mx + qyz * my + qzz * mz;
+  const double uwx = wx - mx * ww - 2.0 * Qmx + 2.0 * nd * mm * mx;
+  const double uwy = wy - my * ww - 2.0 * Qmy + 2.0 * nd * mm * my;
+  const double uwz = wz - mz * ww - 2.0 * Qmz + 2.0 * nd * mm * mz;
+  const double uww = ww - nd * mm;
+  // centre c' (from the mean) solves C c' = (1/2) sum |u|^2 u; Cholesky of C, whose
+  // pivots fall to rounding level when the points span no volume
+  const double tr = cxx + cyy + czz;
+  const double eps = 1e-9 * tr;
+  const double l11sq = cxx;
+  bool ok = l11sq > eps;
+  const double l11 = sqrt(fmax(l11sq, 0.0));
+  const double l21 = ok ? cxy / l11 : 0.0, l31 = ok ? cxz / l11 : 0.0;
+  const double l22sq = cyy - l21 * l21;
+  ok = ok && l22sq > eps;
+  const double l22 = sqrt(fmax(l22sq, 0.0));
+  const double l32 = ok ? (cyz - l31 * l21) / l22 : 0.0;
+  const double l33sq = czz - l31 * l31 - l32 * l32;
+  ok = ok && l33sq > eps;
+  if (!ok) {
+    res[6] = 2.f;  // degenerate: the points span no volume (a plane or a line)
+    return;
+  }
+  const double l33 = sqrt(l33sq);
+  const double r1 = 0.5 * uwx, r2 = 0.5 * uwy, r3 = 0.5 * uwz;
+  const double y1 = r1 / l11, y2 = (r2 - l21 * y1) / l22, y3 = (r3 - l31 * y1 - l32 * y2) / l33;
+  const double cz = y3 / l33, cy = (y2 - l32 * cz) / l22, cx = (y1 - l21 * cy - l31 * cz) / l11;
+  const double R2 = fmax(fma(uww, inv_n, fma(cx, cx, fma(cy, cy, cz * cz))), 0.0);
+  const double R = sqrt(R2);
+  // pass 2: RMS of the geometric residual |q - (m + c')| - R
+  const double ox = mx + cx, oy = my + cy, oz = mz + cz;  // centre relative to p0
+  const float Rf = (float)R;
+  double rr = 0.0;
+  for (int k0 = b; k0 < e; k0 += 64 * KP) {
+    if (!one) load_chunk(pts, k0, e, lane, c);
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const bool v = k0 + 64 * j + lane < e;
+      const double dx = ((double)c.x[j] - x0) - ox, dy = ((double)c.y[j] - y0) - oy, dz = ((double)c.z[j] - z0) - oz;
+      const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      const double d = (d2 - R2) * (double)(1.f / (sqrtf((float)d2) + Rf));
+      rr = v ? fma(d, d, rr) : rr;
+    }
+  }
+  const double rms = sqrt(wave_sum(rr) * inv_n);
+  res[0] = (float)(x0 + ox); res[1] = (float)(y0 + oy); res[2] = (float)(z0 + oz);
+  res[3] = (float)R;
+  res[4] = (float)rms;
+  // the gate decides in FP64, as the reference does
+  res[6] = (R < (double)gate.r_min || R > (double)gate.r_max) ? 3.f : (rms > (double)gate.rms_max ? 4.f : 0.f);
+}
+
 __global__ __launch_bounds__(64 * kWaves) void k_sphere_fit(const float* __restrict__ pts,
                                                            const int32_t* __restrict__ off, int n_patch,
                                                            orchard_sphere_gate_t gate, float* __restrict__ out) {
@@ -37,69 +147,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_sphere_fit(const float* __restr
   const int b = off[patch], e = off[patch + 1];
   const int n = e > b ? e - b : 0;
   float res[8] = {0.f, 0.f, 0.f, 0.f, 0.f, (float)n, 1.f, 0.f};
-  if (n >= gate.min_points && n >= 4) {
-    const double x0 = pts[3 * (int64_t)b], y0 = pts[3 * (int64_t)b + 1], z0 = pts[3 * (int64_t)b + 2];
-    // pass 1: mean of the shifted points
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int k = b + lane; k < e; k += 64) {
-      const float* p = pts + 3 * (int64_t)k;
-      sx += (double)p[0] - x0; sy += (double)p[1] - y0; sz += (double)p[2] - z0;
-    }
-    const double inv_n = 1.0 / (double)n;
-    const double mx = wave_sum(sx) * inv_n, my = wave_sum(sy) * inv_n, mz = wave_sum(sz) * inv_n;
-    // pass 2: central second moments and sum |u|^2 u, sum |u|^2
-    double cxx = 0.0, cxy = 0.0, cxz = 0.0, cyy = 0.0, cyz = 0.0, czz = 0.0, wx = 0.0, wy = 0.0, wz = 0.0, ww = 0.0;
-    for (int k = b + lane; k < e; k += 64) {
-      const float* p = pts + 3 * (int64_t)k;
-      const double ux = ((double)p[0] - x0) - mx, uy = ((double)p[1] - y0) - my, uz = ((double)p[2] - z0) - mz;
-      const double w = fma(ux, ux, fma(uy, uy, uz * uz));
-      cxx = fma(ux, ux, cxx); cxy = fma(ux, uy, cxy); cxz = fma(ux, uz, cxz);
-      cyy = fma(uy, uy, cyy); cyz = fma(uy, uz, cyz); czz = fma(uz, uz, czz);
-      wx = fma(w, ux, wx); wy = fma(w, uy, wy); wz = fma(w, uz, wz);
-      ww += w;
-    }
-    cxx = wave_sum(cxx); cxy = wave_sum(cxy); cxz = wave_sum(cxz);
-    cyy = wave_sum(cyy); cyz = wave_sum(cyz); czz = wave_sum(czz);
-    wx = wave_sum(wx); wy = wave_sum(wy); wz = wave_sum(wz); ww = wave_sum(ww);
-    // centre c' (from the mean) solves C c' = (1/2) sum |u|^2 u; Cholesky of C, whose
-    // pivots fall to rounding level when the points span no volume
-    const double tr = cxx + cyy + czz;
-    const double eps = 1e-9 * tr;
-    const double l11sq = cxx;
-    bool ok = l11sq > eps;
-    const double l11 = sqrt(fmax(l11sq, 0.0));
-    const double l21 = ok ? cxy / l11 : 0.0, l31 = ok ? cxz / l11 : 0.0;
-    const double l22sq = cyy - l21 * l21;
-    ok = ok && l22sq > eps;
-    const double l22 = sqrt(fmax(l22sq, 0.0));
-    const double l32 = ok ? (cyz - l31 * l21) / l22 : 0.0;
-    const double l33sq = czz - l31 * l31 - l32 * l32;
-    ok = ok && l33sq > eps;
-    if (!ok) {
-      res[6] = 2.f;  // degenerate: the points span no volume (a plane or a line)
-    } else {
-      const double l33 = sqrt(l33sq);
-      const double r1 = 0.5 * wx, r2 = 0.5 * wy, r3 = 0.5 * wz;
-      const double y1 = r1 / l11, y2 = (r2 - l21 * y1) / l22, y3 = (r3 - l31 * y1 - l32 * y2) / l33;
-      const double cz = y3 / l33, cy = (y2 - l32 * cz) / l22, cx = (y1 - l21 * cy - l31 * cz) / l11;
-      const double R = sqrt(fmax(fma(ww, inv_n, fma(cx, cx, fma(cy, cy, cz * cz))), 0.0));
-      // pass 3: RMS of the geometric residual |u - c'| - R
-      double rr = 0.0;
-      for (int k = b + lane; k < e; k += 64) {
-        const float* p = pts + 3 * (int64_t)k;
-        const double dx = (((double)p[0] - x0) - mx) - cx, dy = (((double)p[1] - y0) - my) - cy,
-                     dz = (((double)p[2] - z0) - mz) - cz;
-        const double d = sqrt(fma(dx, dx, fma(dy, dy, dz * dz))) - R;
-        rr = fma(d, d, rr);
-      }
-      const double rms = sqrt(wave_sum(rr) * inv_n);
-      res[0] = (float)(x0 + (mx + cx)); res[1] = (float)(y0 + (my + cy)); res[2] = (float)(z0 + (mz + cz));
-      res[3] = (float)R;
-      res[4] = (float)rms;
-      // the gate decides in FP64, as the reference does
-      res[6] = (R < (double)gate.r_min || R > (double)gate.r_max) ? 3.f : (rms > (double)gate.rms_max ? 4.f : 0.f);
-    }
-  }
+  if (n >= gate.min_points && n >= 4) fit_patch(pts, b, e, lane, gate, res);
   if (lane < 2) {
     float4* o = reinterpret_cast<float4*>(out + 8 * (int64_t)patch);
     o[lane] = lane == 0 ? make_float4(res[0], res[1], res[2], res[3]) : make_float4(res[4], res[5], res[6], res[7]);
