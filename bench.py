@@ -30,13 +30,22 @@ sys.path.insert(0, ROOT)
 
 # kernel mapping used by the full-size parity test and the adjoint ratio, and the first of
 # the candidates the autotuner times for the benchmark
-BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=50, persistent=0, lds_width=240)
+# (trees wider than lds_width but not than 512 nodes per level go to the wide-tree bucket,
+# packs of 512 work-items launched on a second stream; no tree of the uneven batch is that
+# wide, the 5000-segment trees of the orchard-row batch are)
+BENCH_TUNING = dict(threads=256, pack_fill=1.0, steps_per_launch=50, persistent=0, lds_width=240, big_threads=512)
 # candidates of the autotuner: workgroup size, LDS width, steps per launch (a multi-step
-# launch fuses the second down pass of a step with the first of the next)
+# launch fuses the second down pass of a step with the first of the next), persistent
+# queue, wave packs for trees whose widest level fits a wavefront
 AUTOTUNE_CANDIDATES = [BENCH_TUNING, dict(BENCH_TUNING, steps_per_launch=10), dict(BENCH_TUNING, steps_per_launch=1),
                        dict(BENCH_TUNING, lds_width=256), dict(BENCH_TUNING, lds_width=224),
                        dict(BENCH_TUNING, lds_width=192), dict(BENCH_TUNING, threads=128, lds_width=128),
-                       dict(BENCH_TUNING, lds_width=0), dict(BENCH_TUNING, threads=128, lds_width=0)]
+                       dict(BENCH_TUNING, lds_width=0), dict(BENCH_TUNING, threads=128, lds_width=0),
+                       dict(BENCH_TUNING, wave_width=64), dict(BENCH_TUNING, wave_width=32),
+                       dict(BENCH_TUNING, threads=64, lds_width=64),
+                       dict(BENCH_TUNING, persistent=1)]
+TUNING_KEYS = ("threads", "pack_fill", "steps_per_launch", "persistent", "lds_width", "pack_skew", "wave_width",
+               "big_threads")
 GRAPH_STEPS = 100  # steps per captured HIP graph in the timed rollout
 # the plain per-step kernel: one 256-thread workgroup per tree, one launch per step,
 # levels exchange through global scratch
@@ -85,11 +94,12 @@ def profiled_counters(kernel: str, tuning: dict):
     return out or None
 
 
-def time_gpu(model, n_steps, warmup, graph_steps=0):
+def time_gpu(model, n_steps, warmup, graph_steps=0, repeats=1):
     """Time n_steps after warmup eager steps.  With graph_steps > 0 the rollout is a HIP
     graph of min(graph_steps, n_steps) steps replayed (capture and one replay happen
     before the timed region; a remainder runs eagerly inside it).  Returns (ms, wall s,
-    non-finite envs, state, description of what was timed, kernel launches timed)."""
+    non-finite envs, state, description of what was timed, kernel launches timed, [ms of
+    each of `repeats` timed rollouts of n_steps, the first being the returned one])."""
     import torch
     st = model.rest_state()
     kp, kd = model.default_params()
@@ -105,27 +115,31 @@ def time_gpu(model, n_steps, warmup, graph_steps=0):
     ev1 = torch.cuda.Event(enable_timing=True)
     spl = max(1, int(model.tuning.steps_per_launch))
     launches = lambda k: -(-k // spl)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    if g is not None:
-        reps, rem = n_steps // gs, n_steps % gs
-        for _ in range(reps):
-            g.launch(stream)
-        if rem:
-            model.step(st, kp, kd, rem)
-        what = f"HIP graph of {gs} steps replayed {reps} times" + (f" + {rem} eager steps" if rem else "")
-        n_launch = reps * launches(gs) + launches(rem)
-    else:
-        model.step(st, kp, kd, n_steps)
-        what = f"one eager call of {n_steps} steps"
-        n_launch = launches(n_steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1)
+    runs = []
+    for r in range(max(1, repeats)):
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        if g is not None:
+            reps, rem = n_steps // gs, n_steps % gs
+            for _ in range(reps):
+                g.launch(stream)
+            if rem:
+                model.step(st, kp, kd, rem)
+            what = f"HIP graph of {gs} steps replayed {reps} times" + (f" + {rem} eager steps" if rem else "")
+            n_launch = reps * launches(gs) + launches(rem)
+        else:
+            model.step(st, kp, kd, n_steps)
+            what = f"one eager call of {n_steps} steps"
+            n_launch = launches(n_steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        if r == 0:
+            wall = time.perf_counter() - t0
+        runs.append(ev0.elapsed_time(ev1))
+    ms = runs[0]
     status = model.status(st)
     what += f" ({n_launch} launches of up to {spl} steps)"
-    return ms, wall, int((status != 0).sum()), st, what, n_launch
+    return ms, wall, int((status != 0).sum()), st, what, n_launch, runs
 
 
 def _cpu_model() -> str:
@@ -220,7 +234,7 @@ def row_scale(fwd_steps: int = 200, warm: int = 10, lead: int = 900, tail: int =
     batch = make_batch("row64x16k")
     consts = step_constants()
     m = Model(batch, consts, BENCH_TUNING)
-    ms, _, n_bad, _, _, _ = time_gpu(m, fwd_steps, warm, GRAPH_STEPS)
+    ms, _, n_bad, _, _, _, _ = time_gpu(m, fwd_steps, warm, GRAPH_STEPS)
     fwd = dict(ms_per_step=round(ms / fwd_steps, 4), env_steps_per_s=round(batch.n_env * fwd_steps / (ms / 1e3), 1),
                alg_GBps=round(algorithmic_bytes(batch) * fwd_steps / (ms / 1e3) / 1e9, 1), nonfinite_envs=n_bad)
     del m
@@ -375,15 +389,17 @@ def main():
         tuning, timings = autotune(batch, consts, AUTOTUNE_CANDIDATES, n_warm=3, n_steps=100)
         tune_log = [dict(c, ms_per_step=round(ms, 4)) for c, ms in timings]
         print(f"# autotune {time.perf_counter() - t_tune:.1f} s: {tuning}", file=sys.stderr, flush=True)
-    tuning = {k: tuning[k] for k in ("threads", "pack_fill", "steps_per_launch", "persistent", "lds_width", "pack_skew")}
+    tuning = {k: tuning[k] for k in TUNING_KEYS}
     model = Model(batch, consts, tuning)
-    ms, wall, n_bad, _, what, n_launch = time_gpu(model, args.steps, args.warmup, GRAPH_STEPS)
+    # the first timed rollout is the reported one; four more of the same length (continuing
+    # from its state) give the median beside it
+    ms, wall, n_bad, _, what, n_launch, runs = time_gpu(model, args.steps, args.warmup, GRAPH_STEPS, repeats=5)
     print(f"# optimized: {args.steps} steps in {ms:.1f} ms ({wall:.2f} s wall), packs={model.n_pack}", file=sys.stderr,
           flush=True)
     plain = None
     if not args.no_plain:
         pm = Model(batch, consts, PLAIN_TUNING)
-        pms, _, _, _, _, _ = time_gpu(pm, max(1, args.steps // 4), args.warmup)
+        pms, _, _, _, _, _, _ = time_gpu(pm, max(1, args.steps // 4), args.warmup)
         plain = dict(value=batch.n_env * max(1, args.steps // 4) / (pms / 1e3), ms_per_step=pms / max(1, args.steps // 4),
                      tuning=PLAIN_TUNING)
         del pm
@@ -442,6 +458,7 @@ def main():
                                     f"10-120 apples, in-step random body forces 5% N(0,5N), dt 1 ms",
                            n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=tuning,
                            rollout=what, autotune=tune_log),
+               repeat_ms=[round(x, 3) for x in runs], median_ms_per_step=round(float(np.median(runs)) / args.steps, 5),
                adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
                roofline=roof, cpu_baseline=cpu, row_scale=rows, sphere_fit=sph)
     print(json.dumps(out), flush=True)

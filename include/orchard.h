@@ -119,8 +119,18 @@ typedef struct {
  * closed before a level would exceed it, and a tree wider than it exchanges through
  * global scratch.  0 = global scratch for every pack.  pack_skew (LDS exchange only):
  * 1 = place trees at level offsets inside a strip of pack_fill x (deepest tree) levels
- * so that their widest levels do not coincide.  No mapping choice changes any result
- * bit. */
+ * so that their widest levels do not coincide.  wave_width (0 .. 64, ignored with
+ * persistent = 1): size buckets; a tree whose widest level has at most wave_width nodes
+ * goes to a wave pack that one wavefront walks alone, with no workgroup barrier, its
+ * levels exchanging through 28 x 64 floats of LDS of its own (threads / 64 wave packs per
+ * workgroup, launched after the workgroup-wide packs); 0 = every pack takes a whole
+ * workgroup.  big_threads (0, 256 or 512; used when it exceeds lds_width, ignored with
+ * persistent = 1): the wide-tree bucket; a tree whose widest level exceeds lds_width but
+ * not big_threads goes to a pack of big_threads work-items with an LDS exchange of
+ * big_threads slots, launched on a second stream of the model's (default priority)
+ * concurrently with the other packs, instead of exchanging through global scratch.  The
+ * adjoint's recompute and reverse pass run every pack in the main mapping.  No mapping
+ * choice changes any result bit. */
 typedef struct {
   int32_t threads;
   float pack_fill;
@@ -132,6 +142,8 @@ typedef struct {
                                 /*   records, a second stream and five events)        */
   int32_t lds_width;
   int32_t pack_skew;
+  int32_t wave_width;
+  int32_t big_threads;
 } orchard_tuning_t;
 
 typedef struct {
@@ -140,6 +152,8 @@ typedef struct {
   int64_t scratch_bytes;        /* device memory the model owns                       */
   int32_t apple_planes;         /* float planes of the apple state: 13 (rigid body) or */
                                 /*   6 (translational fruit)                          */
+  int32_t n_wave_packs;         /* packs walked by one wavefront (tuning.wave_width)   */
+  int32_t n_big_packs;          /* packs of the wide-tree bucket (tuning.big_threads)  */
   int32_t pad;
 } orchard_layout_t;
 

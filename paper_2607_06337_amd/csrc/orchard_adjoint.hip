@@ -542,7 +542,7 @@ __global__ __launch_bounds__(NT) void k_adjoint_packs(DevModel M, DevState W, co
   L.X = reinterpret_cast<float*>(xlds4);
   L.cap = M.lds_cap;
   L.b = 0;
-  if (M.lds_cap > 0 && ldc(M.pack_lds, pk)) adjoint_pack_lds<NT>(M, W, R0, I, X, L, lb, le, n, s_call);
+  if (M.lds_cap > 0 && ldc(M.pack_wmax, pk) <= M.lds_cap) adjoint_pack_lds<NT>(M, W, R0, I, X, L, lb, le, n, s_call);
   else adjoint_pack_global<NT>(M, W, R0, I, X, L, lb, le, n, s_call);
 }
 

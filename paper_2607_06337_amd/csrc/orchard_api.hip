@@ -71,6 +71,11 @@ struct orchard_model_s {
   orchard_tuning_t tun{};
   int64_t n_env = 0, n_seg = 0, n_apple = 0;
   int32_t n_pack = 0, max_depth = 0;
+  int32_t n_wide = 0;                                 // packs that take a whole workgroup
+  int32_t n_main = 0;                                 // packs of the main launch (the rest: wide-tree bucket)
+  size_t big_lds_bytes = 0;                           // dynamic LDS of the wide-tree launch
+  hipStream_t s_big = nullptr;                        // its stream (default priority)
+  hipEvent_t ev_big[2] = {nullptr, nullptr};          // fork and join of the two launches
   std::vector<int32_t> seg_map, apple_map;            // internal -> descriptor global
   std::vector<int32_t> env_seg_off, env_apple_off;    // descriptor offsets
   std::vector<int32_t> node_env_h, apple_env_h;
@@ -125,13 +130,29 @@ struct Arena {
 
 }  // namespace
 
+// Allow a kernel `bytes` of dynamic LDS.  The limit is a property of the kernel, shared by
+// every model in the process, so it only ever rises (to the largest any model asked for).
+static void allow_lds(const void* k, int bytes) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, int>> granted;
+  if (bytes <= 65536) return;
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& g : granted)
+    if (g.first == k) {
+      if (g.second >= bytes) return;
+      g.second = bytes;
+      (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+      return;
+    }
+  granted.push_back({k, bytes});
+  (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 // allow the exchange buffer's dynamic LDS and return resident workgroups per CU
 template <class KP, class KQ>
 static int lds_setup(KP kp, KQ kq, int nt, int lds_bytes) {
-  if (lds_bytes > 65536) {
-    (void)hipFuncSetAttribute((const void*)kp, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    (void)hipFuncSetAttribute((const void*)kq, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-  }
+  allow_lds((const void*)kp, lds_bytes);
+  allow_lds((const void*)kq, lds_bytes);
   int per_cu = 1;
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kq, nt, lds_bytes);
   return per_cu;
@@ -172,10 +193,14 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       d->friction_ramp_time < 0 || d->friction_speed < 0 || d->fade_speed < 0 || d->brake_rate < 0 ||
       (d->friction_base > 0 && !(d->friction_speed > 0)))
     return fail(ORCHARD_ERR_INVALID_ARG, "extra out of range (all >= 0; friction needs friction_speed > 0)");
-  orchard_tuning_t tun{128, 1.0f, 1, 0, 0, 128, 0};
+  orchard_tuning_t tun{128, 1.0f, 1, 0, 0, 128, 0, 0, 0};
   if (tuning) tun = *tuning;
   if (tun.lds_width < 0 || tun.lds_width > tun.threads)
     return fail(ORCHARD_ERR_INVALID_ARG, "tuning.lds_width must be in [0, threads]");
+  if (tun.wave_width < 0 || tun.wave_width > 64)
+    return fail(ORCHARD_ERR_INVALID_ARG, "tuning.wave_width must be in [0, 64]");
+  if (tun.big_threads != 0 && tun.big_threads != 256 && tun.big_threads != 512)
+    return fail(ORCHARD_ERR_INVALID_ARG, "tuning.big_threads must be 0, 256 or 512");
   if (tun.adjoint_ckpt_max < 0) return fail(ORCHARD_ERR_INVALID_ARG, "tuning.adjoint_ckpt_max < 0");
   if (tun.threads != 64 && tun.threads != 128 && tun.threads != 256 && tun.threads != 512)
     return fail(ORCHARD_ERR_INVALID_ARG, "tuning.threads must be 64, 128, 256 or 512");
@@ -262,7 +287,60 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   // packs[p] lists (tree, level offset): tree t placed at offset o occupies the pack's
   // levels o .. o + depth_t - 1.  Levels of different trees never depend on each other,
   // so a pack may run different depths of different trees side by side.
+  // Size buckets: with wave_width > 0 (and no persistent queue) a tree whose widest level
+  // has at most wave_width nodes goes to a wave pack, which one wavefront walks alone
+  // with no workgroup barrier; the other trees go to workgroup-wide packs.
   std::vector<std::vector<std::pair<int32_t, int32_t>>> packs;
+  // With big_threads > lds_width (and no persistent queue) a tree whose widest level does
+  // not fit the main launch's LDS exchange but fits big_threads nodes goes to the wide-tree
+  // bucket: packs of big_threads work-items and an LDS exchange of big_threads slots, run
+  // by a launch of their own on a second stream, concurrently with the main launch.
+  std::vector<int32_t> tree_ids;   // trees of the workgroup-wide packs
+  std::vector<int32_t> wave_trees;  // trees of the wave packs
+  std::vector<int32_t> big_trees;   // trees of the wide-tree bucket
+  std::vector<char> in_wave(B, 0), in_big(B, 0);
+  const bool waves_on = tun.wave_width > 0 && !tun.persistent;
+  const bool big_on = tun.big_threads > tun.lds_width && tun.lds_width > 0 && !tun.persistent;
+  for (int e = 0; e < B; ++e) {
+    const int64_t wm = *std::max_element(lvlw[e].begin(), lvlw[e].end());
+    in_wave[e] = waves_on && wm <= tun.wave_width;
+    in_big[e] = big_on && wm > tun.lds_width && wm <= tun.big_threads;
+    (in_wave[e] ? wave_trees : in_big[e] ? big_trees : tree_ids).push_back(e);
+  }
+  // trees of similar depth, about fill * nt * depth nodes per pack; with w > 0 a pack also
+  // closes before one of its levels would exceed w nodes (a tree wider than w gets a pack
+  // of its own that exchanges through global scratch)
+  auto depth_packs = [&](const std::vector<int32_t>& ids, int nt, int64_t w, float fill) {
+    std::vector<int32_t> tord = ids;
+    std::stable_sort(tord.begin(), tord.end(), [&](int a, int b) {
+      if (lvlw[a].size() != lvlw[b].size()) return lvlw[a].size() > lvlw[b].size();
+      return d->seg_offset[a + 1] - d->seg_offset[a] > d->seg_offset[b + 1] - d->seg_offset[b];
+    });
+    std::vector<std::pair<int32_t, int32_t>> cur;
+    std::vector<int64_t> curw;
+    int64_t cur_nodes = 0;
+    size_t cur_depth = 0;
+    for (int t : tord) {
+      const int64_t St = d->seg_offset[t + 1] - d->seg_offset[t];
+      const size_t dt = lvlw[t].size();
+      bool wide = false;
+      if (w > 0)
+        for (size_t l = 0; l < dt && l < curw.size(); ++l) wide = wide || curw[l] + lvlw[t][l] > w;
+      if (!cur.empty() && (fill <= 0.f || cur_nodes + St > (int64_t)(fill * nt * cur_depth) ||
+                           dt * 10 < cur_depth * 7 || wide)) {
+        packs.push_back(cur);
+        cur.clear();
+        curw.clear();
+        cur_nodes = 0;
+      }
+      if (cur.empty()) cur_depth = dt;
+      cur.push_back({t, 0});
+      cur_nodes += St;
+      if (curw.size() < dt) curw.resize(dt, 0);
+      for (size_t l = 0; l < dt; ++l) curw[l] += lvlw[t][l];
+    }
+    if (!cur.empty()) packs.push_back(cur);
+  };
   const int64_t W = tun.lds_width;
   if (W > 0 && tun.pack_fill > 0.f && tun.pack_skew) {
     // depth-offset first fit.  A pack is a strip of V levels of at most W
@@ -280,6 +358,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     std::vector<size_t> strip_pack;        // strip -> pack index
     const int K = 16;
     for (int t : sord) {
+      if (in_wave[t] || in_big[t]) continue;
       const auto& wt = lvlw[t];
       const int Dt = (int)wt.size();
       const int64_t wmax_t = *std::max_element(wt.begin(), wt.end());
@@ -305,41 +384,12 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       }
     }
   } else {
-    // trees of similar depth, about pack_fill * threads * depth nodes; with an LDS
-    // exchange a pack also closes before one of its levels would exceed W nodes (a tree
-    // wider than W gets a pack of its own that exchanges through global scratch)
-    const int NT0 = tun.threads;
-    std::vector<int32_t> tord(B);
-    std::iota(tord.begin(), tord.end(), 0);
-    std::stable_sort(tord.begin(), tord.end(), [&](int a, int b) {
-      if (lvlw[a].size() != lvlw[b].size()) return lvlw[a].size() > lvlw[b].size();
-      return d->seg_offset[a + 1] - d->seg_offset[a] > d->seg_offset[b + 1] - d->seg_offset[b];
-    });
-    std::vector<std::pair<int32_t, int32_t>> cur;
-    std::vector<int64_t> curw;
-    int64_t cur_nodes = 0;
-    size_t cur_depth = 0;
-    for (int t : tord) {
-      const int64_t St = d->seg_offset[t + 1] - d->seg_offset[t];
-      const size_t dt = lvlw[t].size();
-      bool wide = false;
-      if (W > 0)
-        for (size_t l = 0; l < dt && l < curw.size(); ++l) wide = wide || curw[l] + lvlw[t][l] > W;
-      if (!cur.empty() && (tun.pack_fill <= 0.f || cur_nodes + St > (int64_t)(tun.pack_fill * NT0 * cur_depth) ||
-                           dt * 10 < cur_depth * 7 || wide)) {
-        packs.push_back(cur);
-        cur.clear();
-        curw.clear();
-        cur_nodes = 0;
-      }
-      if (cur.empty()) cur_depth = dt;
-      cur.push_back({t, 0});
-      cur_nodes += St;
-      if (curw.size() < dt) curw.resize(dt, 0);
-      for (size_t l = 0; l < dt; ++l) curw[l] += lvlw[t][l];
-    }
-    if (!cur.empty()) packs.push_back(cur);
+    depth_packs(tree_ids, tun.threads, W, tun.pack_fill);
   }
+  const size_t n_wide = packs.size();
+  depth_packs(wave_trees, 64, tun.wave_width, tun.pack_fill);
+  const size_t n_main = packs.size();
+  depth_packs(big_trees, tun.big_threads, tun.big_threads, tun.pack_fill);
   const int NT = tun.threads;
   // level widths of every pack
   std::vector<std::vector<int64_t>> packw(packs.size());
@@ -357,20 +407,26 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   std::vector<double> pcost(packs.size());
   for (size_t p = 0; p < packs.size(); ++p) {
     int64_t sweeps = 0, nodes = 0, apples = 0;
-    for (int64_t w : packw[p]) sweeps += (w + NT - 1) / NT;
+    const int nt = p < n_wide ? NT : p < n_main ? 64 : tun.big_threads;
+    for (int64_t w : packw[p]) sweeps += (w + nt - 1) / nt;
     for (auto& to : packs[p]) {
       nodes += d->seg_offset[to.first + 1] - d->seg_offset[to.first];
       apples += d->apple_offset[to.first + 1] - d->apple_offset[to.first];
     }
     pcost[p] = 6.67 * (double)sweeps + 3.41 * (double)nodes / 256.0 + 7.74 * (double)apples / 256.0;
   }
+  // workgroup-wide packs first, then the wave packs (threads / 64 consecutive ones share a
+  // workgroup), then the wide-tree bucket, each in longest-processing-time order
   std::vector<int32_t> pord(packs.size());
   std::iota(pord.begin(), pord.end(), 0);
-  std::stable_sort(pord.begin(), pord.end(), [&](int a, int b) { return pcost[a] > pcost[b]; });
+  auto by_cost = [&](int a, int b) { return pcost[a] > pcost[b]; };
+  std::stable_sort(pord.begin(), pord.begin() + n_wide, by_cost);
+  std::stable_sort(pord.begin() + n_wide, pord.begin() + n_main, by_cost);
+  std::stable_sort(pord.begin() + n_main, pord.end(), by_cost);
 
   // ---- internal order ----
   std::vector<int32_t> seg_map;  seg_map.reserve(NS);
-  std::vector<int32_t> pack_node, pack_lvl, lvl_off, pack_lds;
+  std::vector<int32_t> pack_node, pack_lvl, lvl_off, pack_wmax;
   std::vector<int32_t> int_of(NS, -1);
   int n_lds_packs = 0;
   for (int pi : pord) {
@@ -380,7 +436,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     const size_t L = packw[pi].size();
     const int64_t wmax = *std::max_element(packw[pi].begin(), packw[pi].end());
     const int fits = tun.lds_width > 0 && wmax <= tun.lds_width;
-    pack_lds.push_back(fits);
+    pack_wmax.push_back((int32_t)wmax);
     n_lds_packs += fits;
     std::vector<size_t> pos(P.size(), 0);
     for (size_t l = 0; l < L; ++l) {
@@ -495,6 +551,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   M->tun = tun;
   M->n_env = B; M->n_seg = NS; M->n_apple = NA;
   M->n_pack = (int32_t)packs.size();
+  M->n_wide = (int32_t)n_wide;
+  M->n_main = (int32_t)n_main;
   M->max_depth = maxd;
   M->seg_map = seg_map;
   M->apple_map = aord;
@@ -512,7 +570,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
          o_rq = ar.put(rq.data(), NS * 16), o_geo = ar.put(geo.data(), NS * 16), o_mm = ar.put(mmax_f.data(), NS * 4),
          o_ah = ar.put(ahang_h.data(), NA * 16), o_ap = ar.put(apar_h.data(), NA * 16),
          o_kp = ar.put(kp_f.data(), NS * 4), o_kd = ar.put(kd_f.data(), NS * 4), o_ar = ar.put(arest.data(), 3 * NA * 4),
-         o_hr = ar.put(ahrest_h.data(), NA * 16), o_pd = ar.put(pack_lds.data(), pack_lds.size() * 4),
+         o_hr = ar.put(ahrest_h.data(), NA * 16), o_pd = ar.put(pack_wmax.data(), pack_wmax.size() * 4),
          o_nr = ar.put(nrec.data(), NS * sizeof(NodeRec)), o_ar2 = ar.put(arec.data(), NA * sizeof(AppleRec)),
          o_hk = ar.put(hkey.data(), NS * 8), o_pa = ar.put(pack_apl.data(), pack_apl.size() * 4),
          o_nt = ar.put(ntopo.data(), NS * 16), o_len = ar.put(seglen.data(), NS * 4),
@@ -565,7 +623,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.apple_beg = (const int32_t*)(base + o_ab); dm.rq = (const float4*)(base + o_rq);
   dm.geo = (const float4*)(base + o_geo); dm.mmax = (const float*)(base + o_mm);
   dm.ahang = (const float4*)(base + o_ah); dm.apar = (const float4*)(base + o_ap);
-  dm.ahrest = (const float4*)(base + o_hr); dm.pack_lds = (const int32_t*)(base + o_pd);
+  dm.ahrest = (const float4*)(base + o_hr); dm.pack_wmax = (const int32_t*)(base + o_pd);
   dm.nrec = (const NodeRec*)(base + o_nr); dm.arec = (const AppleRec*)(base + o_ar2);
   dm.hkey = (const uint64_t*)(base + o_hk);
   dm.pack_apl = (const int32_t*)(base + o_pa);
@@ -573,8 +631,14 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   dm.len = (const float*)(base + o_len);
   dm.scr_nf = scr_nf;
   dm.lds_cap = n_lds_packs > 0 ? tun.lds_width : 0;
-  // dynamic LDS of the step kernels: the level exchange, reused by the apple phase
+  dm.n_wide = M->n_wide;
+  dm.pack_base = 0;
+  // dynamic LDS of the step kernels: the level exchange, reused by the apple phase; a
+  // workgroup of wave packs holds X_STRIDE x 64 floats per wavefront
   M->lds_bytes = std::max((size_t)dm.lds_cap * 2 * X_STRIDE, (size_t)11 * tun.threads) * 4;
+  if (M->n_wide < M->n_main) M->lds_bytes = std::max(M->lds_bytes, (size_t)(tun.threads / 64) * X_STRIDE * 64 * 4);
+  if (M->n_main < M->n_pack)
+    M->big_lds_bytes = std::max((size_t)tun.big_threads * 2 * X_STRIDE, (size_t)11 * tun.big_threads) * 4;
   M->kp0 = (float*)(base + o_kp); M->kd0 = (float*)(base + o_kd); M->apple_rest = (float*)(base + o_ar);
   dm.queue = (int32_t*)(base + o_q);
   dm.h = (float)d->dt;
@@ -620,11 +684,21 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     default: per_cu = lds_setup(k_step_packs<512>, k_step_persistent<512>, 512, lb); break;
   }
   M->persist_blocks = std::max(1, std::min<int>(M->n_pack, std::max(1, per_cu) * std::max(1, M->n_cu)));
-  if (tun.adjoint_ckpt_max > 0 && lb > 65536) {
+  if (tun.adjoint_ckpt_max > 0) {
     const void* ka = tun.threads == 64 ? (const void*)k_adjoint_packs<64>
                      : tun.threads == 128 ? (const void*)k_adjoint_packs<128>
                      : tun.threads == 256 ? (const void*)k_adjoint_packs<256> : (const void*)k_adjoint_packs<512>;
-    (void)hipFuncSetAttribute(ka, hipFuncAttributeMaxDynamicSharedMemorySize, lb);
+    allow_lds(ka, lb);
+  }
+  if (M->n_main < M->n_pack) {
+    allow_lds(tun.big_threads == 512 ? (const void*)k_step_packs<512> : (const void*)k_step_packs<256>,
+              (int)M->big_lds_bytes);
+    if (hipStreamCreateWithFlags(&M->s_big, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&M->ev_big[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&M->ev_big[1], hipEventDisableTiming) != hipSuccess) {
+      orchard_model_destroy(M);
+      return fail(ORCHARD_ERR_HIP, "wide-tree stream or events");
+    }
   }
   if (tun.adjoint_ckpt_max > 0) {
     const int64_t words = orchard_ckpt_words(M);
@@ -670,9 +744,10 @@ void orchard_model_destroy(orchard_model_t m) {
   if (m->recs) (void)hipFree(m->recs);
   if (m->reps) (void)hipFree(m->reps);
   if (m->work) (void)hipFree(m->work);
-  for (hipEvent_t e : {m->ev_in, m->ev_rec[0], m->ev_rec[1], m->ev_adj[0], m->ev_adj[1]})
+  for (hipEvent_t e : {m->ev_in, m->ev_rec[0], m->ev_rec[1], m->ev_adj[0], m->ev_adj[1], m->ev_big[0], m->ev_big[1]})
     if (e) (void)hipEventDestroy(e);
   if (m->s_aux) (void)hipStreamDestroy(m->s_aux);
+  if (m->s_big) (void)hipStreamDestroy(m->s_big);
   if (m->arena) (void)hipFree(m->arena);
   if (m->scr) (void)hipFree(m->scr);
   delete m;
@@ -682,7 +757,10 @@ orchard_status_t orchard_model_layout(orchard_model_t m, orchard_layout_t* out) 
   if (!m || !out) return fail(ORCHARD_ERR_INVALID_ARG, "null argument");
   out->n_env = m->n_env; out->n_seg = m->n_seg; out->n_apple = m->n_apple;
   out->n_pack = m->n_pack; out->max_depth = m->max_depth; out->scratch_bytes = m->bytes;
-  out->apple_planes = m->apl; out->pad = 0;
+  out->apple_planes = m->apl;
+  out->n_wave_packs = m->n_main - m->n_wide;
+  out->n_big_packs = m->n_pack - m->n_main;
+  out->pad = 0;
   return ORCHARD_OK;
 }
 
@@ -757,8 +835,10 @@ static orchard_status_t launch_steps(orchard_model_t m, const DevModel& dm0, con
   const int NT = m->tun.threads;
   const unsigned lb = (unsigned)m->lds_bytes;
   if (save) {
+    // the adjoint's recompute runs every pack on a whole workgroup
     DevModel dm = dm0;
     dm.save_adj = 1;
+    dm.n_wide = dm.n_pack;
     if (scr) dm.scr = scr;
     const dim3 g(m->n_pack);
     switch (NT) {
@@ -776,13 +856,37 @@ static orchard_status_t launch_steps(orchard_model_t m, const DevModel& dm0, con
       default: hipLaunchKernelGGL(k_step_persistent<512>, g, dim3(512), lb, stream, dm0, ds, di, k, s_call, dm0.queue); break;
     }
   } else {
-    const dim3 g(m->n_pack);
-    switch (NT) {
-      case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, stream, dm0, ds, di, k, s_call); break;
-      case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), lb, stream, dm0, ds, di, k, s_call); break;
-      case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lb, stream, dm0, ds, di, k, s_call); break;
-      default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), lb, stream, dm0, ds, di, k, s_call); break;
+    // the wide-tree bucket (packs [n_main, n_pack)) runs on its own stream, concurrently
+    // with the main launch; both join before the step counter advances
+    const bool big = m->n_main < m->n_pack;
+    if (big) {
+      HIPCHK(hipEventRecord(m->ev_big[0], stream));
+      HIPCHK(hipStreamWaitEvent(m->s_big, m->ev_big[0], 0));
+      DevModel db = dm0;
+      db.pack_base = m->n_main;
+      db.n_wide = db.n_pack;
+      db.lds_cap = m->tun.big_threads;
+      const dim3 gb(m->n_pack - m->n_main);
+      const unsigned lbb = (unsigned)m->big_lds_bytes;
+      if (m->tun.big_threads == 512)
+        hipLaunchKernelGGL(k_step_packs<512>, gb, dim3(512), lbb, m->s_big, db, ds, di, k, s_call);
+      else
+        hipLaunchKernelGGL(k_step_packs<256>, gb, dim3(256), lbb, m->s_big, db, ds, di, k, s_call);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(m->ev_big[1], m->s_big));
     }
+    if (m->n_main > 0) {
+      DevModel dmm = dm0;
+      dmm.n_pack = m->n_main;
+      const dim3 g(m->n_wide + (m->n_main - m->n_wide + NT / 64 - 1) / (NT / 64));
+      switch (NT) {
+        case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, stream, dmm, ds, di, k, s_call); break;
+        case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), lb, stream, dmm, ds, di, k, s_call); break;
+        case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lb, stream, dmm, ds, di, k, s_call); break;
+        default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), lb, stream, dmm, ds, di, k, s_call); break;
+      }
+    }
+    if (big) HIPCHK(hipStreamWaitEvent(stream, m->ev_big[1], 0));
   }
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, stream, ds.step, (m->tun.persistent && !save) ? dm0.queue : nullptr, k);

@@ -119,7 +119,8 @@ struct DevModel {
   const int32_t* pack_node;
   const int32_t* pack_lvl;
   const int32_t* lvl_off;
-  const int32_t* pack_lds;   // 1: every level of the pack fits the workgroup (LDS publications)
+  const int32_t* pack_wmax;  // nodes on the pack's widest level: its levels exchange through
+                             // LDS when that fits the launch's exchange buffer (<= lds_cap)
   const int32_t* pack_apl;   // [n_pack+1] apples of pack p: pack_apl[p] .. pack_apl[p+1]-1
   const NodeRec* nrec;       // per node (internal order)
   const int4* ntopo;         // per node: (env, first child, children | apples << 16, apple-node index)
@@ -159,7 +160,9 @@ struct DevModel {
   int32_t save_adj;          // forward step also writes the fields the adjoint reads back
   int32_t scr_nf;            // fields per node: N_FIELDS, or N_FIELDS_ADJ with adjoint support
   int32_t lds_cap;           // LDS exchange capacity in nodes per level (0: global exchange)
-  int32_t pad1;
+  int32_t n_wide;            // packs [0, n_wide) take a whole workgroup; packs [n_wide, n_pack)
+                             // are walked by one wavefront each, threads / 64 per workgroup
+  int32_t pack_base;         // pack of the launch's first workgroup
 };
 
 // Scratch layout: nodes in blocks of 64 (one wavefront), each block [scr_nf][64].  A node's
@@ -410,6 +413,31 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The same two synchronisations for a pack that one wavefront walks alone: its lanes
+// execute in lockstep and a wave's LDS and memory operations complete in issue order once
+// waited for, so the fences (which wait for the wave's outstanding operations and keep the
+// compiler from moving accesses across them) are all it needs; no workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void sync_lds() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  } else {
+    lds_barrier();
+  }
+}
+template <bool WAVE>
+__device__ __forceinline__ void sync_all() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  } else {
+    __syncthreads();
+  }
 }
 
 }  // namespace orchard

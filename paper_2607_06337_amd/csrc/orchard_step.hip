@@ -282,11 +282,11 @@ __device__ __forceinline__ void put_fields(float* base, const float (&o)[K]) {
 // inertia in apple order, so the sums do not depend on the mapping.
 struct AppleCon { float mv; V3 d, pang, plin; };
 
-template <int NT>
+template <int NT, bool WAVE = false>
 __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S, const DevInputs& I, const Lvl& L,
-                                            float* C, int pk, int64_t n, int s_call) {
+                                            float* C, int pk, int64_t n, int s_call, int t) {
   const int A0 = ldc(M.pack_apl, pk), A1 = ldc(M.pack_apl, pk + 1);
-  const int NS = M.n_seg, t = (int)threadIdx.x;
+  const int NS = M.n_seg;
   const uint32_t NA = (uint32_t)M.n_apple;
   const float h = M.h;
   const V3 gv = v3(M.gx, M.gy, M.gz);
@@ -406,7 +406,7 @@ __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S
     C[4 * NT + t] = con.pang.x; C[5 * NT + t] = con.pang.y; C[6 * NT + t] = con.pang.z;
     C[7 * NT + t] = con.plin.x; C[8 * NT + t] = con.plin.y; C[9 * NT + t] = con.plin.z;
     C[10 * NT + t] = __int_as_float(node);
-    lds_barrier();
+    sync_lds<WAVE>();
     // the thread with a node's first apple in this chunk adds the chunk's contributions;
     // the virtual inertia starts from zero at the node's first apple
     if (has && (t == 0 || __float_as_int(C[10 * NT + t - 1]) != node)) {
@@ -436,7 +436,7 @@ __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S
       es[3] = make_float4(pang.z, plin.x, plin.y, plin.z);
     }
     // node sums of this chunk are visible to the next chunk's threads; the LDS can be reused
-    __syncthreads();
+    sync_all<WAVE>();
   }
 }
 
@@ -805,7 +805,7 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
   for (int st = 0; st < n_inner; ++st) {
     const int64_t n = n0 + st;
     const uint64_t kstep = splitmix64((uint64_t)n);
-    apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
+    apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st, t);
     for (int lv = le - 1; lv >= lb; --lv) {
       L.a = M.lvl_off[lv];
       const int e = M.lvl_off[lv + 1];
@@ -833,11 +833,14 @@ __device__ __forceinline__ void run_pack_global(const DevModel& M, const DevStat
 // threads).  Each pass is software-pipelined: the loads of this thread's node on the
 // next level are issued before the current level's arithmetic; they read only static
 // data, data this thread wrote itself, or data completed before the pass began.
-template <int NT>
+// WAVE: the pack is walked by one wavefront (NT = 64, t its lane) without workgroup
+// barriers; its exchange is then a single buffer (L.cap = 0): every lane reads its
+// neighbours' slots before any lane of the wave writes its own.
+template <int NT, bool WAVE = false>
 __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& S, const DevInputs& I, Lvl& L,
                                              float* Abuf, int pk, int lb, int le, int64_t n0, int n_inner,
                                              int call_step0) {
-  const int t = (int)threadIdx.x;
+  const int t = WAVE ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
   {
     int i = M.lvl_off[lb] + lvl_lane<NT>(t, lb);
     bool has = i < M.lvl_off[lb + 1];
@@ -852,15 +855,15 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
       In1 nxt{};
       if (hn) nxt = load1(M, S, I, in_);
       if (has) pass_down1<true>(M, S, L, i, cur);
-      if (lv + 1 < le) lds_barrier();
+      if (lv + 1 < le) sync_lds<WAVE>();
       i = in_; has = hn; cur = nxt;
     }
   }
-  __syncthreads();
+  sync_all<WAVE>();
   for (int st = 0; st < n_inner; ++st) {
     const int64_t n = n0 + st;
     const uint64_t kstep = splitmix64((uint64_t)n);
-    apple_phase<NT>(M, S, I, L, Abuf, pk, n, call_step0 + st);
+    apple_phase<NT, WAVE>(M, S, I, L, Abuf, pk, n, call_step0 + st, t);
     {
       int i = M.lvl_off[le - 1] + lvl_lane<NT>(t, le - 1);
       bool has = i < M.lvl_off[le];
@@ -879,11 +882,11 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
           node_up<true>(M, S, I, L, i, cur, n, kstep, call_step0 + st, o);
           put_fields<F_WM>(&at(L.P, slane(L.nf, i - L.i0)), o);
         }
-        if (lv > lb) lds_barrier();
+        if (lv > lb) sync_lds<WAVE>();
         i = in_; has = hn; cur = nxt;
       }
     }
-    __syncthreads();
+    sync_all<WAVE>();
     if (st + 1 < n_inner) {
       int i = M.lvl_off[lb] + lvl_lane<NT>(t, lb);
       bool has = i < M.lvl_off[lb + 1];
@@ -900,7 +903,7 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         In1 n1{};
         if (hn) { n2 = load2<false>(M, S, L, in_); n1 = load1<false>(M, S, I, in_); }
         if (has) pass_fused<true>(M, S, L, i, c2, c1);
-        if (lv + 1 < le) lds_barrier();
+        if (lv + 1 < le) sync_lds<WAVE>();
         i = in_; has = hn; c2 = n2; c1 = n1;
       }
     } else {
@@ -917,11 +920,11 @@ __device__ __forceinline__ void run_pack_lds(const DevModel& M, const DevState& 
         In2 nxt{};
         if (hn) nxt = load2(M, S, L, in_);
         if (has) pass_down2<true>(M, S, L, i, cur);
-        if (lv + 1 < le) lds_barrier();
+        if (lv + 1 < le) sync_lds<WAVE>();
         i = in_; has = hn; cur = nxt;
       }
     }
-    __syncthreads();
+    sync_all<WAVE>();
   }
 }
 
@@ -943,20 +946,44 @@ __device__ __forceinline__ void run_pack(const DevModel& M, const DevState& S, c
 template <int NT>
 __device__ __forceinline__ void run_pack_any(const DevModel& M, const DevState& S, const DevInputs& I, float* X,
                                              float* Abuf, int pk, int64_t n0, int n_inner, int call_step0) {
-  if (M.lds_cap > 0 && ldc(M.pack_lds, pk)) run_pack<NT, true>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
+  if (M.lds_cap > 0 && ldc(M.pack_wmax, pk) <= M.lds_cap) run_pack<NT, true>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
   else run_pack<NT, false>(M, S, I, X, Abuf, pk, n0, n_inner, call_step0);
 }
 
-// one workgroup per pack; dynamic LDS: max(2 * X_STRIDE * lds_cap, 11 * NT) floats, the
-// level exchange and, between down 1 and up, the apple phase's chunk buffer
-// At least three waves per SIMD (at most 168 VGPRs): the exchange LDS of the widest
-// packs also allows three workgroups of 256 work-items per CU.
+// A pack walked by one wavefront: its levels fit 64 lanes and exchange through the
+// wave's own X_STRIDE x 64 floats of LDS (a single buffer), which also hold the apple
+// phase's chunk buffer.
+__device__ __forceinline__ void run_pack_wave(const DevModel& M, const DevState& S, const DevInputs& I, float* X,
+                                              int pk, int64_t n0, int n_inner, int call_step0) {
+  const int lb = ldc(M.pack_lvl, pk), le = ldc(M.pack_lvl, pk + 1) - 1;
+  Lvl L;
+  L.i0 = ldc(M.pack_node, pk) & ~63;
+  L.nf = M.scr_nf;
+  L.P = M.scr + (size_t)(L.i0 >> 6) * (size_t)L.nf * 64u;
+  L.X = X;
+  L.cap = 0;
+  L.b = 0;
+  run_pack_lds<64, true>(M, S, I, L, X, pk, lb, le, n0, n_inner, call_step0);
+}
+
+// Packs [0, n_wide): one workgroup each; dynamic LDS max(2 * X_STRIDE * lds_cap, 11 * NT)
+// floats, the level exchange and, between down 1 and up, the apple phase's chunk buffer.
+// Packs [n_wide, n_pack): NT / 64 per workgroup, one per wavefront, X_STRIDE * 64 floats
+// of LDS each.  At least three waves per SIMD (at most 168 VGPRs): the exchange LDS of
+// the widest packs also allows three workgroups of 256 work-items per CU.
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_step_packs(DevModel M, DevState S, DevInputs I, int n_inner, int call_step0) {
   HIP_DYNAMIC_SHARED(float4, xlds4)
   float* xlds = reinterpret_cast<float*>(xlds4);
   const int64_t n0 = *S.step;
-  run_pack_any<NT>(M, S, I, xlds, xlds, (int)blockIdx.x, n0, n_inner, call_step0);
+  const int b = (int)blockIdx.x + M.pack_base;
+  if (b < M.n_wide) {
+    run_pack_any<NT>(M, S, I, xlds, xlds, b, n0, n_inner, call_step0);
+    return;
+  }
+  const int w = (int)(threadIdx.x >> 6);
+  const int pk = M.n_wide + (b - M.n_wide) * (NT / 64) + w;
+  if (pk < M.n_pack) run_pack_wave(M, S, I, xlds + w * (X_STRIDE * 64), pk, n0, n_inner, call_step0);
 }
 
 // persistent grid: workgroups pull packs (largest first) from a counter

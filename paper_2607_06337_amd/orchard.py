@@ -43,13 +43,13 @@ _DESC_DEFAULTS = dict(stiffness_k0=0.0, stiffness_gamma=1.0, fruit_dof=6, drag_l
 
 # the library's defaults (orchard_model_create with a null tuning)
 DEFAULT_TUNING = dict(threads=128, pack_fill=1.0, steps_per_launch=1, persistent=0, adjoint_ckpt_max=0, lds_width=128,
-                      pack_skew=0)
+                      pack_skew=0, wave_width=0, big_threads=0)
 
 
 class Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("pack_fill", C.c_float), ("steps_per_launch", C.c_int32),
                 ("persistent", C.c_int32), ("adjoint_ckpt_max", C.c_int32), ("lds_width", C.c_int32),
-                ("pack_skew", C.c_int32)]
+                ("pack_skew", C.c_int32), ("wave_width", C.c_int32), ("big_threads", C.c_int32)]
 
 
 class CAdjoint(C.Structure):
@@ -59,7 +59,7 @@ class CAdjoint(C.Structure):
 class Layout(C.Structure):
     _fields_ = [("n_env", C.c_int64), ("n_seg", C.c_int64), ("n_apple", C.c_int64), ("n_pack", C.c_int32),
                 ("max_depth", C.c_int32), ("scratch_bytes", C.c_int64), ("apple_planes", C.c_int32),
-                ("pad", C.c_int32)]
+                ("n_wave_packs", C.c_int32), ("n_big_packs", C.c_int32), ("pad", C.c_int32)]
 
 
 class CState(C.Structure):
@@ -241,7 +241,8 @@ def _tuning(t: dict) -> Tuning:
     if "lds_width" not in t:
         u["lds_width"] = min(int(u["lds_width"]), int(u["threads"]))
     return Tuning(int(u["threads"]), float(u["pack_fill"]), int(u["steps_per_launch"]), int(u["persistent"]),
-                  int(u["adjoint_ckpt_max"]), int(u["lds_width"]), int(u["pack_skew"]))
+                  int(u["adjoint_ckpt_max"]), int(u["lds_width"]), int(u["pack_skew"]), int(u["wave_width"]),
+                  int(u["big_threads"]))
 
 
 def _tuning_dict(t: Tuning) -> dict:
@@ -330,6 +331,7 @@ class Model:
         self.n_env, self.n_seg, self.n_apple = int(lay.n_env), int(lay.n_seg), int(lay.n_apple)
         self.apple_planes = int(lay.apple_planes)
         self.n_pack, self.max_depth, self.scratch_bytes = int(lay.n_pack), int(lay.max_depth), int(lay.scratch_bytes)
+        self.n_wave_packs, self.n_big_packs = int(lay.n_wave_packs), int(lay.n_big_packs)
         self.seg_map = np.zeros(self.n_seg, np.int32)
         self.apple_map = np.zeros(self.n_apple, np.int32)
         _check(L.orchard_model_maps(self.h, _np_ptr(self.seg_map), _np_ptr(self.apple_map)))

@@ -159,7 +159,11 @@ def test_gradients_are_bitwise_identical_across_mappings():
     F = grad_apple_forces(batch, T)
     tip_idx, target = grad_targets(batch, _rest_tips(batch))
     ref = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=10, tuning=dict(threads=64, lds_width=0))
-    for tun in (dict(threads=64, lds_width=64), dict(threads=128, lds_width=96), dict(threads=256, lds_width=240)):
+    # the last mapping runs the checkpointed forward in size buckets (wave packs, the
+    # wide-tree bucket on a second stream) while the recompute and reverse pass run every
+    # pack in the main mapping
+    for tun in (dict(threads=64, lds_width=64), dict(threads=128, lds_width=96), dict(threads=256, lds_width=240),
+                dict(threads=128, lds_width=24, wave_width=26, big_threads=256)):
         res = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=10, tuning=tun)
         assert res[0] == ref[0], tun  # the forward is bit-identical across mappings
         for x, y in zip(res[1:4], ref[1:4]):

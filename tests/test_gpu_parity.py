@@ -229,7 +229,13 @@ def test_renumbered_descriptor_is_bitwise_identical():
     dict(threads=128, pack_fill=1.0, lds_width=0), dict(threads=128, pack_fill=1.0, lds_width=48),
     dict(threads=256, pack_fill=1.0, lds_width=0, steps_per_launch=5),
     dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=50),
-    dict(threads=128, pack_fill=1.0, lds_width=128, pack_skew=1), dict(threads=64, pack_fill=2.0, lds_width=64, pack_skew=1)])
+    dict(threads=128, pack_fill=1.0, lds_width=128, pack_skew=1), dict(threads=64, pack_fill=2.0, lds_width=64, pack_skew=1),
+    # size buckets: wave packs for trees whose widest level fits a wavefront, the wide-tree
+    # bucket (packs of big_threads work-items on a second stream) for trees wider than lds_width
+    dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=50, wave_width=64),
+    dict(threads=128, pack_fill=1.0, lds_width=64, wave_width=32, big_threads=256, steps_per_launch=7),
+    dict(threads=64, pack_fill=1.0, lds_width=48, wave_width=24, big_threads=512),
+    dict(threads=256, pack_fill=1.0, lds_width=96, big_threads=512, pack_skew=1)])
 def test_mappings_are_bitwise_identical(tuning):
     # the mapping (workgroup per tree, exchange through LDS or global scratch) changes
     # which workgroup walks a tree and where levels hand data over, never the
@@ -239,6 +245,9 @@ def test_mappings_are_bitwise_identical(tuning):
     c = step_constants("uneven8192")
     ref = Model(b, c, dict(threads=128, pack_fill=0.0, lds_width=0))
     alt = Model(b, c, tuning)
+    # a bucket that is asked for is used by some trees of this batch
+    assert (alt.n_wave_packs > 0) == (tuning.get("wave_width", 0) > 0)
+    assert (alt.n_big_packs > 0) == (tuning.get("big_threads", 0) > tuning.get("lds_width", 128))
     out = []
     for m in (ref, alt):
         st = m.rest_state()

@@ -19,7 +19,11 @@ def _snapshot(m, st):
 
 @pytest.mark.parametrize("tuning", [dict(threads=128, pack_fill=1.0, lds_width=128),
                                     dict(threads=256, pack_fill=1.0, persistent=1, steps_per_launch=4),
-                                    dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=50)])
+                                    dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=50),
+                                    # wave packs beside workgroup packs, and the wide-tree bucket on
+                                    # its own stream joined inside the captured graph
+                                    dict(threads=128, pack_fill=1.0, lds_width=64, wave_width=32, big_threads=256,
+                                         steps_per_launch=10)])
 def test_graph_replays_equal_eager_steps(tuning):
     from paper_2607_06337_amd import Model
     b = make_batch("uneven8192", env_ids=range(48))
