@@ -693,6 +693,9 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   if (M->n_main < M->n_pack) {
     allow_lds(tun.big_threads == 512 ? (const void*)k_step_packs<512> : (const void*)k_step_packs<256>,
               (int)M->big_lds_bytes);
+    if (tun.adjoint_ckpt_max > 0)
+      allow_lds(tun.big_threads == 512 ? (const void*)k_adjoint_packs<512> : (const void*)k_adjoint_packs<256>,
+                (int)M->big_lds_bytes);
     if (hipStreamCreateWithFlags(&M->s_big, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&M->ev_big[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&M->ev_big[1], hipEventDisableTiming) != hipSuccess) {
@@ -830,18 +833,29 @@ int64_t orchard_ckpt_words(orchard_model_t m) {
   return 4LL * m->n_seg + (int64_t)m->apl * m->n_apple + m->n_seg + m->n_apple + m->n_seg + m->n_apple + m->n_env + 2;
 }
 
+// The adjoint's recompute and reverse pass take the wide-tree mapping when every pack is in
+// that bucket (a batch of wide trees only); with packs of both kinds they run the main one.
+static bool adj_big(orchard_model_t m) { return m->n_main == 0 && m->n_pack > 0; }
+
 static orchard_status_t launch_steps(orchard_model_t m, const DevModel& dm0, const DevState& ds, const DevInputs& di,
                                      int k, int s_call, hipStream_t stream, bool save = false, float* scr = nullptr) {
   const int NT = m->tun.threads;
   const unsigned lb = (unsigned)m->lds_bytes;
   if (save) {
-    // the adjoint's recompute runs every pack on a whole workgroup
+    // the adjoint's recompute runs every pack on a whole workgroup: in the wide-tree
+    // mapping when the batch has no other packs, otherwise in the main mapping (wide
+    // trees exchanging through global scratch)
     DevModel dm = dm0;
     dm.save_adj = 1;
     dm.n_wide = dm.n_pack;
     if (scr) dm.scr = scr;
     const dim3 g(m->n_pack);
-    switch (NT) {
+    if (adj_big(m)) {
+      dm.lds_cap = m->tun.big_threads;
+      const unsigned lbb = (unsigned)m->big_lds_bytes;
+      if (m->tun.big_threads == 512) hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), lbb, stream, dm, ds, di, k, s_call);
+      else hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lbb, stream, dm, ds, di, k, s_call);
+    } else switch (NT) {
       case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, stream, dm, ds, di, k, s_call); break;
       case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), lb, stream, dm, ds, di, k, s_call); break;
       case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lb, stream, dm, ds, di, k, s_call); break;
@@ -1104,7 +1118,14 @@ orchard_status_t orchard_step_backward(orchard_model_t m, const float* ckpt, int
       dm.scr = rep(s, j);
       const float* rec = (const float*)rec_at(s, j);
       const dim3 g(m->n_pack);
-      switch (NT) {
+      if (adj_big(m)) {
+        dm.lds_cap = m->tun.big_threads;
+        const unsigned lbb = (unsigned)m->big_lds_bytes;
+        if (m->tun.big_threads == 512)
+          hipLaunchKernelGGL(k_adjoint_packs<512>, g, dim3(512), lbb, st, dm, W, rec, di, X, n0 + j);
+        else
+          hipLaunchKernelGGL(k_adjoint_packs<256>, g, dim3(256), lbb, st, dm, W, rec, di, X, n0 + j);
+      } else switch (NT) {
         case 64: hipLaunchKernelGGL(k_adjoint_packs<64>, g, dim3(64), lb, st, dm, W, rec, di, X, n0 + j); break;
         case 128: hipLaunchKernelGGL(k_adjoint_packs<128>, g, dim3(128), lb, st, dm, W, rec, di, X, n0 + j); break;
         case 256: hipLaunchKernelGGL(k_adjoint_packs<256>, g, dim3(256), lb, st, dm, W, rec, di, X, n0 + j); break;

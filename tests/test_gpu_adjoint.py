@@ -170,6 +170,24 @@ def test_gradients_are_bitwise_identical_across_mappings():
             assert np.array_equal(x, y), (tun, _rel(x, y))
 
 
+def test_wide_tree_bucket_gradients_are_bitwise_identical():
+    # two 5000-segment trees (levels of up to ~420 nodes): the main mapping exchanges their
+    # levels through global scratch; with big_threads = 512 the forward, the recompute and
+    # the reverse pass run them as 512-wide LDS packs
+    from orchard_inputs import make_trees
+    Tl = 40
+    batch = assemble(make_trees("row64x16k", env_ids=[5, 9]))
+    consts = step_constants()
+    rng = np.random.default_rng(22)
+    F = rng.normal(0, 2, (Tl, batch.n_apple, 3))
+    tip_idx, target = grad_targets(batch, _rest_tips(batch))
+    ref = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=20, T=Tl, tuning=dict(lds_width=128))
+    big = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=20, T=Tl, tuning=dict(lds_width=128, big_threads=512))
+    assert big[0] == ref[0]
+    for x, y in zip(big[1:4], ref[1:4]):
+        assert np.array_equal(x, y), _rel(x, y)
+
+
 def test_large_tree_adjoint_matches_fp64_central_differences():
     # a 5000-segment tree of the orchard-row batch (wide levels: global exchange), 60 steps
     # with checkpoints every 20, directional derivatives against FP64 central differences
