@@ -335,6 +335,8 @@ def main():
                     help="kernel mapping as JSON (skips the autotuner), e.g. the one a profile was taken with")
     ap.add_argument("--row-scale-only", action="store_true",
                     help="run only the orchard-row phases and print their figures (for per-phase counters)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint/forward leg (differentiable-rollout batch) and print it (for its profile)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB read + 256 MiB write kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -349,6 +351,12 @@ def main():
         if args.copy_probe:
             _copy_probe()
         print(json.dumps(dict(sphere_fit=sphere_fit_leg())), flush=True)
+        return
+
+    if args.adjoint_only:
+        import torch
+        torch.cuda.init()
+        print(json.dumps(dict(adjoint=adjoint_ratio())), flush=True)
         return
 
     if args.row_scale_only:

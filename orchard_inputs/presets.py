@@ -69,7 +69,9 @@ def make_trees(name: str, env_ids=None, workers: int | None = None) -> list[Tree
         env_ids = range(n_trees(name))
     jobs = [_sizes(name, int(e)) for e in env_ids]
     if workers is None:
-        workers = min(8, os.cpu_count() or 1)
+        # ORCHARD_GEN_WORKERS=1 generates in this process (e.g. under a profiler whose
+        # signal handlers a fork server's workers cannot inherit)
+        workers = int(os.environ.get("ORCHARD_GEN_WORKERS", min(8, os.cpu_count() or 1)))
     # the fork server re-imports the main script in its workers: without one (an
     # interactive session, a script on stdin) the trees are generated here
     main_file = getattr(sys.modules.get("__main__"), "__file__", None)

@@ -12,7 +12,7 @@ def test_comments_do_not_change_the_kernel_hash():
 
 
 def test_profile_lookup_matches_tuning_exactly():
-    t = dict(bench.BENCH_TUNING, pack_skew=0)
+    t = {k: dict(bench.BENCH_TUNING, pack_skew=0, wave_width=0)[k] for k in bench.TUNING_KEYS}
     found = bench.profiled_counters("k_step_packs", t)
     other = bench.profiled_counters("k_step_packs", dict(t, lds_width=t["lds_width"] - 16))
     assert other is None
