@@ -56,7 +56,8 @@ def test_create_rejects_invalid_descriptions():
 def test_create_rejects_invalid_mappings():
     from paper_2607_06337_amd import Model, OrchardError
     b = assemble([gen_tree(1, 20, 3)])
-    for tun in (dict(threads=96), dict(lds_width=-1), dict(threads=64, lds_width=65), dict(adjoint_ckpt_max=-2)):
+    for tun in (dict(threads=96), dict(lds_width=-1), dict(threads=64, lds_width=65), dict(adjoint_ckpt_max=-2),
+                dict(wave_width=65), dict(wave_width=-1), dict(big_threads=300), dict(big_threads=1024)):
         with pytest.raises(OrchardError) as ei:
             Model(b, step_constants(), tun)
         assert ei.value.code == 1, (tun, str(ei.value))
