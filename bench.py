@@ -152,10 +152,11 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(batch, consts, n_envs=512, n_steps=200, n_envs_1=64, n_steps_1=100):
+def cpu_baseline(batch, consts, n_envs=512, n_steps=200, n_envs_1=64, n_steps_1=100, pull_steps=100):
     """FP64 oracle on size-stratified samples of the same workload: all cores of the
-    process's CPU share (at most 16, the share of one GPU on the box) on n_envs trees x
-    n_steps steps, and one core on n_envs_1 trees x n_steps_1 steps."""
+    process's CPU share on n_envs trees x n_steps steps, and one core on n_envs_1 trees x
+    n_steps_1 steps; beside them, all 1024 trees of the pull workload (100-400 segments)
+    x pull_steps steps on all cores."""
     from oracle.oracle import Oracle
     from orchard_inputs import assemble
 
@@ -178,14 +179,24 @@ def cpu_baseline(batch, consts, n_envs=512, n_steps=200, n_envs_1=64, n_steps_1=
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = os.cpu_count() or 1
-    threads = max(1, min(16, avail))
+    threads = max(1, avail)
     v_all, dt_all, n_all, seg_all = run(n_envs, n_steps, threads)
     v_one, dt_one, n_one, seg_one = run(n_envs_1, n_steps_1, 1)
+    from orchard_inputs import make_batch, step_constants
+    pb = make_batch("pull1024")
+    o = Oracle(pb, step_constants("pull1024"))
+    st = o.rest_state()
+    t0 = time.perf_counter()
+    o.rollout(st, pull_steps, threads=threads)
+    dt_pull = time.perf_counter() - t0
     return dict(value=v_all, unit="env-steps/s", cores=threads, kind="oracle",
                 sample=f"{n_all} size-stratified trees of the workload ({seg_all} segments) x {n_steps} steps, FP64, "
                        f"{dt_all:.1f} s on {threads} threads",
                 single_core=dict(value=v_one, sample=f"{n_one} size-stratified trees ({seg_one} segments) x "
                                                      f"{n_steps_1} steps, {dt_one:.1f} s on 1 thread"),
+                pull1024=dict(value=pb.n_env * pull_steps / dt_pull,
+                              sample=f"all {pb.n_env} trees of the pull workload ({pb.n_seg} segments) x {pull_steps} "
+                                     f"steps, {dt_pull:.1f} s on {threads} threads"),
                 nproc=os.cpu_count(), affinity=avail, cpu_model=_cpu_model())
 
 
