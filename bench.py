@@ -142,6 +142,15 @@ def time_gpu(model, n_steps, warmup, graph_steps=0, repeats=1):
     return ms, wall, int((status != 0).sum()), st, what, n_launch, runs
 
 
+def event_counts(model, st):
+    """Breaks and detachments recorded in a state (event kinds 1: break, 2: pull detach,
+    3: tension detach), with the fraction of joints broken."""
+    ev = model.events(st)
+    kinds = np.bincount(np.array([k for (_, k, _, _) in ev], dtype=np.int64), minlength=4) if ev else np.zeros(4, int)
+    return dict(breaks=int(kinds[1]), break_fraction=round(int(kinds[1]) / model.n_seg, 6),
+                pull_detachments=int(kinds[2]), tension_detachments=int(kinds[3]))
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -412,7 +421,10 @@ def main():
     model = Model(batch, consts, tuning)
     # the first timed rollout is the reported one; four more of the same length (continuing
     # from its state) give the median beside it
-    ms, wall, n_bad, _, what, n_launch, runs = time_gpu(model, args.steps, args.warmup, GRAPH_STEPS, repeats=5)
+    ms, wall, n_bad, st_end, what, n_launch, runs = time_gpu(model, args.steps, args.warmup, GRAPH_STEPS, repeats=5)
+    # events of the whole rollout (warmup plus the five timed rollouts)
+    events = dict(event_counts(model, st_end), steps=args.warmup + 5 * args.steps)
+    del st_end
     print(f"# optimized: {args.steps} steps in {ms:.1f} ms ({wall:.2f} s wall), packs={model.n_pack}", file=sys.stderr,
           flush=True)
     plain = None
@@ -478,7 +490,7 @@ def main():
                            n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=tuning,
                            rollout=what, autotune=tune_log),
                repeat_ms=[round(x, 3) for x in runs], median_ms_per_step=round(float(np.median(runs)) / args.steps, 5),
-               adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
+               events=events, adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
                roofline=roof, cpu_baseline=cpu, row_scale=rows, sphere_fit=sph)
     print(json.dumps(out), flush=True)
 
