@@ -127,10 +127,12 @@ typedef struct {
  * workgroup.  big_threads (0, 256 or 512; used when it exceeds lds_width, ignored with
  * persistent = 1): the wide-tree bucket; a tree whose widest level exceeds lds_width but
  * not big_threads goes to a pack of big_threads work-items with an LDS exchange of
- * big_threads slots, launched on a second stream of the model's (default priority)
- * concurrently with the other packs, instead of exchanging through global scratch.  The
- * adjoint's recompute and reverse pass run every pack in the main mapping.  No mapping
- * choice changes any result bit. */
+ * big_threads slots instead of exchanging through global scratch; its launch goes on the
+ * caller's stream and the other packs' launch on a second stream of the model's (default
+ * priority), concurrently, both joined to the caller's stream before orchard_step's work
+ * there ends.  The adjoint's recompute and reverse pass run these packs in the wide-tree
+ * mapping when every pack of the model is in the bucket, otherwise every pack in the main
+ * mapping.  No mapping choice changes any result bit. */
 typedef struct {
   int32_t threads;
   float pack_fill;

@@ -870,12 +870,15 @@ static orchard_status_t launch_steps(orchard_model_t m, const DevModel& dm0, con
       default: hipLaunchKernelGGL(k_step_persistent<512>, g, dim3(512), lb, stream, dm0, ds, di, k, s_call, dm0.queue); break;
     }
   } else {
-    // the wide-tree bucket (packs [n_main, n_pack)) runs on its own stream, concurrently
-    // with the main launch; both join before the step counter advances
+    // the wide-tree bucket (packs [n_main, n_pack)) and the main packs run concurrently:
+    // the wide-tree launch goes first on the caller's stream, so that its workgroups (most
+    // of a CU's LDS each) find free CUs, and the main launch on the model's second stream;
+    // both join before the step counter advances
     const bool big = m->n_main < m->n_pack;
+    hipStream_t s_main = stream;
     if (big) {
+      s_main = m->s_big;
       HIPCHK(hipEventRecord(m->ev_big[0], stream));
-      HIPCHK(hipStreamWaitEvent(m->s_big, m->ev_big[0], 0));
       DevModel db = dm0;
       db.pack_base = m->n_main;
       db.n_wide = db.n_pack;
@@ -883,23 +886,24 @@ static orchard_status_t launch_steps(orchard_model_t m, const DevModel& dm0, con
       const dim3 gb(m->n_pack - m->n_main);
       const unsigned lbb = (unsigned)m->big_lds_bytes;
       if (m->tun.big_threads == 512)
-        hipLaunchKernelGGL(k_step_packs<512>, gb, dim3(512), lbb, m->s_big, db, ds, di, k, s_call);
+        hipLaunchKernelGGL(k_step_packs<512>, gb, dim3(512), lbb, stream, db, ds, di, k, s_call);
       else
-        hipLaunchKernelGGL(k_step_packs<256>, gb, dim3(256), lbb, m->s_big, db, ds, di, k, s_call);
+        hipLaunchKernelGGL(k_step_packs<256>, gb, dim3(256), lbb, stream, db, ds, di, k, s_call);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipEventRecord(m->ev_big[1], m->s_big));
+      HIPCHK(hipStreamWaitEvent(s_main, m->ev_big[0], 0));
     }
     if (m->n_main > 0) {
       DevModel dmm = dm0;
       dmm.n_pack = m->n_main;
       const dim3 g(m->n_wide + (m->n_main - m->n_wide + NT / 64 - 1) / (NT / 64));
       switch (NT) {
-        case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, stream, dmm, ds, di, k, s_call); break;
-        case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), lb, stream, dmm, ds, di, k, s_call); break;
-        case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lb, stream, dmm, ds, di, k, s_call); break;
-        default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), lb, stream, dmm, ds, di, k, s_call); break;
+        case 64: hipLaunchKernelGGL(k_step_packs<64>, g, dim3(64), lb, s_main, dmm, ds, di, k, s_call); break;
+        case 128: hipLaunchKernelGGL(k_step_packs<128>, g, dim3(128), lb, s_main, dmm, ds, di, k, s_call); break;
+        case 256: hipLaunchKernelGGL(k_step_packs<256>, g, dim3(256), lb, s_main, dmm, ds, di, k, s_call); break;
+        default: hipLaunchKernelGGL(k_step_packs<512>, g, dim3(512), lb, s_main, dmm, ds, di, k, s_call); break;
       }
     }
+    if (big) HIPCHK(hipEventRecord(m->ev_big[1], s_main));
     if (big) HIPCHK(hipStreamWaitEvent(stream, m->ev_big[1], 0));
   }
   HIPCHK(hipGetLastError());
