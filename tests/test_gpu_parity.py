@@ -142,7 +142,8 @@ def test_breaking_limbs_and_free_hinges():
 
 def test_row_scale_batch_one_launch():
     # the orchard-row batch in one launch: 64 trees of 5000 segments next to 16384 of 80
-    # (wide levels that take the global exchange next to LDS packs); the oracle follows
+    # (the large trees, 310-420 nodes on their widest levels, in the wide-tree bucket beside
+    # the small trees' LDS packs); the oracle follows
     # 8 large and 64 small trees over 300 steps with breakage enabled
     from bench import BENCH_TUNING
     b = make_batch("row64x16k")
