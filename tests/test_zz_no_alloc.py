@@ -26,7 +26,10 @@ def _run(batch, consts, tuning, n_steps, static):
 
 
 @pytest.mark.parametrize("tuning", [dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=25),
-                                    dict(threads=128, pack_fill=1.0, lds_width=0, persistent=1, steps_per_launch=7)])
+                                    dict(threads=128, pack_fill=1.0, lds_width=0, persistent=1, steps_per_launch=7),
+                                    # size buckets: wave packs and the wide-tree bucket's launch
+                                    dict(threads=128, pack_fill=1.0, lds_width=64, wave_width=32, big_threads=256,
+                                         steps_per_launch=10)])
 def test_static_scratch_step_equals_step(tuning):
     c = step_constants(rng_seed=3_000_000, wrench_fraction=0.05)
     big = make_batch("uneven8192", env_ids=range(200))      # ~85 K segments
