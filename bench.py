@@ -325,6 +325,26 @@ def sphere_fit_leg(n_patch: int = 65536, reps: int = 20, cpu_patches: int = 2000
                                   sample=f"{len(pick)} patches of the workload, FP64 least squares, {cpu_s:.1f} s"))
 
 
+def copy_bandwidth(n_bytes: int = 1 << 30, reps: int = 5) -> float:
+    """Measured device-to-device copy rate (GB/s, bytes read plus written) of a plain
+    tensor copy: the practical HBM ceiling beside the 8 TB/s datasheet figure."""
+    import torch
+    x = torch.empty(n_bytes // 4, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n_bytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del x, y
+    return gbs
+
+
 def _copy_probe():
     """Three launches of one plain elementwise kernel (256 MiB read, 256 MiB written): the
     reference that scales the HBM counters."""
@@ -451,10 +471,15 @@ def main():
     traffic = None
     if prof and prof.get("hbm_bytes_per_launch"):
         traffic = int(prof["hbm_bytes_per_launch"] / prof["tuning"]["steps_per_launch"] * steps_per_launch)
+    copy_gbs = copy_bandwidth()
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                copy_peak_GBps=round(copy_gbs, 1), frac_of_copy_peak=round(achieved / copy_gbs, 4),
                 kernel="k_step_packs", bytes_per_launch=int(per_launch_bytes),
                 launch_us=round(launch_ms * 1e3, 2), launches_timed=n_launch)
+    if traffic:
+        # measured HBM bytes of the profiled launches over this run's launch time
+        roof["traffic_GBps"] = round(traffic / (launch_ms / 1e3) / 1e9, 1)
     if prof and prof.get("valu_insts_per_step"):
         # issue-rate ceiling of the vector ALUs: 1024 SIMDs, one wave64 VALU instruction
         # per 4 cycles at 2.4 GHz; FP32 lane operations (FMA = 2) against 78.6 TFLOP/s
