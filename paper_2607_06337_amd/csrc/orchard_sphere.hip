@@ -30,6 +30,55 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wave sums of N values at once (reduce-scatter): at the stage of mask m a lane keeps the
+// first half of its current list when lane & m is 0 and the second half otherwise, and
+// receives its partner's copy of the half it keeps, so the lists halve while one shuffle
+// per kept value crosses lanes; once a single value is left, the last stages are plain
+// butterflies.  15 shuffles sum 13 values instead of 6 per value.  Lane l ends holding the
+// sum whose index follows from its bits (sum_src gives the lane of each index); every
+// lane then reads each sum from that lane, so all lanes hold the same bits.
+template <int C, int M>
+__device__ __forceinline__ void rs_stage(double* v, int lane) {
+  if constexpr (C > 1) {
+    constexpr int H = (C + 1) / 2;
+    const bool up = (lane & M) != 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const double lo = v[k], hi = H + k < C ? v[H + k] : 0.0;
+      const double got = __shfl_xor(up ? lo : hi, M, 64);
+      v[k] = (up ? hi : lo) + got;
+    }
+    rs_stage<H, M / 2>(v, lane);
+  } else if constexpr (M >= 1) {
+    v[0] += __shfl_xor(v[0], M, 64);
+    rs_stage<1, M / 2>(v, lane);
+  }
+}
+// lane holding the sum of index k after rs_stage<C, 32>
+template <int C, int M>
+__host__ __device__ constexpr int sum_src(int k) {
+  if constexpr (C > 1) {
+    constexpr int H = (C + 1) / 2;
+    return k < H ? sum_src<H, M / 2>(k) : M + sum_src<H, M / 2>(k - H);
+  } else {
+    return 0;
+  }
+}
+__device__ __forceinline__ double read_lane(double v, int src) {
+  const int2 w = *reinterpret_cast<const int2*>(&v);
+  const int2 r = make_int2(__builtin_amdgcn_readlane(w.x, src), __builtin_amdgcn_readlane(w.y, src));
+  return *reinterpret_cast<const double*>(&r);
+}
+template <int N>
+__device__ __forceinline__ void wave_sums(double (&v)[N], int lane) {
+  double t[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) t[k] = v[k];
+  rs_stage<N, 32>(t, lane);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = read_lane(t[0], sum_src<N, 32>(k));
+}
+
 // Points are read in chunks of 64 x KP: each lane issues all KP loads of a chunk before it
 // uses any, and a patch that fits one chunk is read from memory once, its second pass
 // working from registers.
@@ -74,10 +123,12 @@ __device__ __forceinline__ void fit_patch(const float* __restrict__ pts, int b, 
       ww += w;
     }
   }
-  sx = wave_sum(sx); sy = wave_sum(sy); sz = wave_sum(sz);
-  qxx = wave_sum(qxx); qxy = wave_sum(qxy); qxz = wave_sum(qxz);
-  qyy = wave_sum(qyy); qyz = wave_sum(qyz); qzz = wave_sum(qzz);
-  wx = wave_sum(wx); wy = wave_sum(wy); wz = wave_sum(wz); ww = wave_sum(ww);
+  {
+    double v[13] = {sx, sy, sz, qxx, qxy, qxz, qyy, qyz, qzz, wx, wy, wz, ww};
+    wave_sums(v, lane);
+    sx = v[0]; sy = v[1]; sz = v[2]; qxx = v[3]; qxy = v[4]; qxz = v[5];
+    qyy = v[6]; qyz = v[7]; qzz = v[8]; wx = v[9]; wy = v[10]; wz = v[11]; ww = v[12];
+  }
   // central moments of u = q - m, m the mean: C = S_qq - n m m^T,
   // sum |u|^2 u = S_wq - m S_w - 2 S_qq m + 2 n |m|^2 m, sum |u|^2 = S_w - n |m|^2
   const double nd = (double)n, inv_n = 1.0 / nd;
@@ -97,22 +148,23 @@ __device__ __forceinline__ void fit_patch(const float* __restrict__ pts, int b, 
   const double eps = 1e-9 * tr;
   const double l11sq = cxx;
   bool ok = l11sq > eps;
-  const double l11 = sqrt(fmax(l11sq, 0.0));
-  const double l21 = ok ? cxy / l11 : 0.0, l31 = ok ? cxz / l11 : 0.0;
+  // (the diagonal of L is inverted once; the substitutions multiply by the inverses)
+  const double i11 = ok ? 1.0 / sqrt(l11sq) : 0.0;
+  const double l21 = cxy * i11, l31 = cxz * i11;
   const double l22sq = cyy - l21 * l21;
   ok = ok && l22sq > eps;
-  const double l22 = sqrt(fmax(l22sq, 0.0));
-  const double l32 = ok ? (cyz - l31 * l21) / l22 : 0.0;
+  const double i22 = ok ? 1.0 / sqrt(l22sq) : 0.0;
+  const double l32 = (cyz - l31 * l21) * i22;
   const double l33sq = czz - l31 * l31 - l32 * l32;
   ok = ok && l33sq > eps;
   if (!ok) {
     res[6] = 2.f;  // degenerate: the points span no volume (a plane or a line)
     return;
   }
-  const double l33 = sqrt(l33sq);
+  const double i33 = 1.0 / sqrt(l33sq);
   const double r1 = 0.5 * uwx, r2 = 0.5 * uwy, r3 = 0.5 * uwz;
-  const double y1 = r1 / l11, y2 = (r2 - l21 * y1) / l22, y3 = (r3 - l31 * y1 - l32 * y2) / l33;
-  const double cz = y3 / l33, cy = (y2 - l32 * cz) / l22, cx = (y1 - l21 * cy - l31 * cz) / l11;
+  const double y1 = r1 * i11, y2 = (r2 - l21 * y1) * i22, y3 = (r3 - l31 * y1 - l32 * y2) * i33;
+  const double cz = y3 * i33, cy = (y2 - l32 * cz) * i22, cx = (y1 - l21 * cy - l31 * cz) * i11;
   const double R2 = fmax(fma(uww, inv_n, fma(cx, cx, fma(cy, cy, cz * cz))), 0.0);
   const double R = sqrt(R2);
   // pass 2: RMS of the geometric residual |q - (m + c')| - R
