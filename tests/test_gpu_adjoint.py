@@ -189,29 +189,37 @@ def test_wide_tree_bucket_gradients_are_bitwise_identical():
 
 
 def test_large_tree_adjoint_matches_fp64_central_differences():
-    # a 5000-segment tree of the orchard-row batch (wide levels: global exchange), 60 steps
-    # with checkpoints every 20, directional derivatives against FP64 central differences
+    # two 5000-segment trees of the orchard-row batch (wide levels: global exchange in the
+    # main mapping), 60 steps with checkpoints every 20, directional derivatives of each
+    # tree's loss against FP64 central differences
     from orchard_inputs import make_trees
     Tl = 60
-    batch = assemble(make_trees("row64x16k", env_ids=[5]))
+    batch = assemble(make_trees("row64x16k", env_ids=[5, 37]))
     consts = step_constants()
     rng = np.random.default_rng(21)
     F = rng.normal(0, 2, (Tl, batch.n_apple, 3))
     tip_idx, target = grad_targets(batch, _rest_tips(batch))
     L, gkp, gkd, gF, kpd, kdd = _gpu_gradients(batch, consts, F, tip_idx, target, ckpt_every=20, T=Tl)
     o = Oracle(batch, consts)
-    x0 = env_state0(o, o.rest_state(), 0)
-    rec = Record()
-    Lo = loss(o, 0, x0, kpd, kdd, F, Tl, tip_idx[0], target[0], record_out=rec)
-    assert abs(L - Lo) <= 1e-4 * abs(Lo), (L, Lo)
-    f = lambda kp_, kd_, F_: loss(o, 0, x0, kp_, kd_, F_, Tl, tip_idx[0], target[0], record_in=rec)
-    for _ in range(3):
-        dkp, dkd, dF = rng.normal(size=kpd.size) * kpd, rng.normal(size=kdd.size) * kdd, rng.normal(size=F.shape)
-        ep = 1e-5
-        fd = (f(kpd + ep * dkp, kdd + ep * dkd, F + ep * dF) - f(kpd - ep * dkp, kdd - ep * dkd, F - ep * dF)) / (2 * ep)
-        an = gkp @ dkp + gkd @ dkd + np.sum(gF * dF)
-        print(f"large tree: fd {fd:.6e} adjoint {an:.6e}", flush=True)
-        assert abs(fd - an) <= TOL * max(abs(an), 1e-12), (fd, an)
+    st0 = o.rest_state()
+    Lsum = 0.0
+    for e in range(batch.n_env):
+        s0, s1 = batch.seg_offset[e], batch.seg_offset[e + 1]
+        a0, a1 = batch.apple_offset[e], batch.apple_offset[e + 1]
+        kp, kd, Fe = kpd[s0:s1], kdd[s0:s1], F[:, a0:a1].copy()
+        x0 = env_state0(o, st0, e)
+        rec = Record()
+        Lsum += loss(o, e, x0, kp, kd, Fe, Tl, tip_idx[e], target[e], record_out=rec)
+        f = lambda kp_, kd_, F_: loss(o, e, x0, kp_, kd_, F_, Tl, tip_idx[e], target[e], record_in=rec)
+        g_kp, g_kd, g_F = gkp[s0:s1], gkd[s0:s1], gF[:, a0:a1]
+        for _ in range(3):
+            dkp, dkd, dF = rng.normal(size=kp.size) * kp, rng.normal(size=kd.size) * kd, rng.normal(size=Fe.shape)
+            ep = 1e-5
+            fd = (f(kp + ep * dkp, kd + ep * dkd, Fe + ep * dF) - f(kp - ep * dkp, kd - ep * dkd, Fe - ep * dF)) / (2 * ep)
+            an = g_kp @ dkp + g_kd @ dkd + np.sum(g_F * dF)
+            print(f"large tree {e}: fd {fd:.6e} adjoint {an:.6e}", flush=True)
+            assert abs(fd - an) <= TOL * max(abs(an), 1e-12), (e, fd, an)
+    assert abs(L - Lsum) <= 1e-4 * abs(Lsum), (L, Lsum)
 
 
 def test_adjoint_through_every_switch():
