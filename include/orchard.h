@@ -108,6 +108,11 @@ typedef struct {
                                 /*   full at this speed to none at twice it          */
   double brake_rate;            /* speed brake: -rate m (|v| - v_cap) v/|v| on a body */
                                 /*   with an applied force above v_cap (1/s)         */
+  double event_band;            /* >= 0: orchard_events marks an event whose ratio    */
+                                /*   lies within event_band of 1 (its threshold) as  */
+                                /*   in band: FP32 rounding of the state can move    */
+                                /*   such an event by a step (Eq. break, Sec. "Fruit"); */
+                                /*   0 = none marked                                  */
 } orchard_model_desc_t;
 
 /* Kernel mapping choices (nullable in create: defaults {128, 1.0, 1, 0, 0, 128, 0}).
@@ -177,6 +182,12 @@ typedef struct {
                        /*   the next step on; bit 1: an apple state was among the    */
                        /*   non-finite values (with bit 0)          */
   int64_t* step;       /* device scalar: index of the next step (event stamps, RNG)    */
+  float* evt_ratio;    /* [n_seg + n_apple] threshold ratio on the step of the event:  */
+                       /*   mu = Kp |theta| / M_max for a break (Eq. break), pi =     */
+                       /*   |F| / f_det for a pull detach, tau = k_s |s| / (alpha     */
+                       /*   f_det) for a tension detach (Sec. "Fruit"); written only  */
+                       /*   on that step (orchard_state_rest zeroes it); not part of  */
+                       /*   checkpoint records.  Nullable: no ratios recorded         */
 } orchard_state_t;
 
 typedef struct {
@@ -192,10 +203,12 @@ typedef struct {
 } orchard_inputs_t;
 
 typedef struct {
-  int32_t env;   /* descriptor env index                                  */
-  int32_t kind;  /* 1 break, 2 detach by pull, 3 detach by stem tension   */
-  int32_t id;    /* env-local descriptor segment / apple index            */
+  int32_t env;     /* descriptor env index                                  */
+  int32_t kind;    /* 1 break, 2 detach by pull, 3 detach by stem tension   */
+  int32_t id;      /* env-local descriptor segment / apple index            */
   int32_t step;
+  float ratio;     /* state.evt_ratio of the event (0 if the state has none) */
+  int32_t in_band; /* 1 if |ratio - 1| < the model's event_band            */
 } orchard_event_t;
 
 /* Build a model: validates the description (synchronously), derives masses,

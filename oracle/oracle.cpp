@@ -304,6 +304,8 @@ struct EventRefs {  // per-env views of the event state arrays
   uint8_t *broken, *cnt, *det, *cntp, *cntt, *det_path;
   int32_t *break_step, *det_step;
   uint32_t* status;
+  double* break_ratio = nullptr;  // mu on the step a joint breaks (nullable)
+  double* det_ratio = nullptr;    // pi (pull) or tau (tension) on the step an apple detaches
 };
 
 struct BandRefs {  // min |ratio-1| and first in-band step, per joint / apple (nullable)
@@ -372,7 +374,10 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
       }
       int c = mu > 1.0 ? ev->cnt[i] + 1 : 0;
       ev->cnt[i] = (uint8_t)std::min(c, 255);
-      if (c >= g.n_break) { broken[i] = 1; ev->broken[i] = 1; ev->break_step[i] = (int32_t)n; }
+      if (c >= g.n_break) {
+        broken[i] = 1; ev->broken[i] = 1; ev->break_step[i] = (int32_t)n;
+        if (ev->break_ratio) ev->break_ratio[i] = mu;
+      }
     }
     for (int a = 0; a < A; ++a) {
       if (det[a]) continue;
@@ -394,7 +399,10 @@ void step_tree(const Tree& t, const Globals& g, int env, int64_t n,
       ev->cntp[a] = (uint8_t)std::min(cp, 255);
       ev->cntt[a] = (uint8_t)std::min(ct, 255);
       int path = cp >= g.n_pull ? 1 : (ct >= g.n_tension ? 2 : 0);  // pull wins ties
-      if (path) { det[a] = 1; ev->det[a] = 1; ev->det_step[a] = (int32_t)n; ev->det_path[a] = (uint8_t)path; }
+      if (path) {
+        det[a] = 1; ev->det[a] = 1; ev->det_step[a] = (int32_t)n; ev->det_path[a] = (uint8_t)path;
+        if (ev->det_ratio) ev->det_ratio[a] = path == 1 ? pi : tau;
+      }
     }
   }
   // --- snapped mask (root to leaf) ---
@@ -593,6 +601,7 @@ struct OracleIO {
   int64_t aforce_stride;          // doubles between steps; 0 = constant
   double *band_jmin, *band_amin;  // nullable
   int32_t *band_jfirst, *band_afirst;
+  double *break_ratio, *det_ratio;  // [S_tot], [A_tot]: threshold ratio at the event; nullable
 };
 
 void* oracle_create(const OracleDesc* d, const Globals* g) {
@@ -735,7 +744,8 @@ int oracle_rollout(void* m, const OracleIO* io, int n_sel, const int32_t* env_li
       const int S = t.S, A = t.A, s0 = t.seg0, a0 = t.app0;
       std::vector<double> qn(2 * S), qdn(2 * S), axn(3 * A), avn(3 * A), aqn(4 * A), awn(3 * A);
       EventRefs ev{io->broken + s0, io->cnt + s0, io->det + a0, io->cntp + a0, io->cntt + a0,
-                   io->det_path + a0, io->break_step + s0, io->det_step + a0, io->status + e};
+                   io->det_path + a0, io->break_step + s0, io->det_step + a0, io->status + e,
+                   io->break_ratio ? io->break_ratio + s0 : nullptr, io->det_ratio ? io->det_ratio + a0 : nullptr};
       BandRefs band{io->band_jmin ? io->band_jmin + s0 : nullptr, io->band_amin ? io->band_amin + a0 : nullptr,
                     io->band_jfirst ? io->band_jfirst + s0 : nullptr, io->band_afirst ? io->band_afirst + a0 : nullptr};
       double *q = io->q + 2 * s0, *qd = io->qd + 2 * s0, *ax = io->ax + 3 * a0, *av = io->av + 3 * a0,

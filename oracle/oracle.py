@@ -62,7 +62,7 @@ class IO(C.Structure):
                                   "cntt", "det_path", "break_step", "det_step", "status", "kp", "kd",
                                   "wrench")] + [("wrench_stride", C.c_int64), ("aforce", _P),
                                                 ("aforce_stride", C.c_int64)] + \
-        [(n, _P) for n in ("band_jmin", "band_amin", "band_jfirst", "band_afirst")]
+        [(n, _P) for n in ("band_jmin", "band_amin", "band_jfirst", "band_afirst", "break_ratio", "det_ratio")]
 
 
 def _ptr(a):
@@ -117,6 +117,8 @@ class State:
     break_step: np.ndarray
     det_step: np.ndarray
     status: np.ndarray
+    break_ratio: np.ndarray  # mu on the step the joint broke (0 before)
+    det_ratio: np.ndarray    # pi (pull) or tau (tension) on the step the apple detached
     step: int = 0
 
     def copy(self) -> "State":
@@ -254,13 +256,13 @@ class Oracle:
                      cnt=np.zeros(S, np.uint8), det=np.zeros(A, np.uint8), cntp=np.zeros(A, np.uint8),
                      cntt=np.zeros(A, np.uint8), det_path=np.zeros(A, np.uint8),
                      break_step=np.full(S, -1, np.int32), det_step=np.full(A, -1, np.int32),
-                     status=np.zeros(B, np.uint32))
+                     status=np.zeros(B, np.uint32), break_ratio=np.zeros(S), det_ratio=np.zeros(A))
 
     def _io(self, st: State, kp=None, kd=None, wrench=None, wrench_stride=0, aforce=None, aforce_stride=0,
             band: Band | None = None):
         io = IO()
         for f in ("q", "qd", "ax", "av", "aq", "aw", "broken", "cnt", "det", "cntp", "cntt", "det_path",
-                  "break_step", "det_step", "status"):
+                  "break_step", "det_step", "status", "break_ratio", "det_ratio"):
             setattr(io, f, _ptr(getattr(st, f)))
         io.kp = _ptr(kp)
         io.kd = _ptr(kd)

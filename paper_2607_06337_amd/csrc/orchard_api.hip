@@ -80,6 +80,7 @@ struct orchard_model_s {
   std::vector<int32_t> env_seg_off, env_apple_off;    // descriptor offsets
   std::vector<int32_t> node_env_h, apple_env_h;
   std::vector<double> apple_hang_rest;                // [n_apple][3] rest hang points
+  double event_band = 0;                              // |ratio - 1| below which an event is in band
   void* arena = nullptr;
   float* scr = nullptr;
   size_t an_bytes = 0;                                // dense apple-node arrays after the scratch blocks
@@ -193,6 +194,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
       d->friction_ramp_time < 0 || d->friction_speed < 0 || d->fade_speed < 0 || d->brake_rate < 0 ||
       (d->friction_base > 0 && !(d->friction_speed > 0)))
     return fail(ORCHARD_ERR_INVALID_ARG, "extra out of range (all >= 0; friction needs friction_speed > 0)");
+  if (!(d->event_band >= 0) || !std::isfinite(d->event_band))
+    return fail(ORCHARD_ERR_INVALID_ARG, "event_band must be finite and >= 0");
   orchard_tuning_t tun{128, 1.0f, 1, 0, 0, 128, 0, 0, 0};
   if (tuning) tun = *tuning;
   if (tun.lds_width < 0 || tun.lds_width > tun.threads)
@@ -561,6 +564,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   M->node_env_h = env_i;
   M->apple_env_h = apple_env;
   M->apple_hang_rest = ahang_rest;
+  M->event_band = d->event_band;
   const int32_t zero = 0;
   Arena ar;
   size_t o_pn = ar.put(pack_node.data(), pack_node.size() * 4), o_pl = ar.put(pack_lvl.data(), pack_lvl.size() * 4),
@@ -813,6 +817,7 @@ static orchard_status_t dev_state(orchard_model_t m, const orchard_state_t* s, D
   if (m->n_apple > 0 && (!s->apple || !s->apple_evt)) return fail(ORCHARD_ERR_INVALID_ARG, "apple state pointer missing");
   ds->q = (float2*)s->q; ds->qd = (float2*)s->qd; ds->apple = s->apple; ds->seg_evt = s->seg_evt;
   ds->apple_evt = s->apple_evt; ds->evt_step = s->evt_step; ds->status = s->env_status; ds->step = s->step;
+  ds->evt_ratio = s->evt_ratio;
   return ORCHARD_OK;
 }
 
@@ -1026,20 +1031,24 @@ orchard_status_t orchard_events(orchard_model_t m, const orchard_state_t* s, orc
   const int64_t NS = m->n_seg, NA = m->n_apple;
   std::vector<int32_t> steps(NS + NA);
   std::vector<uint8_t> path(NA);
+  std::vector<float> ratio(NS + NA, 0.f);
   hipStream_t hs = (hipStream_t)stream;
   HIPCHK(hipMemcpyAsync(steps.data(), s->evt_step, (NS + NA) * 4, hipMemcpyDeviceToHost, hs));
   if (NA) HIPCHK(hipMemcpyAsync(path.data(), s->apple_evt + 3 * NA, NA, hipMemcpyDeviceToHost, hs));
+  if (s->evt_ratio) HIPCHK(hipMemcpyAsync(ratio.data(), s->evt_ratio, (NS + NA) * 4, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipStreamSynchronize(hs));
   std::vector<orchard_event_t> ev;
+  auto in_band = [&](float r) { return (int32_t)(std::fabs((double)r - 1.0) < m->event_band); };
   for (int64_t i = 0; i < NS; ++i)
     if (steps[i] >= 0) {
       const int g = m->seg_map[i], e = m->node_env_h[i];
-      ev.push_back({e, 1, g - m->env_seg_off[e], steps[i]});
+      ev.push_back({e, 1, g - m->env_seg_off[e], steps[i], ratio[i], in_band(ratio[i])});
     }
   for (int64_t a = 0; a < NA; ++a)
     if (steps[NS + a] >= 0) {
       const int g = m->apple_map[a], e = m->apple_env_h[a];
-      ev.push_back({e, path[a] == 2 ? 3 : 2, g - m->env_apple_off[e], steps[NS + a]});
+      const float r = ratio[NS + a];
+      ev.push_back({e, path[a] == 2 ? 3 : 2, g - m->env_apple_off[e], steps[NS + a], r, in_band(r)});
     }
   std::sort(ev.begin(), ev.end(), [](const orchard_event_t& a, const orchard_event_t& b) {
     if (a.env != b.env) return a.env < b.env;

@@ -202,6 +202,7 @@ struct DevState {
   int32_t* evt_step;  // [n_seg + n_apple]
   uint32_t* status;   // [n_env]
   int64_t* step;
+  float* evt_ratio;   // [n_seg + n_apple] threshold ratio on an event's step, or null
 };
 
 struct DevInputs {

@@ -118,6 +118,13 @@ __device__ __forceinline__ Flags flg_unpack(float f) {
   return Flags{(v & 1) != 0, (v & 2) != 0, (v & 4) != 0, v >> 3};
 }
 
+// Rupture ratio mu = Kp |theta| / M_max of Eq. break; the up pass forms it again, in the
+// same operations, for the event record of a joint that breaks.
+__device__ __forceinline__ float rupture_ratio(float kp, float2 q, float inv_mmax) {
+  const float th = sqrtf(fmaf(q.x, q.x, q.y * q.y));
+  return kp * th * inv_mmax;
+}
+
 // down 1 inputs that do not depend on other nodes
 struct In1 {
   NodeRec nr;
@@ -186,8 +193,7 @@ __device__ __forceinline__ void node_down1(const DevModel& M, const DevState& S,
   const bool brk0 = brk != 0;
   int cnt1 = 0;
   if (!brk0) {
-    const float th = sqrtf(fmaf(q.x, q.x, q.y * q.y));
-    const float mu = kp * th * nr.inv_mmax;
+    const float mu = rupture_ratio(kp, q, nr.inv_mmax);
     cnt1 = mu > 1.f ? (int)cnt0 + 1 : 0;
     cnt1 = cnt1 > 255 ? 255 : cnt1;
     if (cnt1 >= M.n_break) brk = 1;
@@ -348,6 +354,7 @@ __device__ __forceinline__ void apple_phase(const DevModel& M, const DevState& S
             at(S.apple_evt, ua) = 1;
             at(S.apple_evt, 3 * NA + ua) = (uint8_t)path;
             at(S.evt_step, (uint32_t)NS + ua) = (int32_t)n;
+            if (S.evt_ratio) at(S.evt_ratio, (uint32_t)NS + ua) = path == 1 ? pi : tau;
           }
         }
         if (path) det = 1;
@@ -623,7 +630,11 @@ __device__ __forceinline__ void node_up(const DevModel& M, const DevState& S, co
   // rupture events of this step (the test ran in down 1)
   if ((stat & ST_FROZEN) == 0u && !fl.brk0) {
     at(S.seg_evt, (uint32_t)(M.n_seg + i)) = (uint8_t)fl.cnt;
-    if (fl.brk) { at(S.seg_evt, (uint32_t)i) = 1; at(S.evt_step, (uint32_t)i) = (int32_t)n; }
+    if (fl.brk) {
+      at(S.seg_evt, (uint32_t)i) = 1;
+      at(S.evt_step, (uint32_t)i) = (int32_t)n;
+      if (S.evt_ratio) at(S.evt_ratio, (uint32_t)i) = rupture_ratio(in.kp, in.q, at(M.nrec, (uint32_t)i).inv_mmax);
+    }
   }
   // node-private outputs (fields F_WM .. F_DU + 1), stored by the caller
   const float out[N_OUTU] = {W0a.x, W0a.y, W0a.z, W0l.x, W0l.y, W0l.z, W1a.x, W1a.y, W1a.z, W1l.x, W1l.y, W1l.z,
@@ -1024,6 +1035,7 @@ __global__ void k_state_rest(DevModel M, DevState S, const float* apple_rest) {
       S.qd[i] = make_float2(0.f, 0.f);
       S.seg_evt[i] = 0; S.seg_evt[NS + i] = 0;
       S.evt_step[i] = -1;
+      if (S.evt_ratio) S.evt_ratio[i] = 0.f;
     } else {
       const int a = (int)(k - NS);
       for (int c = 0; c < 3; ++c) { S.apple[c * NA + a] = apple_rest[c * NA + a]; S.apple[(3 + c) * NA + a] = 0.f; }
@@ -1033,6 +1045,7 @@ __global__ void k_state_rest(DevModel M, DevState S, const float* apple_rest) {
       }
       for (int c = 0; c < 4; ++c) S.apple_evt[c * NA + a] = 0;
       S.evt_step[NS + a] = -1;
+      if (S.evt_ratio) S.evt_ratio[NS + a] = 0.f;
     }
     if (k < M.n_env) S.status[k] = 0u;
     if (k == 0) *S.step = 0;

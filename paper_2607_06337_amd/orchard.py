@@ -33,12 +33,13 @@ class Desc(C.Structure):
         ("rng_seed", C.c_uint64), ("wrench_fraction", C.c_double), ("wrench_sigma", C.c_double),
         ("stiffness_k0", C.c_double), ("stiffness_gamma", C.c_double), ("fruit_dof", C.c_int32), ("pad1", C.c_int32)] + [
         (k, C.c_double) for k in ("drag_lin", "drag_ang", "drag_snapped", "friction_base", "friction_growth",
-                                  "friction_ramp_time", "friction_speed", "fade_speed", "brake_rate")]
+                                  "friction_ramp_time", "friction_speed", "fade_speed", "brake_rate",
+                                  "event_band")]
 
 # descriptor fields a constants dict may leave out (their "off" values)
 _DESC_DEFAULTS = dict(stiffness_k0=0.0, stiffness_gamma=1.0, fruit_dof=6, drag_lin=0.0, drag_ang=0.0, drag_snapped=1.0,
                       friction_base=0.0, friction_growth=1.0, friction_ramp_time=0.0, friction_speed=0.0,
-                      fade_speed=0.0, brake_rate=0.0)
+                      fade_speed=0.0, brake_rate=0.0, event_band=0.0)
 
 
 # the library's defaults (orchard_model_create with a null tuning)
@@ -63,7 +64,8 @@ class Layout(C.Structure):
 
 
 class CState(C.Structure):
-    _fields_ = [(n, _P) for n in ("q", "qd", "apple", "seg_evt", "apple_evt", "evt_step", "env_status", "step")]
+    _fields_ = [(n, _P) for n in ("q", "qd", "apple", "seg_evt", "apple_evt", "evt_step", "env_status", "step",
+                                  "evt_ratio")]
 
 
 class CParams(C.Structure):
@@ -80,7 +82,8 @@ class SphereGate(C.Structure):
 
 
 class Event(C.Structure):
-    _fields_ = [("env", C.c_int32), ("kind", C.c_int32), ("id", C.c_int32), ("step", C.c_int32)]
+    _fields_ = [("env", C.c_int32), ("kind", C.c_int32), ("id", C.c_int32), ("step", C.c_int32),
+                ("ratio", C.c_float), ("in_band", C.c_int32)]
 
 
 # every exported entry point of include/orchard.h
@@ -196,6 +199,7 @@ class State:
     evt_step: "torch.Tensor"   # int32 [n_seg + n_apple]
     env_status: "torch.Tensor" # int32 [n_env] (bit pattern of the uint32 status words)
     step: "torch.Tensor"       # int64 [1]
+    evt_ratio: "torch.Tensor"  # float32 [n_seg + n_apple]: threshold ratio on the event's step
 
     def c(self) -> CState:
         cs = CState()
@@ -354,7 +358,8 @@ class Model:
                      apple_evt=torch.zeros(4, self.n_apple, dtype=torch.uint8, device=dev),
                      evt_step=torch.full((self.n_seg + self.n_apple,), -1, dtype=torch.int32, device=dev),
                      env_status=torch.zeros(self.n_env, dtype=torch.int32, device=dev),
-                     step=torch.zeros(1, dtype=torch.int64, device=dev))
+                     step=torch.zeros(1, dtype=torch.int64, device=dev),
+                     evt_ratio=torch.zeros(self.n_seg + self.n_apple, device=dev))
 
     def rest(self, state: State, stream=None) -> State:
         cs = state.c()
@@ -462,15 +467,19 @@ class Model:
         return state
 
     # ---- host queries -------------------------------------------------------------------
-    def events(self, state: State, capacity: int = 1 << 16, stream=None):
+    def events(self, state: State, capacity: int = 1 << 16, stream=None, ratios: bool = False):
+        """Events as (env, kind, id, step) in descriptor ids; with ratios=True also the
+        threshold ratio on the event's step and the in-band flag."""
         L = load_library()
         cs = state.c()
         buf = (Event * max(capacity, 1))()
         n = C.c_int32(0)
         code = L.orchard_events(self.h, C.byref(cs), buf, int(capacity), C.byref(n), _stream(stream))
         if code == ERR_CAPACITY:
-            return self.events(state, int(n.value), stream)
+            return self.events(state, int(n.value), stream, ratios)
         _check(code)
+        if ratios:
+            return [(e.env, e.kind, e.id, e.step, e.ratio, e.in_band) for e in buf[: n.value]]
         return [(e.env, e.kind, e.id, e.step) for e in buf[: n.value]]
 
     def status(self, state: State, stream=None) -> np.ndarray:

@@ -42,6 +42,32 @@ def oracle_events(batch, st, envs):
     return ev
 
 
+def event_ratio_errors(model, state, batch, ost, envs, band_eps=EPS):
+    """Threshold ratio of every event that the GPU and the oracle record for the same id,
+    kind and step: returns (number compared, largest |GPU - oracle|, events whose in-band
+    flag disagrees with |ratio - 1| < band_eps)."""
+    envs = set(envs)
+    n, worst, flag_bad = 0, 0.0, []
+    for (e, k, i, s, r, ib) in model.events(state, ratios=True):
+        if e not in envs:
+            continue
+        if bool(ib) != (abs(float(r) - 1.0) < band_eps):
+            flag_bad.append((e, k, i, s, r, ib))
+        if k == 1:
+            j = batch.seg_offset[e] + i
+            if ost.break_step[j] != s:
+                continue
+            ro = ost.break_ratio[j]
+        else:
+            a = batch.apple_offset[e] + i
+            if ost.det_step[a] != s or 1 + int(ost.det_path[a]) != k:
+                continue
+            ro = ost.det_ratio[a]
+        n += 1
+        worst = max(worst, abs(float(r) - float(ro)))
+    return n, worst, flag_bad
+
+
 def _rel(g, o, floor):
     if g.size == 0:
         return 0.0

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from orchard_inputs import assemble, chain_tree, gen_tree, make_batch, pull_forces, step_constants
-from tests.parity import APPLE_TOL, TOL, run_parity, stratified_envs
+from tests.parity import APPLE_TOL, EPS, TOL, event_ratio_errors, run_parity, stratified_envs
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -36,6 +36,17 @@ def _report(name, errs, bad, n_band, oev=None):
 def _no_events(gev, oev):
     """A workload below every threshold: the check is that neither side invents an event."""
     assert len(oev) == 0 and len(gev) == 0, (list(oev.items())[:5], list(gev.items())[:5])
+
+
+def _check_event_ratios(tag, m, st, b, ost, envs, n_gev):
+    # the threshold ratio each event records (mu, pi or tau on its step) against the
+    # oracle's, within the band width: an event outside the band is decided identically
+    # only while both sides' ratios stay that close
+    n, worst, flag_bad = event_ratio_errors(m, st, b, ost, envs)
+    print(f"[{tag}] event ratios: {n} compared, largest difference {worst:.2e}", flush=True)
+    assert n >= 0.9 * n_gev and n > 0
+    assert worst < EPS
+    assert not flag_bad, flag_bad[:5]
 
 
 def test_single_tree_1000_steps():
@@ -73,6 +84,7 @@ def test_pull_workload_all_envs():
     # the pulls detach fruit (by pull, and some by stem tension)
     assert sum(1 for k in oev if k[1] == 2) >= 100
     assert len(gev) >= 100
+    _check_event_ratios("pull1024", m, st, b, ost, range(b.n_env), len(gev))
 
 
 def test_uneven_workload_2000_steps_stratified():
@@ -138,6 +150,7 @@ def test_breaking_limbs_and_free_hinges():
     print(f"[weak-wood] breaks {len(breaks)}, with fruit below {with_fruit}, below an earlier break {nested}",
           flush=True)
     assert with_fruit >= 10
+    _check_event_ratios("weak-wood", m, st, b, ost, range(b.n_env), len(gev))
 
 
 def test_row_scale_batch_one_launch():

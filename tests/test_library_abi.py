@@ -51,6 +51,16 @@ def test_create_rejects_invalid_descriptions():
     _bad(apple_seg, 2)
     _bad(lambda b: None, 1, dt=0.0)
     _bad(lambda b: None, 1, wrench_fraction=1.5)
+    _bad(lambda b: None, 1, event_band=-1e-3)
+    _bad(lambda b: None, 1, event_band=float("nan"))
+
+
+def test_event_record_layout():
+    # orchard_event_t: env, kind, id, step, ratio, in_band (24 bytes, ratio at offset 16)
+    from paper_2607_06337_amd.orchard import CState, Event
+    assert C.sizeof(Event) == 24 and Event.ratio.offset == 16 and Event.in_band.offset == 20
+    # orchard_state_t ends with the nullable evt_ratio pointer
+    assert CState._fields_[-1][0] == "evt_ratio" and C.sizeof(CState) == 9 * C.sizeof(C.c_void_p)
 
 
 def test_create_rejects_invalid_mappings():

@@ -189,6 +189,32 @@ def test_detach_hands_over_the_absolute_position():
     assert np.max(np.abs(st.ax[0] - x_expect)) < 1e-9
 
 
+def test_tension_detach_records_the_stem_tension_ratio():
+    # a downward pull just below f_det plus the weight loads the stem above alpha f_det:
+    # the detach goes by tension, and its ratio is tau = k_s |s| / (alpha f_det) of the
+    # stretch s at the start of the detach step (s = position state - h v_hang)
+    t = with_apples(chain_tree(2, length=0.2, radius=0.02, root_quat=qrot((0, 1, 0), 0.6)), [1], 0.2, 15.0)
+    c = step_constants()
+    o = Oracle(assemble([t]), c)
+    h = c["dt"]
+    F = np.array([[0.0, 0.0, -0.99 * 15.0]])
+    st = o.rest_state()
+    o.rollout(st, 400, aforce=F)
+    assert st.det[0] == 1 and st.det_path[0] == 2
+    nd = int(st.det_step[0])
+    st2 = o.rest_state()
+    o.rollout(st2, nd, aforce=F)
+    q, qd = st2.q.reshape(-1).copy(), st2.qd.reshape(-1).copy()
+    eps = 1e-7
+    vh = (_hang_points(o, q + eps * qd, t)[0] - _hang_points(o, q - eps * qd, t)[0]) / (2 * eps)
+    s = st2.ax[0] - h * vh[0]
+    tau = K_S * np.linalg.norm(s) / (c["tension_factor"] * 15.0)
+    o.rollout(st2, 1, aforce=F)
+    assert st2.det[0] == 1 and st2.det_step[0] == nd
+    assert st2.det_ratio[0] == st.det_ratio[0]
+    assert 1.0 < tau and abs(st.det_ratio[0] - tau) < 1e-8 * tau
+
+
 # ------------------------------------------------------------------------------------------
 # coupled tree + fruit: first-order convergence to the continuous model
 # ------------------------------------------------------------------------------------------

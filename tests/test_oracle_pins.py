@@ -460,6 +460,19 @@ def test_break_threshold_ramp():
     assert st.broken[0] == 1
     # first exceeding step + (N_break - 1)
     assert abs(int(st.break_step[0]) - (n_cross + 4)) <= 1
+    # the event's ratio is mu = kp |theta| / M_max of the state at the start of the break
+    # step: roll to that step again, form mu from its state, take the break step
+    nb = int(st.break_step[0])
+    st2 = o.rest_state()
+    o.rollout(st2, nb, kp=d["kp"], kd=np.array([1e-5 * kp]), wrench=W[:nb])
+    assert st2.broken[0] == 0 and st2.break_ratio[0] == 0.0
+    mu = kp * math.hypot(st2.q[0, 0], st2.q[0, 1]) / mmax
+    o.rollout(st2, 1, kp=d["kp"], kd=np.array([1e-5 * kp]), wrench=W[nb:nb + 1])
+    assert st2.broken[0] == 1 and st2.break_step[0] == nb
+    assert abs(st2.break_ratio[0] - mu) <= 1e-14 * mu
+    assert st.break_ratio[0] == st2.break_ratio[0]
+    # a quasi-static ramp of 1/4000 of the load per step, five steps in a row above 1
+    assert 1.0 < mu < 1.0 + 6.0 / n * 1.5
 
 
 def test_detach_pull_timing_and_tension_path():
@@ -475,6 +488,8 @@ def test_detach_pull_timing_and_tension_path():
     o.rollout(st, 120, aforce=F)
     assert st.det[0] == 1 and st.det_step[0] == n0 + 5 - 1 and st.det_path[0] == 1
     assert st.det[1] == 0 and st.det_step[1] == -1
+    # pull ratio pi = |F| / f_det at the detach step; none for the apple that stays
+    assert abs(st.det_ratio[0] - 1.2) <= 1e-15 * 1.2 and st.det_ratio[1] == 0.0
     # tension path: downward pull just below f_det, weight pushes the stem above 1.1 f_det
     F2 = np.zeros((A, 3))
     F2[2, 2] = -0.99 * t.apple_detach[2]
@@ -482,6 +497,8 @@ def test_detach_pull_timing_and_tension_path():
     o.rollout(st2, 400, aforce=F2)
     assert st2.det[2] == 1 and st2.det_path[2] == 2
     assert st2.det[0] == 0 and st2.det[1] == 0
+    # the tension detach records tau = k_s |s| / (alpha f_det) (above 1), not the pull's 0.99
+    assert st2.det_ratio[2] > 1.0 and st2.det_ratio[0] == 0.0
 
 
 def test_free_hinge_swings_at_gravity_rate():
