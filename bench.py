@@ -209,6 +209,66 @@ def cpu_baseline(batch, consts, n_envs=512, n_steps=200, n_envs_1=64, n_steps_1=
                 nproc=os.cpu_count(), affinity=avail, cpu_model=_cpu_model())
 
 
+def cpu_adjoint_baseline(n_trees: int = 8, n_steps: int = 200):
+    """FP64 oracle adjoint on the first n_trees trees of the differentiable workload (300
+    segments, 40 apples, per-step apple forces): the loss rollout alone and the adjoint
+    (taped forward plus reverse sweep) of a random state loss, one tree per thread."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from orchard_inputs import grad_apple_forces, make_batch, step_constants
+    from oracle.oracle import Oracle, adjoint, env_state0, loss
+    b = make_batch("grad512", env_ids=range(n_trees))
+    F = grad_apple_forces(b, n_steps)
+    o = Oracle(b, step_constants())
+    d = o.derived()
+    st = o.rest_state()
+    rng = np.random.default_rng(0)
+    jobs = []
+    for e in range(n_trees):
+        s0, s1 = b.seg_offset[e], b.seg_offset[e + 1]
+        a0, a1 = b.apple_offset[e], b.apple_offset[e + 1]
+        jobs.append((e, env_state0(o, st, e), d["kp"][s0:s1], d["kd"][s0:s1], F[:, a0:a1],
+                     dict(q=rng.normal(size=(s1 - s0, 2)))))
+    no_tip, no_target = np.zeros(0, np.int32), np.zeros((0, 3))
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    threads = max(1, min(n_trees, avail))
+    with ThreadPoolExecutor(threads) as ex:
+        t0 = time.perf_counter()
+        list(ex.map(lambda j: loss(o, j[0], j[1], j[2], j[3], j[4], n_steps, no_tip, no_target, w_state=j[5]), jobs))
+        t1 = time.perf_counter()
+        list(ex.map(lambda j: adjoint(o, j[0], j[1], j[2], j[3], j[4], n_steps, no_tip, no_target, w_state=j[5]), jobs))
+        t2 = time.perf_counter()
+    return dict(value=round(n_trees * n_steps / (t2 - t1), 1), unit="env-steps/s", cores=threads, kind="oracle",
+                forward_env_steps_per_s=round(n_trees * n_steps / (t1 - t0), 1), ratio=round((t2 - t1) / (t1 - t0), 2),
+                sample=f"{n_trees} trees of the differentiable workload x {n_steps} steps, FP64 adjoint of a state "
+                       f"loss: forward {t1 - t0:.1f} s, adjoint {t2 - t1:.1f} s on {threads} threads, one tree each")
+
+
+def workload_stats(batch) -> dict:
+    """Shape of a batch: depth in levels (max, mean over trees), widest level of any tree,
+    tip (leaf) count and mean tip radius."""
+    sizes = np.diff(batch.seg_offset)
+    env = np.repeat(np.arange(batch.n_env), sizes)
+    par = np.asarray(batch.seg_parent, np.int64)
+    gpar = np.where(par >= 0, par + batch.seg_offset[:-1][env], -1)
+    depth = np.zeros(batch.n_seg, np.int64)
+    while True:  # parents precede children: a fixed point after max-depth sweeps
+        nd = np.where(gpar >= 0, depth[np.maximum(gpar, 0)] + 1, 0)
+        if np.array_equal(nd, depth):
+            break
+        depth = nd
+    tree_depth = np.zeros(batch.n_env, np.int64)
+    np.maximum.at(tree_depth, env, depth + 1)
+    _, width = np.unique(env * (int(depth.max()) + 1) + depth, return_counts=True)
+    tip = np.bincount(gpar[gpar >= 0], minlength=batch.n_seg) == 0
+    return dict(max_depth=int(tree_depth.max()), mean_depth=round(float(tree_depth.mean()), 2),
+                widest_level=int(width.max()), tips=int(tip.sum()),
+                r_tip_mm=round(float(np.mean(batch.seg_radius[tip])) * 1e3, 3))
+
+
 ADJOINT_CANDIDATES = [BENCH_TUNING, dict(BENCH_TUNING, threads=128, lds_width=128),
                       dict(BENCH_TUNING, threads=128, lds_width=64)]
 
@@ -252,7 +312,7 @@ def adjoint_ratio(reps: int = 3, candidates=None):
         del m
     best = min(tried, key=lambda r: r["forward_ms"] + r["backward_ms"])
     return dict(ratio=round(best["backward_ms"] / best["forward_ms"], 3), forward_ms=best["forward_ms"],
-                backward_ms=best["backward_ms"], tuning=best["tuning"], candidates=tried,
+                backward_ms=best["backward_ms"], tuning=best["tuning"], candidates=tried, shape=workload_stats(batch),
                 workload="grad512: 512 trees x 300 segments x 40 apples, 200 steps, checkpoints every 20")
 
 
@@ -292,7 +352,7 @@ def row_scale(fwd_steps: int = 200, warm: int = 10, lead: int = 900, tail: int =
     lb = algorithmic_bytes(large) * tail
     return dict(workload="row64x16k: 64 trees x 5000 segments x 400 apples + 16384 trees x 80 segments x 8 apples, "
                          "one launch, gravity and breakage",
-                forward=fwd,
+                shape=workload_stats(batch), forward=fwd,
                 adjoint_large=dict(steps=f"{lead}..{lead + tail}", forward_ms=round(fw, 2), backward_ms=round(bw, 2),
                                    ratio=round(bw / fw, 3), forward_alg_GBps=round(lb / (fw / 1e3) / 1e9, 1),
                                    backward_alg_GBps=round(lb / (bw / 1e3) / 1e9, 1)))
@@ -453,7 +513,17 @@ def main():
         tune_log = [dict(c, ms_per_step=round(ms, 4)) for c, ms in timings]
         print(f"# autotune {time.perf_counter() - t_tune:.1f} s: {tuning}", file=sys.stderr, flush=True)
     tuning = {k: tuning[k] for k in TUNING_KEYS}
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     model = Model(batch, consts, tuning)
+    st_mem = model.rest_state()
+    torch.cuda.synchronize()
+    # device memory of the model (static records, scratch) and of one batch state
+    memory = dict(model_bytes=int(model.scratch_bytes),
+                  state_bytes=int(sum(getattr(st_mem, f).numel() * getattr(st_mem, f).element_size()
+                                      for f in st_mem.__dataclass_fields__)),
+                  device_bytes_used=int(free0 - torch.cuda.mem_get_info()[0]))
+    del st_mem
     # the first timed rollout is the reported one; four more of the same length (continuing
     # from its state) give the median beside it
     ms, wall, n_bad, st_end, what, n_launch, runs = time_gpu(model, args.steps, args.warmup, GRAPH_STEPS, repeats=5)
@@ -521,16 +591,20 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, consts)
         print(f"# cpu baseline: {cpu['value']:.1f} env-steps/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
+        if not args.no_adjoint:
+            cpu["adjoint8"] = cpu_adjoint_baseline()
+            print(f"# cpu adjoint: {cpu['adjoint8']}", file=sys.stderr, flush=True)
     out = dict(metric="tree-env steps/sec (FP32, 8192 uneven trees) + adjoint/forward cost ratio",
                value=round(value, 1), unit="env-steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=round(ms_step, 5), higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f32", data="synthetic",
                config=dict(workload=f"{WORKLOAD}: 8192 seeded L-system trees, log-uniform 50-1500 segments, "
                                     f"10-120 apples, in-step random body forces 5% N(0,5N), dt 1 ms",
-                           n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple, tuning=tuning,
-                           rollout=what, autotune=tune_log),
+                           n_env=batch.n_env, segments=batch.n_seg, apples=batch.n_apple,
+                           shape=workload_stats(batch), tuning=tuning, rollout=what, autotune=tune_log),
                repeat_ms=[round(x, 3) for x in runs], median_ms_per_step=round(float(np.median(runs)) / args.steps, 5),
-               events=events, adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad, plain_per_step_kernel=plain,
+               events=events, adjoint_forward_ratio=adj["ratio"] if adj else None, adjoint=adj, nonfinite_envs=n_bad,
+               memory=memory, plain_per_step_kernel=plain,
                roofline=roof, cpu_baseline=cpu, row_scale=rows, sphere_fit=sph)
     print(json.dumps(out), flush=True)
 

@@ -215,7 +215,10 @@ typedef struct {
  * inertias, Kp (Eq. beam), M_max (Eq. break) and Kd on the host in FP64, groups
  * trees into packs, and copies everything to the current HIP device.
  * Errors: INVALID_ARG, INVALID_TOPOLOGY (parent >= child, sizes <= 0, quaternion
- * not unit within 1e-6, apple_seg out of range), OUT_OF_MEMORY, HIP. */
+ * not unit within 1e-6, apple_seg out of range), OUT_OF_MEMORY, HIP; on error
+ * nothing stays allocated and *out is NULL.  Test hook: with ORCHARD_FAIL_ALLOC=k in
+ * the environment, the k-th device allocation of the call (k = 1, 2, ...) fails as
+ * if the device were out of memory. */
 orchard_status_t orchard_model_create(const orchard_model_desc_t* desc, const orchard_tuning_t* tuning,
                                       orchard_model_t* out);
 void orchard_model_destroy(orchard_model_t model);

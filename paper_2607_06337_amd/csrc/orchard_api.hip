@@ -6,6 +6,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -106,6 +107,16 @@ struct orchard_model_s {
   hipStream_t s_aux = nullptr;                   // recompute stream (default priority)
   hipEvent_t ev_in = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
 };
+
+// Device allocations of orchard_model_create.  Failure injection for tests of the clean-up
+// paths: with ORCHARD_FAIL_ALLOC=k in the environment the k-th allocation of a create call
+// (k = 1, 2, ...) fails as if the device were out of memory.
+static hipError_t model_alloc(void** p, size_t bytes, int& count) {
+  ++count;
+  const char* e = std::getenv("ORCHARD_FAIL_ALLOC");
+  if (e && std::atoi(e) == count) { *p = nullptr; return hipErrorOutOfMemory; }
+  return hipMalloc(p, bytes);
+}
 
 namespace {
 
@@ -596,7 +607,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
                o_bao = ar.put(d->apple_offset, (B + 1) * 4), o_bas = ar.put(d->apple_seg, NA * 4),
                o_bh = ar.put(d->apple_hang, NA * 24), o_io = ar.put(int_of.data(), NS * 4),
                o_iao = ar.put(int_apple_of.data(), NA * 4), o_hr64 = ar.put(ahang_rest.data(), NA * 24);
-  hipError_t he = hipMalloc(&M->arena, ar.off + 256);
+  int n_alloc = 0;
+  hipError_t he = model_alloc(&M->arena, ar.off + 256, n_alloc);
   if (he != hipSuccess) { delete M; return fail(ORCHARD_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(he)); }
   xc_h.wmom = (const float*)((char*)M->arena + o_wm);
   std::vector<char> zeros(64, 0);
@@ -611,7 +623,7 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
   const size_t scr_bytes = (size_t)scr_nf * (size_t)((std::max<int64_t>(NS, 1) + 63) / 64) * 64 * 4;
   // per-step scratch, then the dense data of the nodes that carry apples
   const size_t an_bytes = (size_t)std::max<int32_t>(n_anode, 1) * (K_N + E_N) * 4;
-  he = hipMalloc(&M->scr, scr_bytes + an_bytes);
+  he = model_alloc((void**)&M->scr, scr_bytes + an_bytes, n_alloc);
   M->scr_bytes = scr_bytes;
   M->an_bytes = an_bytes;
   M->n_anode = n_anode;
@@ -719,8 +731,8 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t wb = 2 * r256(8 * (size_t)NS) + r256(4 * (size_t)M->apl * NA) + r256(2 * (size_t)NS) + r256(4 * (size_t)NA) +
                       r256(4 * (size_t)(NS + NA)) + r256(4 * (size_t)B) + r256(8);
-    if (hipMalloc(&M->recs, rb) != hipSuccess || hipMalloc(&M->work, 2 * wb) != hipSuccess ||
-        (pb > 0 && hipMalloc(&M->reps, pb) != hipSuccess)) {
+    if (model_alloc((void**)&M->recs, rb, n_alloc) != hipSuccess || model_alloc(&M->work, 2 * wb, n_alloc) != hipSuccess ||
+        (pb > 0 && model_alloc((void**)&M->reps, pb, n_alloc) != hipSuccess)) {
       orchard_model_destroy(M);
       return fail(ORCHARD_ERR_OUT_OF_MEMORY, "adjoint buffers");
     }
