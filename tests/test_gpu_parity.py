@@ -157,16 +157,19 @@ def test_row_scale_batch_one_launch():
     # the orchard-row batch in one launch: 64 trees of 5000 segments next to 16384 of 80
     # (the large trees, 310-420 nodes on their widest levels, in the wide-tree bucket beside
     # the small trees' LDS packs); the oracle follows
-    # 8 large and 64 small trees over 300 steps with breakage enabled
+    # 8 large and 64 small trees over the workload's 1000 steps with breakage enabled
     from bench import BENCH_TUNING
     b = make_batch("row64x16k")
     rng = np.random.default_rng(11)
     envs = list(range(0, 64, 8)) + sorted(int(e) for e in rng.choice(np.arange(64, b.n_env), 64, replace=False))
-    errs, bad, n_band, m, st, ost, gev, oev = run_parity(b, step_constants(), 300, 50, envs=envs,
+    errs, bad, n_band, m, st, ost, gev, oev = run_parity(b, step_constants(), 1000, 100, envs=envs,
                                                          tuning=BENCH_TUNING, threads=8)
     wq, wqd = _report("row-scale", errs, bad, n_band, oev)
     assert wq < TOL and wqd < TOL
-    _no_events(gev, oev)
+    # gravity alone breaks a few joints of the large trees late in the run (two, near steps
+    # 770 and 800): identical events outside the band
+    assert not bad, bad[:5]
+    assert len(oev) >= 1 and sum(1 for k in gev if k[1] == 1) >= 1
 
 
 def test_renumbered_descriptor_is_bitwise_identical():
