@@ -214,6 +214,9 @@ typedef struct {
 /* Build a model: validates the description (synchronously), derives masses,
  * inertias, Kp (Eq. beam), M_max (Eq. break) and Kd on the host in FP64, groups
  * trees into packs, and copies everything to the current HIP device.
+ * Limits: at most 2^27 segments and 2^26 apples per model (the kernels address
+ * per-segment and per-apple records with 32-bit byte offsets); larger batches are
+ * INVALID_ARG.
  * Errors: INVALID_ARG, INVALID_TOPOLOGY (parent >= child, sizes <= 0, quaternion
  * not unit within 1e-6, apple_seg out of range), OUT_OF_MEMORY, HIP; on error
  * nothing stays allocated and *out is NULL.  Test hook: with ORCHARD_FAIL_ALLOC=k in

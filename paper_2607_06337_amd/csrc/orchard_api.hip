@@ -108,6 +108,10 @@ struct orchard_model_s {
   hipEvent_t ev_in = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
 };
 
+constexpr int64_t kMaxSegments = int64_t(1) << 27, kMaxApples = int64_t(1) << 26;
+static_assert(sizeof(NodeRec) * kMaxSegments <= (int64_t(1) << 32) && sizeof(AppleRec) * kMaxApples <= (int64_t(1) << 32),
+              "32-bit byte offsets into the per-segment and per-apple records");
+
 // Device allocations of orchard_model_create.  Failure injection for tests of the clean-up
 // paths: with ORCHARD_FAIL_ALLOC=k in the environment the k-th allocation of a create call
 // (k = 1, 2, ...) fails as if the device were out of memory.
@@ -226,7 +230,10 @@ orchard_status_t orchard_model_create(const orchard_model_desc_t* d, const orcha
     if (d->seg_offset[e + 1] <= d->seg_offset[e] || d->apple_offset[e + 1] < d->apple_offset[e])
       return fail(ORCHARD_ERR_INVALID_TOPOLOGY, "env " + std::to_string(e) + ": empty tree or decreasing offsets");
   const int64_t NS = d->seg_offset[B], NA = d->apple_offset[B];
-  if (NS > (1LL << 30) || NA > (1LL << 30)) return fail(ORCHARD_ERR_INVALID_ARG, "batch too large");
+  // the kernels form byte offsets into per-node and per-apple arrays in 32 bits: the largest
+  // record is 32 bytes per segment and 64 bytes per apple
+  if (NS > kMaxSegments || NA > kMaxApples)
+    return fail(ORCHARD_ERR_INVALID_ARG, "batch too large (at most 2^27 segments and 2^26 apples)");
   if (NA > 0 && (!d->apple_seg || !d->apple_hang || !d->apple_mass || !d->apple_radius || !d->apple_detach))
     return fail(ORCHARD_ERR_INVALID_ARG, "missing apple array");
 

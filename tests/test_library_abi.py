@@ -55,6 +55,33 @@ def test_create_rejects_invalid_descriptions():
     _bad(lambda b: None, 1, event_band=float("nan"))
 
 
+def test_create_rejects_batches_beyond_32_bit_record_offsets():
+    # 2^27 + 1 segments or 2^26 + 1 apples: rejected from the offsets alone, before any
+    # per-segment array is read (the small arrays passed here are never touched)
+    from paper_2607_06337_amd.orchard import Desc, OrchardError, _check, load_library
+    L = load_library()
+    small_i = np.zeros(16, np.int32)
+    small_d = np.zeros(64, np.float64)
+    for ns, na in ((2 ** 27 + 1, 0), (10, 2 ** 26 + 1)):
+        d = Desc()
+        d.n_env = 1
+        so = np.array([0, ns], np.int32)
+        ao = np.array([0, na], np.int32)
+        d.seg_offset, d.apple_offset = so.ctypes.data, ao.ctypes.data
+        for name in ("seg_parent", "apple_seg"):
+            setattr(d, name, small_i.ctypes.data)
+        for name in ("seg_rest_quat", "seg_length", "seg_radius", "seg_density", "seg_youngs", "seg_mor",
+                     "apple_hang", "apple_mass", "apple_radius", "apple_detach"):
+            setattr(d, name, small_d.ctypes.data)
+        d.dt, d.tether_k, d.tension_factor, d.v_cap, d.react_max_factor = 1e-3, 2e3, 1.1, 5.0, 2.0
+        d.n_break = d.n_pull = d.n_tension = 5
+        d.stiffness_gamma, d.fruit_dof, d.drag_snapped, d.friction_growth = 1.0, 6, 1.0, 1.0
+        h = C.c_void_p()
+        with pytest.raises(OrchardError) as e:
+            _check(L.orchard_model_create(C.byref(d), None, C.byref(h)))
+        assert e.value.code == 1 and "too large" in str(e.value) and not h.value
+
+
 def test_event_record_layout():
     # orchard_event_t: env, kind, id, step, ratio, in_band (24 bytes, ratio at offset 16)
     from paper_2607_06337_amd.orchard import CState, Event
