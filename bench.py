@@ -273,7 +273,7 @@ ADJOINT_CANDIDATES = [BENCH_TUNING, dict(BENCH_TUNING, threads=128, lds_width=12
                       dict(BENCH_TUNING, threads=128, lds_width=64)]
 
 
-def adjoint_ratio(reps: int = 3, candidates=None):
+def adjoint_ratio(reps: int = 5, candidates=None):
     """Adjoint/forward cost ratio on the differentiable-rollout workload: 512 trees of 300
     segments and 40 apples, 200 steps with checkpoints every 20, per-step apple forces;
     backward = recompute of every checkpoint segment + adjoint kernels.  The mapping is the
@@ -316,10 +316,11 @@ def adjoint_ratio(reps: int = 3, candidates=None):
                 workload="grad512: 512 trees x 300 segments x 40 apples, 200 steps, checkpoints every 20")
 
 
-def row_scale(fwd_steps: int = 200, warm: int = 10, lead: int = 900, tail: int = 100, K: int = 20):
+def row_scale(fwd_steps: int = 200, warm: int = 10, lead: int = 900, tail: int = 100, K: int = 20, reps: int = 5):
     """Orchard-row batch (64 trees of 5000 segments + 16384 of 80) in one launch: forward
     throughput, then the 64 large trees alone: forward to step lead + tail with checkpoints
-    over the final tail steps, and the adjoint over those steps (recompute included).
+    over the final tail steps, and the adjoint over those steps (recompute included), both
+    from the same state after lead steps, one untimed and `reps` timed repetitions, medians.
     Algorithmic-byte rates use the same per-segment / per-apple bytes as the main figure."""
     import torch
     from orchard_inputs import make_batch, step_constants
@@ -336,19 +337,26 @@ def row_scale(fwd_steps: int = 200, warm: int = 10, lead: int = 900, tail: int =
     st = ml.rest_state()
     kp, kd = ml.default_params()
     ml.step(st, kp, kd, lead)
+    st_lead = st.clone()
     ck = torch.empty(-(-tail // K) * ml.ckpt_words, device="cuda")
     adj = dict(q=torch.randn(ml.n_seg, 2, device="cuda"), qd=torch.zeros(ml.n_seg, 2, device="cuda"),
                ax=torch.zeros(3, ml.n_apple, device="cuda"), av=torch.zeros(3, ml.n_apple, device="cuda"))
-    gkp, gkd = torch.zeros_like(kp), torch.zeros_like(kd)
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    torch.cuda.synchronize()
-    e0.record()
-    ml.step(st, kp, kd, tail, ckpt=ck, ckpt_every=K)
-    e1.record()
-    ml.step_backward(ck, K, tail, kp, kd, adj, gkp, gkd)
-    e2.record()
-    torch.cuda.synchronize()
-    fw, bw = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    fws, bws = [], []
+    for _ in range(reps + 1):   # from the same state each time; the first is untimed
+        for f in st.__dataclass_fields__:
+            getattr(st, f).copy_(getattr(st_lead, f))
+        gkp, gkd = torch.zeros_like(kp), torch.zeros_like(kd)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record()
+        ml.step(st, kp, kd, tail, ckpt=ck, ckpt_every=K)
+        e1.record()
+        ml.step_backward(ck, K, tail, kp, kd, adj, gkp, gkd)
+        e2.record()
+        torch.cuda.synchronize()
+        fws.append(e0.elapsed_time(e1))
+        bws.append(e1.elapsed_time(e2))
+    fw, bw = float(np.median(fws[1:])), float(np.median(bws[1:]))
     lb = algorithmic_bytes(large) * tail
     return dict(workload="row64x16k: 64 trees x 5000 segments x 400 apples + 16384 trees x 80 segments x 8 apples, "
                          "one launch, gravity and breakage",
