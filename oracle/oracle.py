@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB names another build of the same sources (the sanitizer test's)
+LIB = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SRC = [os.path.join(HERE, f) for f in ("oracle.cpp", "oracle_math.hpp", "tape.hpp", "dual.hpp", "adjoint.cpp")]
 
 
