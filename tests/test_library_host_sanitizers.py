@@ -46,8 +46,9 @@ bad = assemble([gen_tree(1, 20, 3)])
 bad.seg_parent[5] = 7
 try:
     Model(bad, step_constants())
+    raise SystemExit("an invalid topology was accepted")
 except OrchardError as e:
-    assert e.code == 2
+    assert e.code == 2, e
 print("host paths:", n)
 '''
 
