@@ -22,7 +22,7 @@ def _run(batch, consts, tuning, n_steps, static):
     m.step(st, kp, kd, n_steps, aforce=F, static_scratch=static)
     torch.cuda.synchronize()
     return [getattr(st, f).cpu().clone() for f in ("q", "qd", "apple", "seg_evt", "apple_evt", "evt_step",
-                                                       "env_status", "step")], sorted(m.events(st))
+                                                       "env_status", "step", "evt_ratio")], sorted(m.events(st, ratios=True))
 
 
 @pytest.mark.parametrize("tuning", [dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=25),
