@@ -111,3 +111,36 @@ def test_tips_need_a_model_with_adjoint_support():
         m.tips_backward(st.q, node, torch.ones(4, 3, device="cuda"), gq)
     assert ei.value.code == 1
     assert torch.count_nonzero(gq) == 0
+
+
+def test_state_without_a_ratio_buffer_steps_identically():
+    # evt_ratio is nullable: the same steps with and without it give the same state and
+    # events, the events then carrying ratio 0 (and no in-band flag)
+    import ctypes as C
+
+    from orchard_inputs import pull_forces
+    from paper_2607_06337_amd import Model
+    from paper_2607_06337_amd.orchard import Event, load_library
+    b = make_batch("pull1024", env_ids=range(16))
+    m = Model(b, step_constants())
+    kp, kd = m.default_params()
+    F = torch.tensor(m.apple_from_desc(pull_forces(b, fraction=0.5).astype(np.float32), axis=0), device="cuda")
+    ref = m.rest_state()
+    m.step(ref, kp, kd, 300, aforce=F)
+    st = m.rest_state()
+    st.evt_ratio = None          # the binding passes a null pointer for it
+    m.step(st, kp, kd, 300, aforce=F)
+    torch.cuda.synchronize()
+    for f in ("q", "qd", "apple", "seg_evt", "apple_evt", "evt_step", "env_status", "step"):
+        assert torch.equal(getattr(st, f), getattr(ref, f)), f
+    with_r = m.events(ref, ratios=True)
+    without = m.events(st, ratios=True)
+    assert len(with_r) > 0 and [e[:4] for e in with_r] == [e[:4] for e in without]
+    assert all(e[4] > 1.0 for e in with_r) and all(e[4] == 0.0 and e[5] == 0 for e in without)
+    # the raw record through the C ABI
+    cs = st.c()
+    assert cs.evt_ratio is None
+    buf = (Event * len(without))()
+    n = C.c_int32(0)
+    assert load_library().orchard_events(m.h, C.byref(cs), buf, len(without), C.byref(n), None) == 0
+    assert n.value == len(without) and all(e.ratio == 0.0 for e in buf)
