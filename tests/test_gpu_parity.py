@@ -252,7 +252,9 @@ def test_renumbered_descriptor_is_bitwise_identical():
     dict(threads=256, pack_fill=1.0, lds_width=240, steps_per_launch=50, wave_width=64),
     dict(threads=128, pack_fill=1.0, lds_width=64, wave_width=32, big_threads=256, steps_per_launch=7),
     dict(threads=64, pack_fill=1.0, lds_width=48, wave_width=24, big_threads=512),
-    dict(threads=256, pack_fill=1.0, lds_width=96, big_threads=512, pack_skew=1)])
+    dict(threads=256, pack_fill=1.0, lds_width=96, big_threads=512, pack_skew=1),
+    # 512-wide LDS packs for every tree
+    dict(threads=512, pack_fill=1.0, lds_width=480, steps_per_launch=50)])
 def test_mappings_are_bitwise_identical(tuning):
     # the mapping (workgroup per tree, exchange through LDS or global scratch) changes
     # which workgroup walks a tree and where levels hand data over, never the
@@ -275,6 +277,27 @@ def test_mappings_are_bitwise_identical(tuning):
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
     assert np.array_equal(out[0][2], out[1][2])
+    assert out[0][3] == out[1][3]
+
+
+def test_row_batch_mappings_are_bitwise_identical():
+    # the orchard-row batch's two benchmark mappings (large trees in the wide-tree bucket
+    # beside 240-wide packs, or every tree in 512-wide packs) on 8 large and 64 small trees
+    from bench import ROW_CANDIDATES
+    from paper_2607_06337_amd import Model
+    b = make_batch("row64x16k", env_ids=list(range(0, 64, 8)) + list(range(64, 128)))
+    c = step_constants()
+    out = []
+    for t in ROW_CANDIDATES:
+        m = Model(b, c, t)
+        assert (m.n_big_packs > 0) == (t["lds_width"] < 460)
+        st = m.rest_state()
+        kp, kd = m.default_params()
+        m.step(st, kp, kd, 120)
+        out.append((m.seg_to_desc(st.q.cpu().numpy()), m.seg_to_desc(st.qd.cpu().numpy()),
+                    m.apple_to_desc(st.apple.cpu().numpy(), axis=1), sorted(m.events(st, ratios=True))))
+    for a, b_ in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, b_)
     assert out[0][3] == out[1][3]
 
 
