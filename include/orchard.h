@@ -115,7 +115,7 @@ typedef struct {
                                 /*   0 = none marked                                  */
 } orchard_model_desc_t;
 
-/* Kernel mapping choices (nullable in create: defaults {128, 1.0, 1, 0, 0, 128, 0}).
+/* Kernel mapping choices (nullable in create: defaults {128, 1.0, 1, 0, 0, 128, 0, 0, 0}).
  * threads: workgroup size for the pack kernel (64, 128, 256 or 512).  pack_fill: a
  * pack collects trees of similar depth until it holds about pack_fill * threads *
  * depth nodes (0 = one tree per pack).  lds_width (0 .. threads): capacity, in nodes
