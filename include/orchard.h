@@ -262,11 +262,12 @@ orchard_status_t orchard_model_rebuild(orchard_model_t model, const double* seg_
 
 /* Rest state: q = qd = 0 (the generated skeleton pose), apples hanging
  * m |g| / k_s below their hang point at rest, counters and flags zero, event steps
- * -1, status 0, step counter 0. */
+ * -1, event ratios 0 (if the state has them), status 0, step counter 0. */
 orchard_status_t orchard_state_rest(orchard_model_t model, const orchard_state_t* state, orchard_stream_t stream);
 
 /* Advance every env by n_steps (stream-ordered, asynchronous, no allocation).
- * Per step: event tests on the current state (rupture, detachment), snapped mask,
+ * Per step: event tests on the current state (rupture, detachment; an event stamps
+ * its step and, if the state has the array, its threshold ratio), snapped mask,
  * applied forces (inputs plus, if wrench_fraction > 0, the counter-based random
  * forces), apple reactions, bias forces, factorisation of the implicit mass
  * matrix, solve, integration.  If ckpt is non-NULL, the full state is written to
