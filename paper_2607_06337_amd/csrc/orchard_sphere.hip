@@ -1,8 +1,9 @@
 // Batched sphere-fit detector (Sec. "Geometric fruit perception", Eq. spherefit): each
 // patch of back-projected depth points is fitted with the sphere that solves
 // 2 p.c + b = |p|^2 (b = R^2 - |c|^2) in the least-squares sense, then gated on radius and
-// RMS geometric residual.  One wavefront per patch; the work is a few streaming passes
-// over 12 bytes per point, so the kernel is bound by memory, not by arithmetic.
+// RMS geometric residual.  One wavefront per patch, two streaming passes over 12 bytes per
+// point; on the benchmark's patches the vector ALUs are the busier resource (the FP64
+// passes plus each patch's cross-lane sums and solve), HBM runs well below its rate.
 //
 // Numerics: the FP32 points are shifted by the patch's first point in FP64 (exact), and
 // one pass gathers the shifted sums n, sum q, sum q q^T, sum |q|^2 q and sum |q|^2 in FP64;
