@@ -72,18 +72,22 @@ def code_without_comments(text: str) -> str:
     return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
 
 
-def kernel_source_hash() -> str:
+STEP_SOURCES = ("paper_2607_06337_amd/csrc/orchard_step.hip", "paper_2607_06337_amd/csrc/orchard_dev.h")
+SPHERE_SOURCES = ("paper_2607_06337_amd/csrc/orchard_sphere.hip",)
+
+
+def kernel_source_hash(files=STEP_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in ("paper_2607_06337_amd/csrc/orchard_step.hip", "paper_2607_06337_amd/csrc/orchard_dev.h"):
+    for f in files:
         h.update(code_without_comments(open(os.path.join(ROOT, f)).read()).encode())
     return h.hexdigest()[:16]
 
 
-def profiled_counters(kernel: str, tuning: dict):
+def profiled_counters(kernel: str, tuning, files=STEP_SOURCES):
     """Counter figures of the committed rocprofv3 summaries of this kernel (HBM bytes per
-    launch, VALU instructions and FP32 operations per step), merged over the summaries
-    taken on the current kernel source and mapping; None if there is none."""
-    cur = kernel_source_hash()
+    launch, VALU instructions and FP32 operations), merged over the summaries taken on the
+    current source of `files` and mapping `tuning`; None if there is none."""
+    cur = kernel_source_hash(files)
     out = {}
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(f):
@@ -409,12 +413,21 @@ def sphere_fit_leg(n_patch: int = 65536, reps: int = 20, cpu_patches: int = 2000
     t0 = time.perf_counter()
     fit_patches(pts, off, GATE, patches=pick)
     cpu_s = time.perf_counter() - t0
+    roof = dict(bound="hbm", achieved=round(alg / (us * 1e-6) / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), bytes_per_launch=alg)
+    prof = profiled_counters("k_sphere_fit", None, SPHERE_SOURCES)
+    if prof and prof.get("hbm_bytes_per_launch"):
+        roof["traffic"] = int(prof["hbm_bytes_per_launch"])
+    if prof and prof.get("valu_insts_per_launch"):
+        # VALU issue against 1024 SIMDs x one wave64 instruction per 4 cycles at 2.4 GHz:
+        # the busier resource of this kernel
+        vi = prof["valu_insts_per_launch"]
+        roof["valu"] = dict(insts_per_launch=vi, frac=round(vi / (us * 1e-6) / VALU_ISSUE_PEAK, 4),
+                            peak_insts_per_s=VALU_ISSUE_PEAK)
     return dict(workload=f"{n_patch} synthetic depth patches ({n_pts} points; fruit caps, branch sections, leaves)",
                 us_per_launch=round(us, 2), patches_per_s=round(n_patch / (us * 1e-6), 1),
                 points_per_s=round(n_pts / (us * 1e-6), 1), accepted=int(acc.sum()),
-                fruit_recall=round(float(acc[kind == 0].mean()), 4),
-                roofline=dict(bound="hbm", achieved=round(alg / (us * 1e-6) / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                              frac=round(alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), bytes_per_launch=alg),
+                fruit_recall=round(float(acc[kind == 0].mean()), 4), roofline=roof,
                 cpu_baseline=dict(value=round(len(pick) / cpu_s, 1), unit="patches/s", cores=1, kind="oracle",
                                   sample=f"{len(pick)} patches of the workload, FP64 least squares, {cpu_s:.1f} s"))
 

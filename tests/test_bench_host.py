@@ -33,3 +33,11 @@ def test_workload_shape_statistics_on_known_trees():
     s = bench.workload_stats(assemble([a, b]))
     assert (s["max_depth"], s["mean_depth"], s["widest_level"], s["tips"]) == (5, 4.0, 3, 5)
     assert abs(s["r_tip_mm"] - (20.0 + 4 * 10.0) / 5) < 1e-9
+
+
+def test_sphere_fit_profile_record_keys_on_its_source():
+    # the sphere-fit summary's counters apply only while its kernel source (comments aside)
+    # is the profiled one
+    rec = bench.profiled_counters("k_sphere_fit", None, bench.SPHERE_SOURCES)
+    assert rec is None or (rec["valu_insts_per_launch"] > 0 and rec["hbm_bytes_per_launch"] > 0)
+    assert bench.profiled_counters("k_sphere_fit", None, bench.STEP_SOURCES) is None
